@@ -1,0 +1,143 @@
+"""CPU oracle for the iterated clamped star stencils -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py``
+may import this package.  The HIP library never imports, links or calls it, and it shares
+no code with the library.
+
+The arithmetic lives in ``stencil_oracle.c`` (plain loops, FP64 and FP32 instantiations,
+see that file's header for the paper passages it follows: Section 2.1 ping-pong
+stepping, Table 2 formulas, Section 5.1 clamp-to-edge boundary).  This module only builds
+that file with gcc and marshals numpy arrays into it.
+
+Parity status: every function here is pinned by ``tests/test_oracle_pins.py`` (dense
+brute-force matrix powers, DCT-II eigenmodes, exact Green's function, conservation,
+constant fields, closed-form hotspot recurrence, dimension reduction, dense transpose,
+dot-product and exact central-difference checks of the adjoint).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "stencil_oracle.c")
+_LIB = os.path.join(_HERE, "libstencil_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+DIFFUSION = 0
+HOTSPOT = 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (OpenMP, no FP contraction).  Returns the .so path."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-shared",
+           "-fPIC", _SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = ctypes.CDLL(_LIB)
+            for suf, ct in (("f64", ctypes.c_double), ("f32", ctypes.c_float)):
+                p = ctypes.POINTER(ct)
+                fwd = getattr(lib, "oracle_forward_" + suf)
+                fwd.restype = ctypes.c_int
+                fwd.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_float), p, p, ctypes.c_int]
+                adj = getattr(lib, "oracle_adjoint_" + suf)
+                adj.restype = ctypes.c_int
+                adj.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_float), p, ctypes.c_int, p, p]
+            lib.oracle_num_threads.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def _dims(shape):
+    if len(shape) == 2:
+        return 2, shape[1], shape[0], 1
+    if len(shape) == 3:
+        return 3, shape[2], shape[1], shape[0]
+    raise ValueError("grid must be 2D (ny, nx) or 3D (nz, ny, nx)")
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _prep(a, dtype):
+    return np.ascontiguousarray(np.asarray(a), dtype=dtype).copy()
+
+
+def forward(x0, coeffs, T, power=None, form=None, dtype=np.float64):
+    """T clamped Jacobi steps of the diffusion (power None) or hotspot stencil.
+
+    ``x0`` has shape (ny, nx) or (nz, ny, nx); ``coeffs`` is the 10-vector
+    [cc, cw, ce, cn, cs, cb, ca, cp, c_amb, t_amb] (FP32 values; the FP64 run promotes
+    them exactly).  Returns a new array of ``dtype`` (float64 or float32).
+    """
+    lib = _load()
+    dtype = np.dtype(dtype)
+    ct = ctypes.c_double if dtype == np.float64 else ctypes.c_float
+    fn = lib.oracle_forward_f64 if dtype == np.float64 else lib.oracle_forward_f32
+    if form is None:
+        form = HOTSPOT if power is not None else DIFFUSION
+    g = _prep(x0, dtype)
+    ndim, nx, ny, nz = _dims(g.shape)
+    cf = np.ascontiguousarray(coeffs, dtype=np.float32)
+    p = None
+    if form == HOTSPOT:
+        if power is None:
+            raise ValueError("hotspot needs a power map")
+        p = _prep(power, dtype)
+        if p.shape != g.shape:
+            raise ValueError("power must match the grid shape")
+    rc = fn(form, ndim, nx, ny, nz, _ptr(cf, ctypes.c_float), _ptr(g, ct),
+            _ptr(p, ct) if p is not None else None, int(T))
+    if rc != 0:
+        raise ValueError("oracle_forward rejected its arguments")
+    return g
+
+
+def adjoint(cot, coeffs, T, form=DIFFUSION, dtype=np.float64, want_grad_p=None):
+    """Vector-Jacobian product of ``forward`` w.r.t. the initial field and the power map.
+
+    ``cot`` = dJ/dx_T.  Returns (grad_x0, grad_p); grad_p is None for diffusion.
+    """
+    lib = _load()
+    dtype = np.dtype(dtype)
+    ct = ctypes.c_double if dtype == np.float64 else ctypes.c_float
+    fn = lib.oracle_adjoint_f64 if dtype == np.float64 else lib.oracle_adjoint_f32
+    c = _prep(cot, dtype)
+    ndim, nx, ny, nz = _dims(c.shape)
+    cf = np.ascontiguousarray(coeffs, dtype=np.float32)
+    gx = np.empty_like(c)
+    if want_grad_p is None:
+        want_grad_p = form == HOTSPOT
+    gp = np.empty_like(c) if want_grad_p else None
+    rc = fn(form, ndim, nx, ny, nz, _ptr(cf, ctypes.c_float), _ptr(c, ct), int(T), _ptr(gx, ct),
+            _ptr(gp, ct) if gp is not None else None)
+    if rc != 0:
+        raise ValueError("oracle_adjoint rejected its arguments")
+    return gx, gp
+
+
+def loss(xT, target) -> float:
+    """L2 misfit J = 1/2 * sum (x_T - y)^2, accumulated in FP64."""
+    d = np.asarray(xT, dtype=np.float64) - np.asarray(target, dtype=np.float64)
+    return 0.5 * float(np.dot(d.ravel(), d.ravel()))

@@ -1,0 +1,162 @@
+/*
+ * stencil_oracle.c -- plain CPU oracle for iterated first-order star stencils.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library's product path may include, link or
+ * call this file; only the test suite, the smoke check and the bench's CPU-baseline leg use
+ * it.  It shares no code with the HIP library.
+ *
+ * What it computes (Zohouri, Podobas, Matsuoka, "Combined Spatial and Temporal Blocking for
+ * High-Performance Stencil Computation on FPGAs Using OpenCL"):
+ *
+ *   * Section 2.1: each time step reads every cell from one buffer and writes the updated
+ *     cell to a second buffer; the buffers are swapped before the next step (Jacobi
+ *     ping-pong, out-of-place).
+ *   * Table 2: Diffusion 2D/3D are weighted sums of the centre and the 4 (2D) or 6 (3D)
+ *     face neighbours; Hotspot adds a per-cell power term scaled by sdc and an ambient
+ *     temperature term.  Hotspot is evaluated in its weighted-sum form (centre and
+ *     neighbour weights, plus cp*power + c_amb*t_amb); the physical Table-2 form of
+ *     Hotspot 2D maps onto it with cc = 1 - sdc*(2Rx+2Ry+Rz), cw = ce = sdc*Rx,
+ *     cn = cs = sdc*Ry, cp = sdc, c_amb = sdc*Rz.
+ *   * Section 5.1: an out-of-range neighbour of a boundary cell takes the value of the
+ *     boundary cell itself (clamp-to-edge), in every direction and at every step.
+ *
+ * Evaluation order (the paper does not fix one; this is the reading used throughout):
+ *   acc = cc*c; acc = fma(cw,w,acc); acc = fma(ce,e,acc); acc = fma(cs,s,acc);
+ *   acc = fma(cn,n,acc); [3D: acc = fma(cb,b,acc); acc = fma(ca,a,acc)];
+ *   hotspot: acc = acc + q, with the time-invariant source q = fma(cp, p, k_amb) and
+ *            k_amb = c_amb*t_amb rounded once in the working precision.
+ * Two instantiations are built from the same text: FP64 (coefficients promoted from their
+ * FP32 values) and FP32.  Compile with -ffp-contract=off so no other fusion happens.
+ *
+ * The adjoint is the literal transpose of the forward gather: every cell i scatters
+ * c_d * lambda[i] onto the cell its direction-d neighbour clamps to.  With
+ * x_{t+1} = A x_t + cp*p + k_amb, lambda_T = dJ/dx_T:
+ *   grad_x0 = (A^T)^T lambda_T,  grad_p = cp * sum_{t=1..T} lambda_t.
+ *
+ * Parallelism: the forward sweep parallelises over rows with OpenMP; every output cell has
+ * exactly one writer, so results do not depend on the thread count.  The adjoint scatter
+ * runs serially.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { ORACLE_DIFFUSION = 0, ORACLE_HOTSPOT = 1 };
+enum { C_CC = 0, C_CW, C_CE, C_CN, C_CS, C_CB, C_CA, C_CP, C_AMB, C_TAMB };
+
+static inline long clampl(long v, long lo, long hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* One instantiation per precision.  REAL is the working type, FMA its fused multiply-add. */
+#define ORACLE_DEFINE(REAL, SUF, FMA)                                                            \
+  /* Forward: T clamped Jacobi steps applied to grid (in/out).  power may be NULL for         \
+   * diffusion.  Returns 0, or -1 on bad arguments / allocation failure. */                   \
+  int oracle_forward_##SUF(int form, int ndim, int nx, int ny, int nz, const float* cf,       \
+                           REAL* grid, const REAL* power, int T) {                            \
+    if (nx < 1 || ny < 1 || nz < 1 || T < 0 || (ndim != 2 && ndim != 3)) return -1;           \
+    if (ndim == 2) nz = 1;                                                                    \
+    if (form == ORACLE_HOTSPOT && !power) return -1;                                          \
+    const long n = (long)nx * ny * nz;                                                        \
+    const REAL cc = (REAL)cf[C_CC], cw = (REAL)cf[C_CW], ce = (REAL)cf[C_CE];                 \
+    const REAL cn = (REAL)cf[C_CN], cs = (REAL)cf[C_CS], cb = (REAL)cf[C_CB];                 \
+    const REAL ca = (REAL)cf[C_CA], cp = (REAL)cf[C_CP];                                      \
+    const REAL kamb = (REAL)cf[C_AMB] * (REAL)cf[C_TAMB];                                     \
+    REAL* buf = (REAL*)malloc(sizeof(REAL) * (size_t)n);                                      \
+    REAL* q = NULL;                                                                           \
+    if (!buf) return -1;                                                                      \
+    if (form == ORACLE_HOTSPOT) {                                                             \
+      q = (REAL*)malloc(sizeof(REAL) * (size_t)n);                                            \
+      if (!q) { free(buf); return -1; }                                                       \
+      for (long i = 0; i < n; ++i) q[i] = FMA(cp, power[i], kamb);                            \
+    }                                                                                         \
+    REAL* v = grid;                                                                           \
+    REAL* o = buf;                                                                            \
+    for (int t = 0; t < T; ++t) {                                                             \
+      _Pragma("omp parallel for collapse(2) schedule(static)")                                \
+      for (long z = 0; z < nz; ++z) {                                                         \
+        for (long y = 0; y < ny; ++y) {                                                       \
+          const long zm = clampl(z - 1, 0, nz - 1), zp = clampl(z + 1, 0, nz - 1);            \
+          const long ym = clampl(y - 1, 0, ny - 1), yp = clampl(y + 1, 0, ny - 1);            \
+          const REAL* row = v + (z * ny + y) * nx;                                            \
+          const REAL* rn = v + (z * ny + ym) * nx;                                            \
+          const REAL* rs = v + (z * ny + yp) * nx;                                            \
+          const REAL* rb = v + (zm * ny + y) * nx;                                            \
+          const REAL* ra = v + (zp * ny + y) * nx;                                            \
+          REAL* out = o + (z * ny + y) * nx;                                                  \
+          const REAL* qr = q ? q + (z * ny + y) * nx : NULL;                                  \
+          for (long x = 0; x < nx; ++x) {                                                     \
+            const long xm = clampl(x - 1, 0, nx - 1), xp = clampl(x + 1, 0, nx - 1);          \
+            REAL acc = cc * row[x];                                                           \
+            acc = FMA(cw, row[xm], acc);                                                      \
+            acc = FMA(ce, row[xp], acc);                                                      \
+            acc = FMA(cs, rs[x], acc);                                                        \
+            acc = FMA(cn, rn[x], acc);                                                        \
+            if (ndim == 3) {                                                                  \
+              acc = FMA(cb, rb[x], acc);                                                      \
+              acc = FMA(ca, ra[x], acc);                                                      \
+            }                                                                                 \
+            if (qr) acc = acc + qr[x];                                                        \
+            out[x] = acc;                                                                     \
+          }                                                                                   \
+        }                                                                                     \
+      }                                                                                       \
+      REAL* tmp = v; v = o; o = tmp;                                                          \
+    }                                                                                         \
+    if (v != grid) memcpy(grid, v, sizeof(REAL) * (size_t)n);                                 \
+    free(buf);                                                                                \
+    free(q);                                                                                  \
+    return 0;                                                                                 \
+  }                                                                                           \
+                                                                                              \
+  /* Adjoint (vector-Jacobian product) of T forward steps.  cot = dJ/dx_T.  Writes           \
+   * grad_x0 = dJ/dx_0 and, when grad_p is not NULL (hotspot), grad_p = dJ/dp.  The          \
+   * affine source does not enter the adjoint, so no forward state is needed. */             \
+  int oracle_adjoint_##SUF(int form, int ndim, int nx, int ny, int nz, const float* cf,       \
+                           const REAL* cot, int T, REAL* grad_x0, REAL* grad_p) {             \
+    if (nx < 1 || ny < 1 || nz < 1 || T < 0 || (ndim != 2 && ndim != 3)) return -1;           \
+    if (ndim == 2) nz = 1;                                                                    \
+    const long n = (long)nx * ny * nz;                                                        \
+    const REAL cc = (REAL)cf[C_CC], cw = (REAL)cf[C_CW], ce = (REAL)cf[C_CE];                 \
+    const REAL cn = (REAL)cf[C_CN], cs = (REAL)cf[C_CS], cb = (REAL)cf[C_CB];                 \
+    const REAL ca = (REAL)cf[C_CA], cp = (REAL)cf[C_CP];                                      \
+    REAL* lam = grad_x0;                                                                      \
+    REAL* nl = (REAL*)malloc(sizeof(REAL) * (size_t)n);                                       \
+    if (!nl) return -1;                                                                       \
+    memcpy(lam, cot, sizeof(REAL) * (size_t)n);                                               \
+    if (grad_p) memset(grad_p, 0, sizeof(REAL) * (size_t)n);                                  \
+    for (int t = T; t >= 1; --t) {                                                            \
+      if (grad_p && form == ORACLE_HOTSPOT)                                                   \
+        for (long i = 0; i < n; ++i) grad_p[i] = grad_p[i] + cp * lam[i];                     \
+      memset(nl, 0, sizeof(REAL) * (size_t)n);                                                \
+      for (long z = 0; z < nz; ++z)                                                           \
+        for (long y = 0; y < ny; ++y)                                                         \
+          for (long x = 0; x < nx; ++x) {                                                     \
+            const REAL l = lam[(z * ny + y) * nx + x];                                        \
+            nl[(z * ny + y) * nx + x] += cc * l;                                              \
+            nl[(z * ny + y) * nx + clampl(x - 1, 0, nx - 1)] += cw * l;                       \
+            nl[(z * ny + y) * nx + clampl(x + 1, 0, nx - 1)] += ce * l;                       \
+            nl[(z * ny + clampl(y + 1, 0, ny - 1)) * nx + x] += cs * l;                       \
+            nl[(z * ny + clampl(y - 1, 0, ny - 1)) * nx + x] += cn * l;                       \
+            if (ndim == 3) {                                                                  \
+              nl[(clampl(z - 1, 0, nz - 1) * ny + y) * nx + x] += cb * l;                     \
+              nl[(clampl(z + 1, 0, nz - 1) * ny + y) * nx + x] += ca * l;                     \
+            }                                                                                 \
+          }                                                                                   \
+      memcpy(lam, nl, sizeof(REAL) * (size_t)n);                                              \
+    }                                                                                         \
+    free(nl);                                                                                 \
+    return 0;                                                                                 \
+  }
+
+ORACLE_DEFINE(double, f64, fma)
+ORACLE_DEFINE(float, f32, fmaf)

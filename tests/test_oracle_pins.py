@@ -1,0 +1,393 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these checks re-types the oracle's loop.  Each one compares it with something
+independent: a hand-worked step, a dense matrix built from the definition and raised to a
+power by numpy, closed-form eigenmodes, an exact rational Green's function, conservation and
+fixed-point laws, a closed-form scalar recurrence, symmetry and dimension-reduction
+identities, and (for the adjoint) a dense transpose, the dot-product identity, exact central
+differences and an independent gather formulation.
+
+Paper passages: Section 2.1 (Jacobi ping-pong steps), Table 2 (stencil formulas),
+Section 5.1 (out-of-range neighbours fall back on the boundary cell).
+"""
+import itertools
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import SETS, DIFFUSION, HOTSPOT, uniform
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+# direction -> (coefficient index in the 10-vector, offset (dz, dy, dx) of the neighbour read)
+DIRS = {
+    "w": (1, (0, 0, -1)), "e": (2, (0, 0, 1)), "n": (3, (0, -1, 0)), "s": (4, (0, 1, 0)),
+    "b": (5, (-1, 0, 0)), "a": (6, (1, 0, 0)),
+}
+
+
+def dense_operator(shape, cf):
+    """Dense A with (A x)_i = cc x_i + sum_d c_d x_{clamp(i + d)} (Table 2 + Section 5.1)."""
+    shape3 = (1,) * (3 - len(shape)) + tuple(shape)
+    nz, ny, nx = shape3
+    n = nx * ny * nz
+    A = np.zeros((n, n))
+    dirs = ["w", "e", "n", "s"] + (["b", "a"] if len(shape) == 3 else [])
+    for z, y, x in itertools.product(range(nz), range(ny), range(nx)):
+        i = (z * ny + y) * nx + x
+        A[i, i] += float(cf[0])
+        for d in dirs:
+            ci, (dz, dy, dx) = DIRS[d]
+            zz = min(max(z + dz, 0), nz - 1)
+            yy = min(max(y + dy, 0), ny - 1)
+            xx = min(max(x + dx, 0), nx - 1)
+            A[i, (zz * ny + yy) * nx + xx] += float(cf[ci])
+    return A
+
+
+def dense_forward(x0, cf, T, power=None):
+    """Brute force: x_T = A^T x_0 (diffusion) or the augmented affine power (hotspot)."""
+    A = dense_operator(x0.shape, cf)
+    n = A.shape[0]
+    x = x0.astype(np.float64).ravel()
+    if power is None:
+        return (np.linalg.matrix_power(A, T) @ x).reshape(x0.shape)
+    q = float(cf[7]) * power.astype(np.float64).ravel() + float(cf[8]) * float(cf[9])
+    Aug = np.zeros((n + 1, n + 1))
+    Aug[:n, :n] = A
+    Aug[:n, n] = q
+    Aug[n, n] = 1.0
+    xa = np.append(x, 1.0)
+    return (np.linalg.matrix_power(Aug, T) @ xa)[:n].reshape(x0.shape)
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+# ---------------------------------------------------------------- hand-worked example
+
+def test_hand_worked_step_matches_golden():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "hand_step_A2_3x2.txt")) if l.strip() and l[0] != "#"]
+    expected = np.array(rows, dtype=np.float64)
+    x0 = np.array([[1, 2, 4], [8, 16, 32]], dtype=np.float32)
+    for dt in (np.float64, np.float32):
+        out = oracle.forward(x0, SETS["A2"], 1, dtype=dt)
+        assert np.array_equal(out.astype(np.float64), expected), dt
+
+
+# ---------------------------------------------------------------- dense brute force
+
+SMALL_2D = [(8, 8), (5, 3), (1, 7), (7, 1), (1, 1), (2, 9)]
+SMALL_3D = [(6, 6, 6), (3, 4, 2), (1, 5, 4), (2, 1, 3), (1, 1, 1)]
+TS = [0, 1, 2, 3, 7, 16, 33]
+
+
+@pytest.mark.parametrize("shape", SMALL_2D)
+@pytest.mark.parametrize("cset", ["A2", "D2", "AH2", "H2"])
+def test_forward_2d_equals_dense_matrix_power(shape, cset):
+    cf = SETS[cset]
+    x0 = uniform(shape, 0.0, 1.0, 11)
+    p = uniform(shape, 0.0, 1.0, 12) if cset.startswith(("H", "AH")) else None
+    for T in TS:
+        ref = dense_forward(x0, cf, T, p)
+        out = oracle.forward(x0, cf, T, power=p)
+        assert relerr(out, ref) < 1e-13, (shape, cset, T)
+        out32 = oracle.forward(x0, cf, T, power=p, dtype=np.float32)
+        assert relerr(out32, ref) < 2e-6, (shape, cset, T)
+
+
+@pytest.mark.parametrize("shape", SMALL_3D)
+@pytest.mark.parametrize("cset", ["A3", "D3", "AH3", "H3"])
+def test_forward_3d_equals_dense_matrix_power(shape, cset):
+    cf = SETS[cset]
+    x0 = uniform(shape, 0.0, 1.0, 21)
+    p = uniform(shape, 0.0, 1.0, 22) if cset.startswith(("H", "AH")) else None
+    for T in TS:
+        ref = dense_forward(x0, cf, T, p)
+        out = oracle.forward(x0, cf, T, power=p)
+        assert relerr(out, ref) < 1e-13, (shape, cset, T)
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("shape,cset,T", [((48, 64), "D2", 16), ((37, 23), "H2", 9),
+                                          ((12, 16, 20), "D3", 12), ((9, 7, 5), "H3", 7)])
+def test_dct_modes_are_eigenvectors(shape, cset, T):
+    """cos(pi*j*(x+1/2)/n) products are exact eigenvectors of the clamped symmetric stencil;
+    the eigenvalue is cc + 2*c_x*cos(pi*jx/nx) + 2*c_y*cos(pi*jy/ny) (+ 2*c_z*cos(pi*jz/nz))."""
+    cf = SETS[cset].astype(np.float64)
+    axes = [np.arange(n) for n in shape]
+    c_axis = {len(shape) - 1: cf[1], len(shape) - 2: cf[3]}
+    if len(shape) == 3:
+        c_axis[0] = cf[5]
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        js = [int(rng.integers(0, n)) for n in shape]
+        mode = np.ones(shape)
+        lam = cf[0]
+        for ax, (n, j) in enumerate(zip(shape, js)):
+            v = np.cos(np.pi * j * (axes[ax] + 0.5) / n)
+            mode = mode * v.reshape([-1 if a == ax else 1 for a in range(len(shape))])
+            lam += 2.0 * c_axis[ax] * np.cos(np.pi * j / n)
+        # diffusion form only: the eigen-relation is for the linear operator
+        out = oracle.forward(mode, np.r_[SETS[cset][:7], 0, 0, 0].astype(np.float32), T, form=DIFFUSION)
+        assert np.max(np.abs(out - lam ** T * mode)) < 1e-12, js
+
+
+def _green_exact(T, cf, dirs, ndim):
+    """Exact impulse response: coefficients of (cc + sum_d c_d * shift_d)^T, as Fractions.
+    Reading the neighbour at offset delta moves mass by -delta."""
+    terms = [((0,) * ndim, Fraction(float(cf[0])))]
+    for d in dirs:
+        ci, off = DIRS[d]
+        off = off[3 - ndim:]
+        terms.append((tuple(-o for o in off), Fraction(float(cf[ci]))))
+    poly = {(0,) * ndim: Fraction(1)}
+    for _ in range(T):
+        nxt = {}
+        for k, v in poly.items():
+            for off, c in terms:
+                kk = tuple(a + b for a, b in zip(k, off))
+                nxt[kk] = nxt.get(kk, 0) + v * c
+        poly = nxt
+    return poly
+
+
+@pytest.mark.parametrize("cset,shape,T", [("D2", (40, 40), 16), ("A2", (36, 41), 14), ("A3", (19, 20, 21), 8)])
+def test_green_function_exact(cset, shape, T):
+    """Away from the boundary the FP64 oracle reproduces the exact rational impulse response
+    bit for bit (dyadic weights: every intermediate is exactly representable)."""
+    cf = SETS[cset]
+    ndim = len(shape)
+    dirs = ["w", "e", "n", "s"] + (["b", "a"] if ndim == 3 else [])
+    centre = tuple(n // 2 for n in shape)
+    x0 = np.zeros(shape)
+    x0[centre] = 1.0
+    out = oracle.forward(x0, cf, T)
+    exact = np.zeros(shape)
+    for k, v in _green_exact(T, cf, dirs, ndim).items():
+        exact[tuple(c + o for c, o in zip(centre, k))] = float(v)
+        assert float(v) == v  # the expected value itself is exact in double
+    assert np.array_equal(out, exact)
+
+
+# ---------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("cset,shape", [("D2", (33, 17)), ("A2", (9, 30)), ("D3", (7, 9, 11)), ("A3", (5, 8, 6))])
+def test_constant_field_preserved(cset, shape):
+    cf = SETS[cset]
+    x0 = np.full(shape, 0.75, dtype=np.float32)
+    for dt in (np.float64, np.float32):
+        out = oracle.forward(x0, cf, 40, dtype=dt)
+        if cset == "D3":  # 0.4 + 6*0.1 is 1 only to FP32 rounding
+            assert np.max(np.abs(out - 0.75)) < 1e-6
+        else:
+            assert np.all(out == 0.75)
+
+
+@pytest.mark.parametrize("cset,shape", [("H2", (20, 30)), ("H3", (6, 7, 8)), ("H3p", (5, 6, 7))])
+def test_hotspot_ambient_fixed_point(cset, shape):
+    """With zero power, the ambient temperature is a fixed point (weights sum to exactly 1)."""
+    cf = SETS[cset]
+    x0 = np.full(shape, 80.0, dtype=np.float32)
+    for dt in (np.float64, np.float32):
+        out = oracle.forward(x0, cf, 25, power=np.zeros(shape, np.float32), dtype=dt)
+        assert np.all(out == 80.0)
+
+
+@pytest.mark.parametrize("cset,shape", [("H2", (6, 9)), ("H3", (4, 5, 6))])
+def test_hotspot_uniform_closed_form(cset, shape):
+    """Uniform X and P: x_t = x* + (X - x*)(1 - c_amb)^t, x* = t_amb + cp*P/c_amb."""
+    cf = SETS[cset].astype(np.float64)
+    X, P = 300.0, 1e-3
+    xs = cf[9] + cf[7] * np.float64(np.float32(P)) / cf[8]
+    for T in (1, 5, 50, 400):
+        out = oracle.forward(np.full(shape, X), SETS[cset], T, power=np.full(shape, np.float32(P)))
+        ref = xs + (X - xs) * (1.0 - cf[8]) ** T
+        assert np.max(np.abs(out - ref)) / ref < 1e-13, T
+
+
+@pytest.mark.parametrize("cset,shape", [("D2", (31, 47)), ("D3", (9, 13, 11))])
+def test_conservation_and_maximum_principle(cset, shape):
+    cf = SETS[cset]
+    x0 = uniform(shape, 0.0, 1.0, 31)
+    out = oracle.forward(x0, cf, 60)
+    # symmetric weights summing to one: the clamped operator is symmetric and doubly stochastic
+    total = float(np.sum(x0, dtype=np.float64))
+    s = float(np.sum(cf[:7], dtype=np.float64))
+    assert abs(float(out.sum()) - total * s ** 60) / total < 1e-12
+    assert out.min() >= x0.min() - 1e-12 and out.max() <= x0.max() + 1e-12
+
+
+def test_dimension_reduction_3d_single_plane():
+    """3D with nz = 1 is 2D with cc' = cc + cb + ca (both z-neighbours clamp to the cell)."""
+    cf3 = SETS["A3"]
+    cf2 = cf3.copy()
+    cf2[0] = np.float32(float(cf3[0]) + float(cf3[5]) + float(cf3[6]))
+    x0 = uniform((1, 11, 14), 0.0, 1.0, 41)
+    out3 = oracle.forward(x0, cf3, 9)
+    out2 = oracle.forward(x0[0], cf2, 9)
+    assert relerr(out3[0], out2) < 1e-14
+
+
+def test_axis_swap_transposes_output():
+    """Swapping x and y together with (cw, ce) <-> (cn, cs) transposes the result; catches
+    index mistakes on non-square grids."""
+    cf = SETS["A2"]
+    sw = cf.copy()
+    sw[1], sw[2], sw[3], sw[4] = cf[3], cf[4], cf[1], cf[2]
+    x0 = uniform((13, 7), 0.0, 1.0, 51)
+    a = oracle.forward(x0, cf, 11)
+    b = oracle.forward(np.ascontiguousarray(x0.T), sw, 11)
+    assert relerr(b.T, a) < 1e-14
+
+
+def test_linearity():
+    cf = SETS["A3"]
+    x = uniform((6, 7, 8), 0.0, 1.0, 61).astype(np.float64)
+    y = uniform((6, 7, 8), 0.0, 1.0, 62).astype(np.float64)
+    lhs = oracle.forward(2.5 * x - 0.75 * y, cf, 10)
+    rhs = 2.5 * oracle.forward(x, cf, 10) - 0.75 * oracle.forward(y, cf, 10)
+    assert relerr(lhs, rhs) < 1e-13
+
+
+# ---------------------------------------------------------------- adjoint
+
+def _linear_part(cf):
+    c = cf.copy()
+    c[7:] = 0
+    return c
+
+
+@pytest.mark.parametrize("shape,cset", [((8, 8), "AH2"), ((5, 3), "A2"), ((6, 6, 6), "AH3"), ((3, 4, 2), "A3"),
+                                        ((1, 6), "AH2"), ((1, 1, 4), "A3")])
+def test_adjoint_equals_dense_transpose(shape, cset):
+    cf = SETS[cset]
+    form = HOTSPOT if cset.startswith("AH") else DIFFUSION
+    A = dense_operator(shape, cf)
+    g = uniform(shape, -1.0, 1.0, 71).astype(np.float64).ravel()
+    for T in (0, 1, 2, 5, 13):
+        gx, gp = oracle.adjoint(g.reshape(shape), cf, T, form=form)
+        ref = np.linalg.matrix_power(A.T, T) @ g
+        assert relerr(gx.ravel(), ref) < 1e-13, T
+        if form == HOTSPOT:
+            acc = np.zeros_like(g)
+            lam = g.copy()
+            for _ in range(T):
+                acc += lam
+                lam = A.T @ lam
+            refp = float(cf[7]) * acc
+            if T == 0:
+                assert np.all(gp == 0)
+            else:
+                assert relerr(gp.ravel(), refp) < 1e-13, T
+
+
+def _gather_adjoint_step(lam, cf):
+    """Independent gather form of A^T: mirrored weights with zero padding plus, at each
+    boundary face, a self term carrying the weight of the direction that leaves the grid."""
+    nd = lam.ndim
+    out = float(cf[0]) * lam
+    dirs = ["w", "e", "n", "s"] + (["b", "a"] if nd == 3 else [])
+    for d in dirs:
+        ci, off = DIRS[d]
+        off = off[3 - nd:]
+        c = float(cf[ci])
+        ax = [i for i, o in enumerate(off) if o != 0][0]
+        o = off[ax]
+        n = lam.shape[ax]
+        # gather lam_{j - d}: shift lam by +o along ax with zero fill
+        sh = np.zeros_like(lam)
+        src = [slice(None)] * nd
+        dst = [slice(None)] * nd
+        if n > 1:
+            if o > 0:
+                src[ax], dst[ax] = slice(0, n - 1), slice(1, n)
+            else:
+                src[ax], dst[ax] = slice(1, n), slice(0, n - 1)
+            sh[tuple(dst)] = lam[tuple(src)]
+        out = out + c * sh
+        # self term where j + d leaves the grid
+        edge = [slice(None)] * nd
+        edge[ax] = slice(n - 1, n) if o > 0 else slice(0, 1)
+        selfterm = np.zeros_like(lam)
+        selfterm[tuple(edge)] = lam[tuple(edge)]
+        out = out + c * selfterm
+    return out
+
+
+@pytest.mark.parametrize("shape,cset", [((9, 12), "A2"), ((5, 6, 7), "A3"), ((1, 5), "A2"), ((4, 1, 3), "A3")])
+def test_adjoint_gather_form(shape, cset):
+    cf = SETS[cset]
+    g = uniform(shape, -1.0, 1.0, 81).astype(np.float64)
+    lam = g.copy()
+    for T in range(1, 8):
+        lam = _gather_adjoint_step(lam, cf)
+        gx, _ = oracle.adjoint(g, cf, T)
+        assert relerr(gx, lam) < 1e-13, T
+
+
+@pytest.mark.parametrize("shape,cset", [((23, 17), "A2"), ((7, 9, 8), "A3")])
+def test_dot_product_identity(shape, cset):
+    cf = SETS[cset]
+    x = uniform(shape, 0.0, 1.0, 91).astype(np.float64)
+    y = uniform(shape, 0.0, 1.0, 92).astype(np.float64)
+    for T in (1, 6, 25):
+        Ax = oracle.forward(x, cf, T)
+        ATy, _ = oracle.adjoint(y, cf, T)
+        a, b = float(np.vdot(ATy, x)), float(np.vdot(y, Ax))
+        assert abs(a - b) / max(abs(a), abs(b)) < 1e-13
+
+
+@pytest.mark.parametrize("shape,cset", [((10, 12), "AH2"), ((5, 6, 4), "AH3")])
+def test_central_differences_exact_for_quadratic_loss(shape, cset):
+    """J = 1/2 ||x_T - y||^2 is quadratic in (x0, p), so central differences carry no
+    truncation error: they match the adjoint gradient up to rounding."""
+    cf = SETS[cset]
+    T = 7
+    x0 = uniform(shape, 300.0, 350.0, 101).astype(np.float64)
+    p = uniform(shape, 0.0, 1e-3, 102).astype(np.float64)
+    y = uniform(shape, 300.0, 350.0, 103).astype(np.float64)
+    xT = oracle.forward(x0, cf, T, power=p)
+    gx, gp = oracle.adjoint(xT - y, cf, T, form=HOTSPOT)
+    rng = np.random.default_rng(0)
+    h = 0.5
+    for _ in range(6):
+        idx = tuple(int(rng.integers(0, n)) for n in shape)
+        for which, grad in (("x", gx), ("p", gp)):
+            xp, xm = x0.copy(), x0.copy()
+            pp, pm = p.copy(), p.copy()
+            if which == "x":
+                xp[idx] += h
+                xm[idx] -= h
+            else:
+                pp[idx] += h
+                pm[idx] -= h
+            jp = oracle.loss(oracle.forward(xp, cf, T, power=pp), y)
+            jm = oracle.loss(oracle.forward(xm, cf, T, power=pm), y)
+            fd = (jp - jm) / (2 * h)
+            assert abs(fd - grad[idx]) <= 1e-7 * max(1.0, abs(grad[idx])), (which, idx, fd, grad[idx])
+
+
+def test_rejects_bad_arguments():
+    with pytest.raises(ValueError):
+        oracle.forward(np.zeros((3, 3)), SETS["D2"], -1)
+    with pytest.raises(ValueError):
+        oracle.forward(np.zeros((3, 3)), SETS["H2"], 1, form=HOTSPOT)
+
+
+def test_fp32_vs_fp64_error_budget():
+    """The FP32 oracle stays well within the 1e-5 relative budget of the FP64 one on a
+    hotspot run of a thousand steps (the large 2D workload's step count)."""
+    cf = SETS["H2"]
+    x0 = uniform((64, 64), 300.0, 350.0, 111)
+    p = uniform((64, 64), 0.0, 1e-3, 112)
+    a = oracle.forward(x0, cf, 1000, power=p)
+    b = oracle.forward(x0, cf, 1000, power=p, dtype=np.float32)
+    assert relerr(b, a) < 1e-5

@@ -1,0 +1,177 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU parity tests and the bench.
+
+This module holds no stencil arithmetic: only shapes, coefficient sets, seeds and
+random draws.  Both the CPU oracle (``oracle/``) and the HIP library take their
+inputs from here, so the two sides never share anything that computes the method.
+
+Recipe (all arrays FP32, row-major, x fastest: index = (z*ny + y)*nx + x):
+
+* A uniform draw U[a, b) is ``a + (b - a) * u`` evaluated in FP32, where ``u`` comes
+  from ``numpy.random.Generator(PCG64(seed)).random(n, dtype=float32)``.
+* Workload *i* (1-based, in the order listed in ``WORKLOADS``) uses seed ``1000*i``
+  for the initial field, ``+1`` for the power map, ``+2`` for the target field and
+  ``+3`` for the batch-size draw.
+
+The paper's benchmarks (Section 5.1, Table 2) are Diffusion 2D/3D and Rodinia's
+Hotspot 2D/3D on square/cubic grids of at least 1 GB, run for many iterations
+(Section 5.2).  Rodinia's own temperature/power files are not used; the uniform
+fields below stand in for them.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+DIFFUSION = 0
+HOTSPOT = 1
+
+# Coefficient vector layout used everywhere (oracle and library binding):
+#   [cc, cw, ce, cn, cs, cb, ca, cp, c_amb, t_amb]
+# Direction convention: w = x-1, e = x+1, n = y-1, s = y+1, b = z-1, a = z+1.
+COEF_NAMES = ("cc", "cw", "ce", "cn", "cs", "cb", "ca", "cp", "c_amb", "t_amb")
+
+
+def coeffs(cc, cw, ce, cn, cs, cb=0.0, ca=0.0, cp=0.0, c_amb=0.0, t_amb=0.0):
+    """Pack a coefficient set as a float32 vector in the canonical layout."""
+    return np.array([cc, cw, ce, cn, cs, cb, ca, cp, c_amb, t_amb], dtype=np.float32)
+
+
+# Coefficient sets.  D2/D3 are the diffusion weights of the workloads; the hotspot sets
+# are dyadic (exact in FP32) with weights summing to exactly 1; A2/A3 are deliberately
+# asymmetric so orientation and transpose mistakes show up.
+SETS = {
+    "D2": coeffs(0.5, 0.125, 0.125, 0.125, 0.125),
+    "D3": coeffs(0.4, 0.1, 0.1, 0.1, 0.1, 0.1, 0.1),
+    "H2": coeffs(0.5 - 2.0 ** -10, 0.125, 0.125, 0.125, 0.125, cp=64.0, c_amb=2.0 ** -10, t_amb=80.0),
+    "H3": coeffs(0.375 - 2.0 ** -10, 0.125, 0.125, 0.125, 0.125, 0.0625, 0.0625,
+                 cp=64.0, c_amb=2.0 ** -10, t_amb=80.0),
+    # Table-2-faithful hotspot 3D ambient term: ambient coupling equals c_a.
+    "H3p": coeffs(0.3125, 0.125, 0.125, 0.125, 0.125, 0.0625, 0.0625, cp=64.0, c_amb=0.0625, t_amb=80.0),
+    "A2": coeffs(0.375, 0.0625, 0.1875, 0.125, 0.25),
+    "A3": coeffs(0.25, 0.0625, 0.1875, 0.125, 0.1875, 0.0625, 0.125),
+    # asymmetric hotspot sets (for adjoint / orientation tests of the affine form)
+    "AH2": coeffs(0.375, 0.0625, 0.1875, 0.125, 0.25, cp=8.0, c_amb=2.0 ** -8, t_amb=80.0),
+    "AH3": coeffs(0.25, 0.0625, 0.1875, 0.125, 0.1875, 0.0625, 0.125, cp=8.0, c_amb=2.0 ** -8, t_amb=80.0),
+}
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def uniform(shape, lo: float, hi: float, seed: int) -> np.ndarray:
+    """U[lo, hi) in FP32 from a PCG64 stream (see module docstring)."""
+    n = int(np.prod(shape)) if len(shape) else 1
+    u = rng(seed).random(n, dtype=np.float32)
+    out = np.float32(lo) + np.float32(hi - lo) * u
+    return out.astype(np.float32, copy=False).reshape(shape)
+
+
+def grid_shape(ndim: int, nx: int, ny: int, nz: int = 1):
+    """numpy shape of a grid (slowest axis first)."""
+    return (ny, nx) if ndim == 2 else (nz, ny, nx)
+
+
+@dataclass
+class Workload:
+    name: str
+    form: int
+    ndim: int
+    nx: int
+    ny: int
+    nz: int
+    T: int
+    coef_set: str
+    field_lo: float
+    field_hi: float
+    power_hi: float = 0.0
+    seed: int = 0
+    target_lo: float = 300.0
+    target_hi: float = 350.0
+    ckpt_every: int = 0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def shape(self):
+        return grid_shape(self.ndim, self.nx, self.ny, self.nz)
+
+    @property
+    def coeffs(self) -> np.ndarray:
+        return SETS[self.coef_set].copy()
+
+    def field(self) -> np.ndarray:
+        return uniform(self.shape, self.field_lo, self.field_hi, self.seed)
+
+    def power(self):
+        if self.form != HOTSPOT:
+            return None
+        return uniform(self.shape, 0.0, self.power_hi, self.seed + 1)
+
+    def target(self) -> np.ndarray:
+        return uniform(self.shape, self.target_lo, self.target_hi, self.seed + 2)
+
+
+# The five workloads, in order: small 2D diffusion, large 2D hotspot, large 3D diffusion,
+# the batch of uneven grids, and the 3D hotspot adjoint problem.
+WORKLOADS = {
+    "diffusion2d_256": Workload("diffusion2d_256", DIFFUSION, 2, 256, 256, 1, 16, "D2", 0.0, 1.0, seed=1000),
+    "hotspot2d_16384": Workload("hotspot2d_16384", HOTSPOT, 2, 16384, 16384, 1, 1000, "H2", 300.0, 350.0,
+                                power_hi=1e-3, seed=2000),
+    "diffusion3d_512": Workload("diffusion3d_512", DIFFUSION, 3, 512, 512, 512, 200, "D3", 0.0, 1.0, seed=3000),
+    "hotspot3d_256_adjoint": Workload("hotspot3d_256_adjoint", HOTSPOT, 3, 256, 256, 256, 400, "H3", 300.0, 350.0,
+                                      power_hi=1e-3, seed=5000, ckpt_every=20),
+}
+BATCH_SEED = 4000
+
+
+@dataclass
+class BatchGrid:
+    ndim: int
+    nx: int
+    ny: int
+    nz: int
+    T: int
+    seed: int
+
+    @property
+    def shape(self):
+        return grid_shape(self.ndim, self.nx, self.ny, self.nz)
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def coef_set(self) -> str:
+        return "D2" if self.ndim == 2 else "D3"
+
+    def field(self) -> np.ndarray:
+        return uniform(self.shape, 0.0, 1.0, self.seed)
+
+
+def batch_grids(n2d: int = 48, n3d: int = 16, lo2: int = 256, hi2: int = 4096, lo3: int = 64, hi3: int = 256,
+                tlo: int = 50, thi: int = 500, seed: int = BATCH_SEED, scale: float = 1.0):
+    """The batched workload: n2d square 2D grids with log-uniform side in [lo2, hi2], n3d cubic 3D
+    grids with log-uniform side in [lo3, hi3], and integer step counts uniform in [tlo, thi].
+
+    Sides are drawn first (2D then 3D), then step counts, from PCG64(seed + 3).  ``scale``
+    shrinks every side (for small test versions of the same recipe).
+    """
+    g = rng(seed + 3)
+    s2 = np.rint(np.exp(g.uniform(math.log(lo2), math.log(hi2), n2d))).astype(int)
+    s3 = np.rint(np.exp(g.uniform(math.log(lo3), math.log(hi3), n3d))).astype(int)
+    steps = g.integers(tlo, thi + 1, n2d + n3d)
+    out = []
+    for i, s in enumerate(s2):
+        s = max(1, int(round(s * scale)))
+        out.append(BatchGrid(2, s, s, 1, int(steps[i]), seed + 10 + i))
+    for j, s in enumerate(s3):
+        s = max(1, int(round(s * scale)))
+        out.append(BatchGrid(3, s, s, s, int(steps[n2d + j]), seed + 10 + n2d + j))
+    return out
