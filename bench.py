@@ -1,0 +1,280 @@
+"""Benchmark: temporal-blocked hotspot 2D, 16384 x 16384 cells, 1000 time steps, one MI355X.
+
+One "step" of this bench is one whole run of the hot path: stencil_run over the 16384^2
+hotspot grid for T = 1000 time steps (all passes, boundary handling, ping-pong), with the
+temperature and power maps already resident in HBM.  value = cell updates per second
+(GCell/s); the single-pass HBM roofline of this stencil is 8 TB/s / 12 B = 667 GCell/s
+(Table 2 bytes per update).  The same JSON line carries, for the dominant kernel, the
+achieved rate against its roofline, the CPU oracle timed on a bounded sample, and (unless
+--quick) the plain one-step-per-launch kernel, the 3D and batched workloads and the adjoint.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 FLOP per FMA, plain (non-packed) FP32
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def tb2d_bytes_flops(nx, ny, K, keff, seg, hot=True):
+    """Algorithmic HBM bytes and executed FP32 FLOPs of one temporal-blocked 2D pass
+    (overlapped windows of 256 columns, halo K, segments of `seg` rows)."""
+    W = 256
+    kr = (K + 3) // 4 * 4
+    cs = (W - K - kr) // 4 * 4
+    ntx = math.ceil(nx / cs)
+    nseg = math.ceil(ny / seg)
+    rows = seg + 2 * keff
+    nread = 2 if hot else 1
+    read_cells = ntx * nseg * rows * W  # each window row is read once per pass
+    bytes_ = read_cells * 4 * nread + nx * ny * 4
+    flops_per = 10 if hot else 9  # mul + 4 fma (+ add of the source term), FMA = 2 FLOP
+    flops = ntx * nseg * W * (seg + keff) * keff * flops_per
+    return bytes_, flops
+
+
+def time_call(fn, stream, reps):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(wl, budget_s=12.0):
+    """The FP32 oracle on a bounded sample of the same workload (a square sub-grid of the
+    hotspot field, the same coefficients), scaled to GCell/s."""
+    import oracle
+    side = 2048
+    x0 = wl.field()[:side, :side].copy()
+    p = wl.power()[:side, :side].copy()
+    t0 = time.perf_counter()
+    oracle.forward(x0, wl.coeffs, 4, power=p, dtype=np.float32)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    steps = max(4, min(wl.T, int(budget_s / dt * 4)))
+    t0 = time.perf_counter()
+    oracle.forward(x0, wl.coeffs, steps, power=p, dtype=np.float32)
+    dt = time.perf_counter() - t0
+    return {"value": round(side * side * steps / dt / 1e9, 4), "unit": "GCell/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "FP32 oracle, hotspot 2D %dx%d sub-grid of the same field, %d steps, %.1f s" % (
+                side, side, steps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--quick", action="store_true", help="main workload only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the slab "
+              "decomposition over xGMI is design-only).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1802_00438_amd as S
+    from workloads import WORKLOADS, SETS, HOTSPOT, DIFFUSION, batch_grids
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    wl = WORKLOADS["hotspot2d_16384"]
+    cells = wl.cells
+    log("[bench] generating %s inputs" % wl.name)
+    x_host = wl.field()
+    p_host = wl.power()
+    x = torch.from_numpy(x_host).to(dev)
+    p = torch.from_numpy(p_host).to(dev)
+    del x_host
+    log("[bench] creating plan (auto-tune)")
+    plan = S.Plan(HOTSPOT, wl.shape)
+    tun = plan.tuning
+    log("[bench] tuning %s" % tun)
+    cf = wl.coeffs
+
+    def step():
+        plan.run(x, cf, wl.T, p)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for i in range(args.steps):
+        step()
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    gcells = cells * wl.T / (ms * 1e-3) / 1e9
+    log("[bench] main: %.3f ms per run, %.1f GCell/s (wall %.2f s)" % (ms, gcells, wall))
+
+    # dominant kernel: the temporal-blocked hotspot pass; its average launch duration over the
+    # timed region is the run time minus the parity copy, divided by the launches per run
+    K = tun["k"]
+    passes = math.ceil(wl.T / K)
+    copy_ms = 0.0
+    if passes % 2 == 1:
+        tmp = torch.empty_like(x)
+        copy_ms = time_call(lambda: tmp.copy_(x), stream, 5)
+        del tmp
+    kern_ms = (ms - copy_ms) / passes
+    full_bytes, full_flops = tb2d_bytes_flops(wl.nx, wl.ny, K, K, tun["seg_len"], hot=True)
+    gbs = full_bytes / (kern_ms * 1e-3) / 1e9
+    tflops = full_flops / (kern_ms * 1e-3) / 1e12
+    frac_hbm = gbs / HBM_PEAK_GBS
+    frac_alu = tflops / ALU_PEAK_TFLOPS
+    if frac_alu >= frac_hbm:
+        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                "frac": round(frac_alu, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(frac_hbm, 4)}
+    roof["traffic"] = None
+    roof["kernel"] = "tb2d_kernel<K=%d,V=4,hotspot>" % K
+    roof["avg_launch_ms"] = round(kern_ms, 4)
+    roof["hbm_gbs_algorithmic"] = round(gbs, 1)
+    roof["tflops_executed"] = round(tflops, 3)
+
+    out = {
+        "metric": "GCell-updates/s & % HBM roofline (fwd, adjoint) vs plain 1-step/pass kernel",
+        "value": round(gcells, 2),
+        "unit": "GCell/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "hotspot2d_16384", "nx": wl.nx, "ny": wl.ny, "T": wl.T, "coeffs": "H2",
+                   "k": K, "seg_len": tun["seg_len"], "bsize_x": tun["bsize_x"]},
+        "pct_single_pass_roofline": round(100.0 * gcells / (HBM_PEAK_GBS / 12.0), 1),
+        "effective_gbs_eq9": round(gcells * 12.0, 1),
+        "effective_gflops_table2": round(gcells * 15.0, 1),
+        "roofline": roof,
+    }
+
+    extras = {}
+    if not args.quick:
+        # plain one-step-per-launch comparator on the same grid (fewer steps, same per-step work)
+        pplan = S.Plan(HOTSPOT, wl.shape, {"variant": 1})
+        Tp = 200
+        pplan.run(x, cf, 4, p)
+        pms = time_call(lambda: pplan.run(x, cf, Tp, p), stream, 2)
+        pg = cells * Tp / (pms * 1e-3) / 1e9
+        extras["plain_hotspot2d_16384"] = {"gcells": round(pg, 1), "ms_per_step_update": round(pms / Tp, 4),
+                                           "hbm_gbs_eff": round(pg * 12, 1),
+                                           "speedup_tb_vs_plain": round(gcells / pg, 2)}
+        pplan.close()
+        log("[bench] plain: %.1f GCell/s" % pg)
+    plan.close()
+    del x, p
+    torch.cuda.empty_cache()
+
+    if not args.quick:
+        # 3D diffusion 512^3, 200 steps: temporal-blocked vs plain
+        w3 = WORKLOADS["diffusion3d_512"]
+        x3 = torch.from_numpy(w3.field()).to(dev)
+        pl3 = S.Plan(DIFFUSION, w3.shape)
+        pl3.run(x3, w3.coeffs, 8)
+        ms3 = time_call(lambda: pl3.run(x3, w3.coeffs, w3.T), stream, 2)
+        g3 = w3.cells * w3.T / (ms3 * 1e-3) / 1e9
+        pp3 = S.Plan(DIFFUSION, w3.shape, {"variant": 1})
+        msp3 = time_call(lambda: pp3.run(x3, w3.coeffs, 40), stream, 1)
+        gp3 = w3.cells * 40 / (msp3 * 1e-3) / 1e9
+        extras["diffusion3d_512"] = {"gcells_tb": round(g3, 1), "ms_tb": round(ms3, 2), "k": pl3.tuning["k"],
+                                     "gcells_plain": round(gp3, 1),
+                                     "pct_single_pass_roofline": round(100 * g3 / (HBM_PEAK_GBS / 8), 1)}
+        pl3.close(); pp3.close()
+        del x3
+        log("[bench] 3D: tb %.1f plain %.1f GCell/s" % (g3, gp3))
+
+        # small 2D diffusion 256^2, 16 steps (launch-latency bound)
+        w1 = WORKLOADS["diffusion2d_256"]
+        x1 = torch.from_numpy(w1.field()).to(dev)
+        pl1 = S.Plan(DIFFUSION, w1.shape)
+        pl1.run(x1, w1.coeffs, w1.T)
+        ms1 = time_call(lambda: pl1.run(x1, w1.coeffs, w1.T), stream, 20)
+        extras["diffusion2d_256"] = {"us_per_run": round(ms1 * 1e3, 1),
+                                     "gcells": round(w1.cells * w1.T / (ms1 * 1e-3) / 1e9, 1)}
+        pl1.close()
+
+        # adjoint: hotspot 3D 256^3, 400 steps, checkpoints every 20 steps
+        w5 = WORKLOADS["hotspot3d_256_adjoint"]
+        x5 = torch.from_numpy(w5.field()).to(dev)
+        p5 = torch.from_numpy(w5.power()).to(dev)
+        y5 = torch.from_numpy(w5.target()).to(dev)
+        pl5 = S.Plan(HOTSPOT, w5.shape)
+        xs = x5.clone()
+        pl5.run(xs, w5.coeffs, 4, p5)
+        xs.copy_(x5)
+        fwd_ms = time_call(lambda: pl5.run_ckpt(xs, w5.coeffs, w5.T, w5.ckpt_every, p5), stream, 1)
+        cot = (xs - y5).contiguous()
+        gx = torch.empty_like(x5)
+        gp = torch.empty_like(x5)
+        adj_ms = time_call(lambda: pl5.adjoint(cot, w5.coeffs, w5.T, gx, gp, p5, 0), stream, 1)
+        t0 = time.perf_counter()
+        pl5.adjoint(cot, w5.coeffs, w5.T, gx, gp, p5, 1)
+        torch.cuda.synchronize()
+        adj_rc_ms = (time.perf_counter() - t0) * 1e3
+        extras["hotspot3d_256_adjoint"] = {
+            "fwd_ckpt_ms": round(fwd_ms, 2), "adjoint_ms": round(adj_ms, 2),
+            "adjoint_recompute_ms": round(adj_rc_ms, 2), "ratio_adjoint_fwd": round(adj_ms / fwd_ms, 2),
+            "ratio_recompute_fwd": round(adj_rc_ms / fwd_ms, 2),
+            "gcells_fwd": round(w5.cells * w5.T / (fwd_ms * 1e-3) / 1e9, 1), "k": pl5.tuning["k"]}
+        pl5.close()
+        del x5, p5, y5, xs, cot, gx, gp
+        log("[bench] adjoint: fwd %.2f ms adj %.2f ms" % (fwd_ms, adj_ms))
+
+        # batched: 64 uneven grids in one persistent launch (graph replay)
+        grids = batch_grids()
+        xs = [torch.from_numpy(g.field()).to(dev) for g in grids]
+        cfs = [SETS[g.coef_set] for g in grids]
+        ts = [g.T for g in grids]
+        cache = S.run_batched(xs, cfs, ts)
+        torch.cuda.synchronize()
+        bms = time_call(lambda: S.run_batched(xs, cfs, ts, cache=cache), stream, 2)
+        upd = sum(g.cells * g.T for g in grids)
+        extras["batched_64"] = {"ms": round(bms, 2), "updates": upd,
+                                "gcells_aggregate": round(upd / (bms * 1e-3) / 1e9, 1)}
+        S.stencil_batch_destroy(cache)
+        del xs
+        log("[bench] batched: %.1f GCell/s aggregate" % (upd / (bms * 1e-3) / 1e9))
+
+    out["other_workloads"] = extras
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * stencil.h -- C ABI of the MI355X (gfx950) temporal-blocked star-stencil library.
+ *
+ * The library runs T time steps of first-order star stencils (5-point 2D, 7-point 3D) in
+ * FP32 on one GPU, with combined spatial and temporal blocking: overlapped tiles carry
+ * several fused time steps per pass over HBM.  Method: Zohouri, Podobas, Matsuoka,
+ * "Combined Spatial and Temporal Blocking for High-Performance Stencil Computation on FPGAs
+ * Using OpenCL" (Sections 2.1, 3.1, 3.2, 4, 5.1; Table 2).
+ *
+ * Conventions shared by every entry point
+ *   - Grids are FP32, row-major, x fastest: index = (z*ny + y)*nx + x (2D: nz = 1).
+ *   - Directions: w = x-1, e = x+1, n = y-1, s = y+1, b = z-1, a = z+1.
+ *   - Boundary: an out-of-range neighbour takes the value of the boundary cell itself, in
+ *     every direction and at every step (Section 5.1).
+ *   - One time step (Section 2.1, Table 2) reads every cell from one buffer and writes
+ *       out = cc*c + cw*w + ce*e + cs*s + cn*n [+ cb*b + ca*a]   (diffusion)
+ *       out = (same weighted sum) + q,  q = fma(cp, p, c_amb*t_amb)  (hotspot)
+ *     evaluated as the FMA chain c, w, e, s, n, b, a then + q, with k_amb = c_amb*t_amb
+ *     rounded once in FP32.  Steps are Jacobi (out-of-place, ping-pong).
+ *   - Pointers named "device" must be device memory of the current HIP device, 16-byte
+ *     aligned for the fast path (4-byte aligned is accepted), and must not alias each
+ *     other.  The caller owns them and keeps them alive until the stream work completes.
+ *   - Every call is stream-ordered on the plan's stream (or the stream passed in); nothing
+ *     synchronises the host unless stated.
+ *   - Errors: argument errors return before any device work.  No C++ exception crosses
+ *     this ABI.  stencil_last_error() gives a thread-local detail message.
+ */
+#ifndef STENCIL_MI355_H
+#define STENCIL_MI355_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STENCIL_OK = 0,
+  STENCIL_ERR_INVALID_ARG = -1,   /* bad pointer, size, step count, coefficient, form */
+  STENCIL_ERR_UNSUPPORTED = -2,   /* valid request this build does not implement */
+  STENCIL_ERR_OUT_OF_MEMORY = -3, /* device allocation of plan-owned memory failed */
+  STENCIL_ERR_HIP = -4,           /* a HIP runtime call failed (message in stencil_last_error) */
+  STENCIL_ERR_INTERNAL = -5       /* invariant violated inside the library */
+} stencil_status_t;
+
+typedef enum { STENCIL_DIFFUSION = 0, STENCIL_HOTSPOT = 1 } stencil_form_t;
+
+/* Stencil weights (Table 2).  cb, ca are ignored for 2D; cp, c_amb, t_amb for diffusion.
+ * All must be finite.  The paper's Hotspot 2D form maps onto these with
+ * cc = 1 - sdc*(2Rx_1 + 2Ry_1 + Rz_1), cw = ce = sdc*Rx_1, cn = cs = sdc*Ry_1, cp = sdc,
+ * c_amb = sdc*Rz_1; its Hotspot 3D form sets c_amb = ca. */
+typedef struct {
+  float cc, cw, ce, cn, cs, cb, ca;
+  float cp;    /* hotspot: weight of the power map (sdc in Table 2) */
+  float c_amb; /* hotspot: ambient coupling */
+  float t_amb; /* hotspot: ambient temperature (a compile-time constant in the paper) */
+} stencil_coeffs_t;
+
+/* Blocking parameters.  0 in any field means "choose automatically".
+ *   variant  0 auto, 1 plain one-step-per-pass kernel, 2 temporal-blocked kernel
+ *   k        fused time steps per pass (par_time of Section 3.2; halo = k, Eq. 2)
+ *   vec      FP32 cells per lane along x (par_vec of Section 3.1)
+ *   bsize_x  spatial block width in cells (64*vec for the temporal-blocked kernels)
+ *   bsize_y  3D: spatial block height in cells
+ *   seg_len  cells of the streamed axis (y in 2D, z in 3D) handled by one tile pass */
+typedef struct {
+  int variant, k, vec, bsize_x, bsize_y, seg_len;
+} stencil_tuning_t;
+
+typedef struct stencil_plan_s* stencil_plan_t;
+
+/* Create a plan for a grid of nx*ny*nz cells (ndim 2: nz must be 1).  Allocates the plan's
+ * ping-pong scratch (one grid) on the current device and, when tuning is NULL or has zero
+ * fields, picks the blocking from the bandwidth/halo cost model and short timed trials on
+ * scratch memory (cached per shape).  hip_stream: a hipStream_t, or NULL for the default
+ * stream.  *out receives the plan; on error *out is NULL. */
+stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int ndim, int nx, int ny,
+                                int nz, const stencil_tuning_t* tuning, void* hip_stream);
+
+/* Run exactly T >= 0 time steps in place on grid (device, nx*ny*nz FP32).  power (device,
+ * same shape) is required for HOTSPOT and ignored for DIFFUSION.  T == 0 leaves grid
+ * unchanged.  Enqueues ceil(T/k) temporal-blocked passes (the last one shorter when k does
+ * not divide T, Section 3.2) alternating between grid and plan scratch so that the result
+ * lands in grid.  Asynchronous. */
+stencil_status_t stencil_run(stencil_plan_t plan, float* grid, const float* power,
+                             const stencil_coeffs_t* coeffs, int T);
+
+/* As stencil_run, and additionally keeps checkpoints of the field every ckpt_every steps
+ * (0 = round(sqrt(T))) in plan-owned device memory: checkpoint j holds x_{j*ckpt_every}
+ * for j = 0 .. floor((T-1)/ckpt_every).  Passes are cut at checkpoint steps.  The
+ * checkpoints replace any earlier ones.  Returns OUT_OF_MEMORY if they do not fit. */
+stencil_status_t stencil_run_ckpt(stencil_plan_t plan, float* grid, const float* power,
+                                  const stencil_coeffs_t* coeffs, int T, int ckpt_every);
+
+/* Adjoint (vector-Jacobian product) of T steps.  cotangent = dJ/dx_T (device, read only).
+ * Writes grad_x0 = dJ/dx_0 (device) and, if grad_power is not NULL and the plan is
+ * HOTSPOT, grad_power = dJ/dp (device).  Applies the transposed stencil backward in time
+ * with the same temporal blocking as the forward pass; dJ/dp = cp * sum_{t=1..T} lambda_t is
+ * accumulated in registers over the fused steps of a pass and written once per pass.
+ * recompute = 1 additionally re-runs each checkpoint segment of the last stencil_run_ckpt
+ * (power must then be the same device map) and checks the recomputed segment end equals
+ * the next stored checkpoint bit for bit (STENCIL_ERR_INTERNAL if not); the gradient of
+ * these affine maps does not depend on forward states, so recompute = 0 is exact too.
+ * grad_x0 and grad_power must not alias cotangent. */
+stencil_status_t stencil_adjoint(stencil_plan_t plan, const float* cotangent, const float* power,
+                                 const stencil_coeffs_t* coeffs, int T, float* grad_x0,
+                                 float* grad_power, int recompute);
+
+/* One grid of a batch. */
+typedef struct {
+  stencil_form_t form; /* DIFFUSION only in this build (HOTSPOT returns UNSUPPORTED) */
+  int ndim, nx, ny, nz;
+  float* grid;         /* device, in/out */
+  const float* power;  /* unused for diffusion */
+  stencil_coeffs_t coeffs;
+  int T;
+} stencil_batch_item_t;
+
+/* Opaque captured batch (persistent kernels inside a HIP graph, plus their work lists). */
+typedef struct stencil_batch_s* stencil_batch_t;
+
+/* Run every item of the batch, each for its own T steps, in one persistent launch per
+ * dimensionality, captured once in a HIP graph.  Work items (grid, pass, tile) are claimed
+ * in a global dependency order by resident workgroups; an item waits only for the tiles of
+ * the previous pass of its own grid that overlap its halo.  Tile shape and temporal degree
+ * per grid come from the cost model.
+ *   graph_cache: NULL -> build, run and free everything in this call.
+ *                non-NULL -> if *graph_cache is NULL, build and store the captured batch
+ *                there; otherwise replay *graph_cache, which must have been built from
+ *                items with identical shapes, T, grid pointers and coefficients
+ *                (INVALID_ARG otherwise).
+ * Items must not share grid memory.  Asynchronous on hip_stream. */
+stencil_status_t stencil_run_batched(int n, const stencil_batch_item_t* items, void* hip_stream,
+                                     stencil_batch_t* graph_cache);
+
+/* Free a captured batch (synchronises its stream first).  NULL is a no-op. */
+void stencil_batch_destroy(stencil_batch_t batch);
+
+/* Report the blocking the plan resolved to (after auto-tuning). */
+stencil_status_t stencil_get_tuning(stencil_plan_t plan, stencil_tuning_t* out);
+
+/* Free the plan, its scratch and checkpoints (synchronises the plan stream).  NULL ok. */
+void stencil_destroy(stencil_plan_t plan);
+
+const char* stencil_status_string(stencil_status_t status);
+const char* stencil_last_error(void); /* thread-local; "" if none */
+
+/* ---------------------------------------------------------------- performance model
+ * The paper's external-memory model (Section 4, Eq. 3-9), as used to prune the tuning
+ * space (Section 5.3).  Pure host arithmetic; needs no device.  rad = 1 for the evaluated
+ * stencils.  dims: 2D uses dim_x, dim_y; 3D uses dim_x, dim_y, dim_z.  th_max in GB/s
+ * (1 GB = 1e9 B). */
+typedef struct {
+  int ndim, rad, par_vec, par_time;
+  double f_max_hz;
+  int size_cell, num_read, num_write;
+  int bsize_x, bsize_y;
+  long dim_x, dim_y, dim_z;
+  long iter;
+  double th_max_gbs;
+} stencil_model_params_t;
+
+typedef struct {
+  double th_mem_gbs;     /* Eq. 3 */
+  long csize_x, csize_y; /* Eq. 4 */
+  long bnum_x, bnum_y;   /* Eq. 5 */
+  double t_cell;         /* Eq. 6 */
+  double t_read, t_write;/* Eq. 7 and the write count */
+  double run_time_s;     /* Eq. 8 */
+  double throughput_gbs; /* Eq. 9, effective GB/s */
+} stencil_model_result_t;
+
+stencil_status_t stencil_model_estimate(const stencil_model_params_t* p, stencil_model_result_t* r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STENCIL_MI355_H */

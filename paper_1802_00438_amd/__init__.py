@@ -1,0 +1,342 @@
+"""Python binding of the MI355X temporal-blocked stencil library (C ABI of include/stencil.h).
+
+Argument marshalling only: every step of the computation runs in the HIP kernels of
+``libstencil_mi355.so``.  PyTorch supplies device memory (tensor data pointers) and the current
+HIP stream.  If the shared library is missing, every call raises; there is no fallback.
+
+Names follow the C ABI (``stencil_create``, ``stencil_run``, ``stencil_run_ckpt``,
+``stencil_adjoint``, ``stencil_run_batched``, ...).  ``Plan``, ``run``, ``adjoint``,
+``StencilFn`` and ``run_batched`` are thin conveniences over them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstencil_mi355.so")
+
+DIFFUSION = 0
+HOTSPOT = 1
+
+STENCIL_OK = 0
+STATUS = {0: "STENCIL_OK", -1: "STENCIL_ERR_INVALID_ARG", -2: "STENCIL_ERR_UNSUPPORTED",
+          -3: "STENCIL_ERR_OUT_OF_MEMORY", -4: "STENCIL_ERR_HIP", -5: "STENCIL_ERR_INTERNAL"}
+
+EXPORTED = ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoint", "stencil_run_batched",
+            "stencil_batch_destroy", "stencil_get_tuning", "stencil_destroy", "stencil_status_string",
+            "stencil_last_error", "stencil_model_estimate")
+
+
+class StencilError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), message))
+        self.status = status
+
+
+class Coeffs(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_float) for n in ("cc", "cw", "ce", "cn", "cs", "cb", "ca", "cp", "c_amb", "t_amb")]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int) for n in ("variant", "k", "vec", "bsize_x", "bsize_y", "seg_len")]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int), ("ndim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("nz", ctypes.c_int), ("grid", ctypes.c_void_p), ("power", ctypes.c_void_p),
+                ("coeffs", Coeffs), ("T", ctypes.c_int)]
+
+
+class ModelParams(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("rad", ctypes.c_int), ("par_vec", ctypes.c_int), ("par_time", ctypes.c_int),
+                ("f_max_hz", ctypes.c_double), ("size_cell", ctypes.c_int), ("num_read", ctypes.c_int),
+                ("num_write", ctypes.c_int), ("bsize_x", ctypes.c_int), ("bsize_y", ctypes.c_int),
+                ("dim_x", ctypes.c_long), ("dim_y", ctypes.c_long), ("dim_z", ctypes.c_long), ("iter", ctypes.c_long),
+                ("th_max_gbs", ctypes.c_double)]
+
+
+class ModelResult(ctypes.Structure):
+    _fields_ = [("th_mem_gbs", ctypes.c_double), ("csize_x", ctypes.c_long), ("csize_y", ctypes.c_long),
+                ("bnum_x", ctypes.c_long), ("bnum_y", ctypes.c_long), ("t_cell", ctypes.c_double),
+                ("t_read", ctypes.c_double), ("t_write", ctypes.c_double), ("run_time_s", ctypes.c_double),
+                ("throughput_gbs", ctypes.c_double)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def lib():
+    """The loaded ctypes library.  Raises if libstencil_mi355.so has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError("libstencil_mi355.so is not built (run __graft_entry__.build() or "
+                                  "python paper_1802_00438_amd/build.py)")
+            L = ctypes.CDLL(LIB_PATH)
+            vp, i, f = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_float)
+            L.stencil_create.argtypes = [ctypes.POINTER(vp), i, i, i, i, i, ctypes.POINTER(Tuning), vp]
+            L.stencil_run.argtypes = [vp, vp, vp, ctypes.POINTER(Coeffs), i]
+            L.stencil_run_ckpt.argtypes = [vp, vp, vp, ctypes.POINTER(Coeffs), i, i]
+            L.stencil_adjoint.argtypes = [vp, vp, vp, ctypes.POINTER(Coeffs), i, vp, vp, i]
+            L.stencil_run_batched.argtypes = [i, ctypes.POINTER(BatchItem), vp, ctypes.POINTER(vp)]
+            L.stencil_batch_destroy.argtypes = [vp]
+            L.stencil_batch_destroy.restype = None
+            L.stencil_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+            L.stencil_destroy.argtypes = [vp]
+            L.stencil_destroy.restype = None
+            L.stencil_status_string.argtypes = [i]
+            L.stencil_status_string.restype = ctypes.c_char_p
+            L.stencil_last_error.argtypes = []
+            L.stencil_last_error.restype = ctypes.c_char_p
+            L.stencil_model_estimate.argtypes = [ctypes.POINTER(ModelParams), ctypes.POINTER(ModelResult)]
+            for name in ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoint",
+                         "stencil_run_batched", "stencil_get_tuning", "stencil_model_estimate"):
+                getattr(L, name).restype = i
+            _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != STENCIL_OK:
+        msg = lib().stencil_last_error().decode(errors="replace")
+        raise StencilError(status, msg)
+
+
+def make_coeffs(c) -> Coeffs:
+    """From a 10-vector [cc, cw, ce, cn, cs, cb, ca, cp, c_amb, t_amb], a dict or a Coeffs."""
+    if isinstance(c, Coeffs):
+        return c
+    if isinstance(c, dict):
+        return Coeffs(**{k: float(v) for k, v in c.items()})
+    vals = [float(v) for v in c]
+    vals += [0.0] * (10 - len(vals))
+    return Coeffs(*vals[:10])
+
+
+def make_tuning(t) -> Tuning | None:
+    if t is None:
+        return None
+    if isinstance(t, Tuning):
+        return t
+    return Tuning(**{k: int(v) for k, v in t.items()})
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+# ------------------------------------------------------------------ C ABI, same names
+
+def stencil_create(form, ndim, nx, ny, nz, tuning=None, stream=None):
+    h = ctypes.c_void_p()
+    t = make_tuning(tuning)
+    _check(lib().stencil_create(ctypes.byref(h), int(form), int(ndim), int(nx), int(ny), int(nz),
+                                ctypes.byref(t) if t is not None else None, _stream(stream)))
+    return h
+
+
+def stencil_run(plan, grid, power, coeffs, T):
+    c = make_coeffs(coeffs)
+    _check(lib().stencil_run(plan, _ptr(grid), _ptr(power), ctypes.byref(c), int(T)))
+
+
+def stencil_run_ckpt(plan, grid, power, coeffs, T, ckpt_every=0):
+    c = make_coeffs(coeffs)
+    _check(lib().stencil_run_ckpt(plan, _ptr(grid), _ptr(power), ctypes.byref(c), int(T), int(ckpt_every)))
+
+
+def stencil_adjoint(plan, cotangent, power, coeffs, T, grad_x0, grad_power=None, recompute=0):
+    c = make_coeffs(coeffs)
+    _check(lib().stencil_adjoint(plan, _ptr(cotangent), _ptr(power), ctypes.byref(c), int(T), _ptr(grad_x0),
+                                 _ptr(grad_power), int(recompute)))
+
+
+def stencil_run_batched(items, stream=None, cache=None):
+    """items: sequence of BatchItem.  cache: None, or a ctypes.c_void_p holder (build-and-keep /
+    replay).  Returns the cache holder."""
+    arr = (BatchItem * len(items))(*items)
+    _check(lib().stencil_run_batched(len(items), arr, _stream(stream),
+                                     ctypes.byref(cache) if cache is not None else None))
+    return cache
+
+
+def stencil_batch_destroy(cache):
+    if cache is not None and cache.value:
+        lib().stencil_batch_destroy(cache)
+        cache.value = None
+
+
+def stencil_get_tuning(plan) -> dict:
+    t = Tuning()
+    _check(lib().stencil_get_tuning(plan, ctypes.byref(t)))
+    return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+
+def stencil_destroy(plan):
+    lib().stencil_destroy(plan)
+
+
+def stencil_status_string(status: int) -> str:
+    return lib().stencil_status_string(int(status)).decode()
+
+
+def stencil_last_error() -> str:
+    return lib().stencil_last_error().decode(errors="replace")
+
+
+def stencil_model_estimate(**kw) -> dict:
+    p = ModelParams(**kw)
+    r = ModelResult()
+    _check(lib().stencil_model_estimate(ctypes.byref(p), ctypes.byref(r)))
+    return {k: getattr(r, k) for k, _ in ModelResult._fields_}
+
+
+# ------------------------------------------------------------------ conveniences
+
+def _dims(x):
+    if x.dim() == 2:
+        return 2, x.shape[1], x.shape[0], 1
+    if x.dim() == 3:
+        return 3, x.shape[2], x.shape[1], x.shape[0]
+    raise ValueError("grid must be (ny, nx) or (nz, ny, nx)")
+
+
+def _check_tensor(x, name):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float32 or not x.is_contiguous():
+        raise ValueError("%s must be a contiguous float32 CUDA/HIP tensor" % name)
+
+
+class Plan:
+    """A plan for one grid shape: owns the ping-pong scratch and checkpoints."""
+
+    def __init__(self, form, shape, tuning=None, stream=None):
+        self.form = int(form)
+        self.shape = tuple(int(s) for s in shape)
+        if len(self.shape) == 2:
+            ndim, nx, ny, nz = 2, self.shape[1], self.shape[0], 1
+        else:
+            ndim, nx, ny, nz = 3, self.shape[2], self.shape[1], self.shape[0]
+        self.ndim = ndim
+        self.handle = stencil_create(self.form, ndim, nx, ny, nz, tuning, stream)
+
+    def run(self, grid, coeffs, T, power=None):
+        _check_tensor(grid, "grid")
+        if power is not None:
+            _check_tensor(power, "power")
+        stencil_run(self.handle, grid, power, coeffs, T)
+        return grid
+
+    def run_ckpt(self, grid, coeffs, T, ckpt_every=0, power=None):
+        _check_tensor(grid, "grid")
+        stencil_run_ckpt(self.handle, grid, power, coeffs, T, ckpt_every)
+        return grid
+
+    def adjoint(self, cotangent, coeffs, T, grad_x0, grad_power=None, power=None, recompute=0):
+        _check_tensor(cotangent, "cotangent")
+        _check_tensor(grad_x0, "grad_x0")
+        stencil_adjoint(self.handle, cotangent, power, coeffs, T, grad_x0, grad_power, recompute)
+        return grad_x0, grad_power
+
+    @property
+    def tuning(self):
+        return stencil_get_tuning(self.handle)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            stencil_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run(x, coeffs, T, power=None, tuning=None):
+    """T steps in place on x (float32 device tensor, (ny, nx) or (nz, ny, nx))."""
+    _check_tensor(x, "x")
+    form = HOTSPOT if power is not None else DIFFUSION
+    p = Plan(form, x.shape, tuning)
+    try:
+        p.run(x, coeffs, T, power)
+    finally:
+        p.close()
+    return x
+
+
+def _stencil_fn():
+    import torch
+
+    class StencilFn(torch.autograd.Function):
+        """x_T = T steps of the stencil applied to x0 (hotspot when power is given).
+
+        backward returns dJ/dx0 and dJ/dpower from the library's adjoint kernels; forward keeps
+        checkpoints every ckpt_every steps (0 = sqrt(T)), and recompute=1 re-runs and checks them
+        during backward."""
+
+        @staticmethod
+        def forward(ctx, x0, power, coeffs, T, ckpt_every=0, recompute=0, tuning=None):
+            form = HOTSPOT if power is not None else DIFFUSION
+            plan = Plan(form, x0.shape, tuning)
+            x = x0.detach().clone()
+            plan.run_ckpt(x, coeffs, T, ckpt_every, power)
+            ctx.plan = plan
+            ctx.coeffs = coeffs
+            ctx.T = T
+            ctx.recompute = recompute
+            ctx.has_power = power is not None
+            ctx.save_for_backward(power if power is not None else torch.empty(0, device=x0.device))
+            return x
+
+        @staticmethod
+        def backward(ctx, g):
+            (power,) = ctx.saved_tensors
+            g = g.contiguous()
+            gx = torch.empty_like(g)
+            gp = torch.empty_like(g) if ctx.has_power else None
+            ctx.plan.adjoint(g, ctx.coeffs, ctx.T, gx, gp, power if ctx.has_power else None, ctx.recompute)
+            ctx.plan.close()
+            return gx, gp, None, None, None, None, None
+
+    return StencilFn
+
+
+_fn_cache = {}
+
+
+def __getattr__(name):
+    if name == "StencilFn":
+        if "fn" not in _fn_cache:
+            _fn_cache["fn"] = _stencil_fn()
+        return _fn_cache["fn"]
+    raise AttributeError(name)
+
+
+def run_batched(grids, coeffs_list, steps, stream=None, cache=None):
+    """Run grids[i] (device tensors, 2D or 3D, diffusion) for steps[i] steps each, in one
+    persistent launch captured in a HIP graph.  Pass the returned cache back to replay."""
+    items = []
+    for x, c, T in zip(grids, coeffs_list, steps):
+        _check_tensor(x, "grid")
+        ndim, nx, ny, nz = _dims(x)
+        items.append(BatchItem(DIFFUSION, ndim, nx, ny, nz, x.data_ptr(), None, make_coeffs(c), int(T)))
+    if cache is None:
+        cache = ctypes.c_void_p()
+    return stencil_run_batched(items, stream, cache)

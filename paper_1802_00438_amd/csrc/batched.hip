@@ -1,0 +1,369 @@
+// batched.hip -- many grids of uneven sizes in one persistent launch per dimensionality.
+//
+// Every grid is split into temporal-blocked passes and overlapped tiles exactly as a single
+// run would be (paper Sections 3.1-3.2).  All (grid, pass, tile) work items go into one list in
+// pass-major order; resident workgroups claim items with an atomic counter and, before
+// computing, wait until every tile of the previous pass of the same grid whose output
+// overlaps the item's halo window has finished (a per-tile "passes done" flag, acquire/
+// release at agent scope).  An item only ever waits for items that precede it in the list, so
+// the claim order is a topological order and the launch cannot deadlock, whatever the number
+// of resident workgroups.  Waiting on the previous-pass neighbours also covers the
+// write-after-read hazard of the ping-pong buffers: the buffer a pass writes was last read by
+// exactly those neighbours one pass earlier.
+//
+// Each grid uses an even number of passes (the steps spread over them), so its result ends in
+// the caller's buffer.  The flag reset and both persistent kernels are captured once in a HIP
+// graph and replayed; the reset is a fill kernel, not a memset node.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+#include "runtime.hpp"
+
+namespace {
+
+constexpr int kBatchK2 = 16;  // fused-step capacity of the 2D persistent kernel
+constexpr int kBatchK3 = 4;   // and of the 3D one
+
+struct BGrid {
+  float* buf[2];  // buf[0] = caller's grid, buf[1] = scratch
+  int nx, ny, nz;
+  int cs, kr, ntx, seg, nseg;           // 2D geometry
+  int csx, csy, krx, kry, nty;          // 3D geometry (ntx shared)
+  int flag_off;
+  int aligned;
+  DevCoef cf;
+};
+
+struct BItem {
+  int g, p, tile, keff;
+};
+
+__device__ __forceinline__ void wait_flag(const int* f, int want) {
+  while (ld_acquire(f) < want) __builtin_amdgcn_s_sleep(2);
+}
+
+__global__ __launch_bounds__(64) void batched2d_kernel(const BGrid* __restrict__ grids, const BItem* __restrict__ items,
+                                                       int nitems, int* counter, int* flags) {
+  __shared__ int sh;
+  for (;;) {
+    if (threadIdx.x == 0) sh = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = sh;
+    __syncthreads();
+    if (it >= nitems) break;
+    const BItem w = items[it];
+    const BGrid& g = grids[w.g];
+    const int tx = w.tile % g.ntx, ty = w.tile / g.ntx;
+    if (threadIdx.x == 0 && w.p > 0) {
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int x = tx + dx, y = ty + dy;
+          if (x < 0 || y < 0 || x >= g.ntx || y >= g.nseg) continue;
+          wait_flag(flags + g.flag_off + y * g.ntx + x, w.p);
+        }
+    }
+    __syncthreads();
+    Tb2dArgs a;
+    a.src = g.buf[w.p & 1];
+    a.dst = g.buf[(w.p + 1) & 1];
+    a.power = nullptr;
+    a.gp = nullptr;
+    a.nx = g.nx; a.ny = g.ny; a.keff = w.keff;
+    a.cs = g.cs; a.kr = g.kr; a.ntx = g.ntx; a.seg = g.seg; a.nseg = g.nseg;
+    a.aligned = g.aligned;
+    a.cf = g.cf;
+    {
+      Tb2dTile<kBatchK2, kTb2dV, false, false, false, false> t(a, threadIdx.x, nullptr);
+      t.process(w.tile);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      st_release(flags + g.flag_off + w.tile, w.p + 1);
+    }
+  }
+}
+
+__global__ __launch_bounds__(64 * kTb3dNW) void batched3d_kernel(const BGrid* __restrict__ grids,
+                                                                 const BItem* __restrict__ items, int nitems,
+                                                                 int* counter, int* flags) {
+  __shared__ __align__(16) float hal[2 * kBatchK3 * kTb3dNW * 2 * 64 * kTb3dV];
+  __shared__ int sh;
+  for (;;) {
+    if (threadIdx.x == 0) sh = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = sh;
+    __syncthreads();
+    if (it >= nitems) break;
+    const BItem w = items[it];
+    const BGrid& g = grids[w.g];
+    const int tx = w.tile % g.ntx, ty = w.tile / g.ntx;
+    if (threadIdx.x == 0 && w.p > 0) {
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int x = tx + dx, y = ty + dy;
+          if (x < 0 || y < 0 || x >= g.ntx || y >= g.nty) continue;
+          wait_flag(flags + g.flag_off + y * g.ntx + x, w.p);
+        }
+    }
+    __syncthreads();
+    Tb3dArgs a;
+    a.src = g.buf[w.p & 1];
+    a.dst = g.buf[(w.p + 1) & 1];
+    a.power = nullptr;
+    a.gp = nullptr;
+    a.nx = g.nx; a.ny = g.ny; a.nz = g.nz; a.keff = w.keff;
+    a.csx = g.csx; a.csy = g.csy; a.krx = g.krx; a.kry = g.kry; a.ntx = g.ntx; a.nty = g.nty;
+    a.segz = g.nz; a.nsegz = 1;
+    a.aligned = g.aligned;
+    a.cf = g.cf;
+    {
+      Tb3dTile<kBatchK3, kTb3dV, kTb3dR, kTb3dNW, false, false, false, false> t(a, threadIdx.x & 63, threadIdx.x >> 6,
+                                                                                 hal);
+      t.process(w.tile);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      st_release(flags + g.flag_off + w.tile, w.p + 1);
+    }
+  }
+}
+
+__global__ void reset_kernel(int* flags, int nflags, int* counters) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nflags) flags[i] = 0;
+  if (i < 2) counters[i] = 0;
+}
+
+}  // namespace
+
+struct stencil_batch_s {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::vector<stencil_batch_item_t> items;  // what was captured
+  std::vector<float*> scratch;
+  BGrid* d_grids = nullptr;
+  BItem* d_items2 = nullptr;
+  BItem* d_items3 = nullptr;
+  int* d_flags = nullptr;
+  int* d_counters = nullptr;
+  int n2 = 0, n3 = 0, nflags = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+using namespace stn;
+
+namespace {
+
+void release(stencil_batch_s* b) {
+  if (!b) return;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  for (float* s : b->scratch) hipFree(s);
+  hipFree(b->d_grids);
+  hipFree(b->d_items2);
+  hipFree(b->d_items3);
+  hipFree(b->d_flags);
+  hipFree(b->d_counters);
+  delete b;
+}
+
+bool same_items(const stencil_batch_s* b, int n, const stencil_batch_item_t* items) {
+  if ((int)b->items.size() != n) return false;
+  for (int i = 0; i < n; ++i) {
+    const stencil_batch_item_t& x = b->items[i];
+    const stencil_batch_item_t& y = items[i];
+    if (x.form != y.form || x.ndim != y.ndim || x.nx != y.nx || x.ny != y.ny || x.nz != y.nz || x.grid != y.grid ||
+        x.T != y.T || std::memcmp(&x.coeffs, &y.coeffs, sizeof(x.coeffs)) != 0)
+      return false;
+  }
+  return true;
+}
+
+// Steps of each pass: an even number of passes of at most kcap steps (0 passes when T == 0).
+std::vector<int> even_split(int T, int kcap) {
+  std::vector<int> v;
+  if (T <= 0) return v;
+  int P = (T + kcap - 1) / kcap;
+  if (P % 2) ++P;
+  const int base = T / P, rem = T % P;
+  for (int i = 0; i < P; ++i) v.push_back(base + (i < rem ? 1 : 0));
+  return v;
+}
+
+stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t stream, stencil_batch_s** out) {
+  stencil_batch_s* b = new stencil_batch_s();
+  b->stream = stream;
+  hipGetDevice(&b->device);
+  b->items.assign(items, items + n);
+  std::vector<BGrid> grids(n);
+  std::vector<std::vector<int>> steps(n);
+  std::vector<int> ntiles(n);
+  int nflags = 0;
+  int maxP = 0;
+  for (int i = 0; i < n; ++i) {
+    const stencil_batch_item_t& it = items[i];
+    BGrid& g = grids[i];
+    std::memset(&g, 0, sizeof(g));
+    g.nx = it.nx; g.ny = it.ny; g.nz = it.ndim == 3 ? it.nz : 1;
+    g.cf = dev_coef(it.coeffs, false);
+    const size_t cells = (size_t)g.nx * g.ny * g.nz;
+    float* s = nullptr;
+    if (hipMalloc(&s, cells * sizeof(float)) != hipSuccess) {
+      hipGetLastError();
+      release(b);
+      return fail(STENCIL_ERR_OUT_OF_MEMORY, "batch scratch allocation failed");
+    }
+    b->scratch.push_back(s);
+    g.buf[0] = it.grid;
+    g.buf[1] = s;
+    // temporal degree per grid from the cost model (tile shape fixed by the kernel)
+    if (it.ndim == 2) {
+      double best = 1e300;
+      int bestk = kBatchK2;
+      for (int k : {4, 8, 12, 16}) {
+        const int seg = pick_seg2d(kBatchK2, g.nx, g.ny, 8);
+        Geom2D gg = geom2d(kBatchK2, g.nx, g.ny, seg);
+        gg.K = k;  // price k fused steps on the fixed window
+        const double t = model_time_2d(gg, g.nx, g.ny, it.T, false, false);
+        if (t < best) { best = t; bestk = k; }
+      }
+      const int seg = std::max(pick_seg2d(kBatchK2, g.nx, g.ny, 8), kBatchK2);
+      const Geom2D gg = geom2d(kBatchK2, g.nx, g.ny, seg);
+      g.cs = gg.cs; g.kr = gg.kr; g.ntx = gg.ntx; g.seg = gg.seg; g.nseg = gg.nseg;
+      g.aligned = ((g.nx & 3) == 0) && ((reinterpret_cast<uintptr_t>(g.buf[0]) | reinterpret_cast<uintptr_t>(s)) & 15) == 0;
+      ntiles[i] = gg.ntx * gg.nseg;
+      steps[i] = even_split(it.T, bestk);
+    } else {
+      const Geom3D gg = geom3d(kBatchK3, false, g.nx, g.ny, g.nz, g.nz);
+      g.csx = gg.csx; g.csy = gg.csy; g.krx = gg.krx; g.kry = gg.kry; g.ntx = gg.ntx; g.nty = gg.nty;
+      g.aligned = ((g.nx & 1) == 0) && ((reinterpret_cast<uintptr_t>(g.buf[0]) | reinterpret_cast<uintptr_t>(s)) & 7) == 0;
+      ntiles[i] = gg.ntx * gg.nty;
+      steps[i] = even_split(it.T, kBatchK3);
+    }
+    g.flag_off = nflags;
+    nflags += ntiles[i];
+    maxP = std::max(maxP, (int)steps[i].size());
+  }
+  std::vector<BItem> it2, it3;
+  for (int p = 0; p < maxP; ++p)
+    for (int i = 0; i < n; ++i) {
+      if (p >= (int)steps[i].size()) continue;
+      std::vector<BItem>& dst = items[i].ndim == 2 ? it2 : it3;
+      for (int t = 0; t < ntiles[i]; ++t) dst.push_back({i, p, t, steps[i][p]});
+    }
+  b->n2 = (int)it2.size();
+  b->n3 = (int)it3.size();
+  b->nflags = nflags;
+  hipError_t e = hipSuccess;
+  e = hipMalloc(&b->d_grids, sizeof(BGrid) * std::max(1, n));
+  if (e == hipSuccess) e = hipMalloc(&b->d_items2, sizeof(BItem) * std::max(1, b->n2));
+  if (e == hipSuccess) e = hipMalloc(&b->d_items3, sizeof(BItem) * std::max(1, b->n3));
+  if (e == hipSuccess) e = hipMalloc(&b->d_flags, sizeof(int) * std::max(1, nflags));
+  if (e == hipSuccess) e = hipMalloc(&b->d_counters, sizeof(int) * 2);
+  if (e == hipSuccess && n) e = hipMemcpy(b->d_grids, grids.data(), sizeof(BGrid) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess && b->n2) e = hipMemcpy(b->d_items2, it2.data(), sizeof(BItem) * b->n2, hipMemcpyHostToDevice);
+  if (e == hipSuccess && b->n3) e = hipMemcpy(b->d_items3, it3.data(), sizeof(BItem) * b->n3, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    stencil_status_t st = hip_fail(e, "batch setup");
+    release(b);
+    return st;
+  }
+  // persistent grid sizes: resident capacity of the device
+  const DeviceInfo& d = device_info();
+  int occ2 = 1, occ3 = 1;
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, batched2d_kernel, 64, 0);
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ3, batched3d_kernel, 64 * kTb3dNW, 0);
+  const int g2 = std::max(1, std::min(b->n2, d.cus * std::max(1, occ2)));
+  const int g3 = std::max(1, std::min(b->n3, d.cus * std::max(1, occ3)));
+  // capture: reset flags/counters, then the two persistent kernels
+  hipStream_t cs = nullptr;
+  e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const int nr = std::max(nflags, 2);
+    hipLaunchKernelGGL(reset_kernel, dim3((nr + 255) / 256), dim3(256), 0, cs, b->d_flags, nflags, b->d_counters);
+    if (b->n2)
+      hipLaunchKernelGGL(batched2d_kernel, dim3(g2), dim3(64), 0, cs, b->d_grids, b->d_items2, b->n2, b->d_counters,
+                         b->d_flags);
+    if (b->n3)
+      hipLaunchKernelGGL(batched3d_kernel, dim3(g3), dim3(64 * kTb3dNW), 0, cs, b->d_grids, b->d_items3, b->n3,
+                         b->d_counters + 1, b->d_flags);
+    e = hipStreamEndCapture(cs, &b->graph);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (cs) hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    stencil_status_t st = hip_fail(e, "graph capture");
+    release(b);
+    return st;
+  }
+  if (log_enabled())
+    std::fprintf(stderr, "[stencil] batch: %d grids, %d 2D items (%d WGs), %d 3D items (%d WGs)\n", n, b->n2, g2,
+                 b->n3, g3);
+  *out = b;
+  return STENCIL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+stencil_status_t stencil_run_batched(int n, const stencil_batch_item_t* items, void* hip_stream,
+                                     stencil_batch_t* graph_cache) {
+  if (n < 0 || (n > 0 && !items)) return fail(STENCIL_ERR_INVALID_ARG, "invalid item list");
+  for (int i = 0; i < n; ++i) {
+    const stencil_batch_item_t& it = items[i];
+    if (it.form != STENCIL_DIFFUSION)
+      return fail(it.form == STENCIL_HOTSPOT ? STENCIL_ERR_UNSUPPORTED : STENCIL_ERR_INVALID_ARG,
+                  "batched launch supports the diffusion form");
+    if ((it.ndim != 2 && it.ndim != 3) || it.nx < 1 || it.ny < 1 || it.nz < 1 || (it.ndim == 2 && it.nz != 1))
+      return fail(STENCIL_ERR_INVALID_ARG, "item " + std::to_string(i) + ": bad dimensions");
+    if (!it.grid || (reinterpret_cast<uintptr_t>(it.grid) & 3))
+      return fail(STENCIL_ERR_INVALID_ARG, "item " + std::to_string(i) + ": grid NULL or misaligned");
+    if (it.T < 0) return fail(STENCIL_ERR_INVALID_ARG, "item " + std::to_string(i) + ": T < 0");
+    if (!coeffs_finite(it.coeffs)) return fail(STENCIL_ERR_INVALID_ARG, "item " + std::to_string(i) + ": coefficients");
+    for (int j = 0; j < i; ++j)
+      if (items[j].grid == it.grid) return fail(STENCIL_ERR_INVALID_ARG, "items share a grid");
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  stencil_batch_s* b = nullptr;
+  if (graph_cache && *graph_cache) {
+    b = *graph_cache;
+    if (!same_items(b, n, items))
+      return fail(STENCIL_ERR_INVALID_ARG, "cached batch was built from different items");
+  } else {
+    stencil_status_t st = build(n, items, s, &b);
+    if (st != STENCIL_OK) return st;
+    if (graph_cache) *graph_cache = b;
+  }
+  hipError_t e = hipGraphLaunch(b->exec, s);
+  if (e != hipSuccess) {
+    stencil_status_t st = hip_fail(e, "hipGraphLaunch");
+    if (!graph_cache) {
+      hipStreamSynchronize(s);
+      release(b);
+    }
+    return st;
+  }
+  if (!graph_cache) {
+    e = hipStreamSynchronize(s);
+    release(b);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  }
+  return STENCIL_OK;
+}
+
+void stencil_batch_destroy(stencil_batch_t b) {
+  if (!b) return;
+  hipSetDevice(b->device);
+  hipStreamSynchronize(b->stream);
+  release(b);
+}
+
+}  // extern "C"

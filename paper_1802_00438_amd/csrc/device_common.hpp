@@ -1,0 +1,57 @@
+// device_common.hpp -- small device helpers shared by the gfx950 stencil kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// Weights as seen by a kernel.  The names give the *position* of the value each weight
+// multiplies (x-1, x+1, y-1, y+1, z-1, z+1), not a direction of flow:
+//   forward step (Table 2):   wx_m = cw, wx_p = ce, wy_m = cn, wy_p = cs, wz_m = cb, wz_p = ca
+//   transposed step (adjoint): wx_m = ce, wx_p = cw, wy_m = cs, wy_p = cn, wz_m = ca, wz_p = cb
+// kamb = c_amb * t_amb rounded once in FP32; cp multiplies the power map.
+struct DevCoef {
+  float c0, wx_m, wx_p, wy_m, wy_p, wz_m, wz_p, cp, kamb;
+};
+
+// The canonical evaluation order of one cell update: centre, x-1, x+1, y+1, y-1, z-1, z+1
+// (the term order of Table 2), every step an FP32 fused multiply-add.
+__device__ __forceinline__ float upd2(float c0, float c, float wxm, float xm, float wxp, float xp,
+                                      float wyp, float yp, float wym, float ym) {
+  float acc = c0 * c;
+  acc = __builtin_fmaf(wxm, xm, acc);
+  acc = __builtin_fmaf(wxp, xp, acc);
+  acc = __builtin_fmaf(wyp, yp, acc);
+  acc = __builtin_fmaf(wym, ym, acc);
+  return acc;
+}
+
+// Cross-lane moves inside one 64-wide wavefront through DPP (no LDS traffic):
+// from_lower(x) returns lane i-1's x on lane i, from_upper(x) lane i+1's x.  The end lanes
+// receive 0; they only ever hold halo columns whose values are never stored.
+__device__ __forceinline__ float from_lower(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
+                                                               0x138 /* wave_shr:1 */, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_upper(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
+                                                               0x130 /* wave_shl:1 */, 0xf, 0xf, true));
+}
+
+// gfx950 dispatches consecutive workgroup ids round-robin over its 8 XCDs, each with a
+// private L2.  Remap so that each XCD receives a contiguous run of logical tile ids (and
+// so shares the overlapping halo reads of neighbouring tiles in its own L2).  Bijective
+// on [0, n): the tail that does not fill all 8 XCDs evenly keeps its id.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int q = n >> 3;
+  if (b < (q << 3)) return (b & 7) * q + (b >> 3);
+  return b;
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Agent-scope acquire/release helpers for cross-workgroup flags (persistent kernels).
+__device__ __forceinline__ int ld_acquire(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}

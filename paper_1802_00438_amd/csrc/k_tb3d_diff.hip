@@ -1,0 +1,7 @@
+// Temporal-blocked 3D diffusion kernels (forward).
+#include "launch.hpp"
+#define C(K) case K: if (full) TB_LAUNCH3D(K, kTb3dR, kTb3dNW, false, false, false, true, a, s); \
+                     else TB_LAUNCH3D(K, kTb3dR, kTb3dNW, false, false, false, false, a, s);
+hipError_t launch_tb3d_diff(int K, bool full, const Tb3dArgs& a, hipStream_t s) {
+  switch (K) { C(1) C(2) C(3) C(4) default: return hipErrorInvalidValue; }
+}

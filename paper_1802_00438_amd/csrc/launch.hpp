@@ -1,0 +1,48 @@
+// launch.hpp -- internal interface between the host runtime and the kernel translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "tb2d.hpp"
+#include "tb3d.hpp"
+#include "plain.hpp"
+
+// Kernel mode: forward diffusion, forward hotspot, or transposed step (adjoint) without /
+// with grad_p accumulation.
+enum KMode { KM_DIFF = 0, KM_HOT = 1, KM_ADJ = 2, KM_ADJ_ACC = 3 };
+
+// Tile shapes of the temporal-blocked kernels.
+constexpr int kTb2dV = 4;                               // 256-column windows, one wave each
+constexpr int kTb3dV = 2, kTb3dR = 6, kTb3dNW = 8;       // forward: 128 x 48 x-y window, 512 threads
+constexpr int kTb3dAdjR = 4, kTb3dAdjNW = 8;            // adjoint: 128 x 32 window
+
+// Largest fused-step count instantiated per (dimensionality, mode); every k in
+// [1, max] is served by the smallest instantiated K >= k (levels past k forward their input).
+int tb_max_k(int ndim, KMode m);
+// Instantiated K values (ascending) for (ndim, mode); returns the count.
+int tb_instantiated(int ndim, KMode m, const int** ks);
+
+hipError_t launch_tb2d(int K, KMode m, bool full, const Tb2dArgs& a, hipStream_t s);
+hipError_t launch_tb3d(int K, KMode m, bool full, const Tb3dArgs& a, hipStream_t s);
+hipError_t launch_plain(KMode m, const PlainArgs& a, hipStream_t s);
+hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
+hipError_t launch_fill_int(int* p, size_t n, int v, hipStream_t s);
+
+// Per-mode launchers (one translation unit each).
+hipError_t launch_tb2d_diff(int K, bool full, const Tb2dArgs& a, hipStream_t s);
+hipError_t launch_tb2d_hot(int K, bool full, const Tb2dArgs& a, hipStream_t s);
+hipError_t launch_tb2d_adj(int K, bool acc, bool full, const Tb2dArgs& a, hipStream_t s);
+hipError_t launch_tb3d_diff(int K, bool full, const Tb3dArgs& a, hipStream_t s);
+hipError_t launch_tb3d_hot(int K, bool full, const Tb3dArgs& a, hipStream_t s);
+hipError_t launch_tb3d_adj(int K, bool acc, bool full, const Tb3dArgs& a, hipStream_t s);
+
+#define TB_LAUNCH2D(K, HOT, ADJ, ACC, FULL, a, s)                                                       \
+  do {                                                                                                  \
+    hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL>), dim3((a).ntx * (a).nseg), dim3(64), \
+                       0, s, a);                                                                        \
+    return hipGetLastError();                                                                           \
+  } while (0)
+#define TB_LAUNCH3D(K, R, NW, HOT, ADJ, ACC, FULL, a, s)                                               \
+  do {                                                                                                  \
+    hipLaunchKernelGGL((tb3d_kernel<K, kTb3dV, R, NW, HOT, ADJ, ACC, FULL>),                           \
+                       dim3((a).ntx * (a).nty * (a).nsegz), dim3(64 * NW), 0, s, a);                    \
+    return hipGetLastError();                                                                           \
+  } while (0)

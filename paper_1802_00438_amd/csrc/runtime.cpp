@@ -1,0 +1,751 @@
+// runtime.cpp -- plan, pass scheduler, cost model, auto-tuner and the C ABI of stencil.h.
+//
+// Pass scheduling (paper Section 3.2, Eq. 8): T steps run as ceil(T/k) passes; each pass reads
+// one buffer and writes the other (Section 2.1 ping-pong).  A pass with fewer than k steps
+// runs the same kernel with its surplus levels forwarding their input.  The buffer roles are
+// arranged so that the last pass writes the caller's buffer; when the pass count is odd the
+// input is first copied to the plan scratch.
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+namespace stn {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+stencil_status_t fail(stencil_status_t st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+stencil_status_t hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? STENCIL_ERR_OUT_OF_MEMORY : STENCIL_ERR_HIP;
+}
+bool env_flag(const char* name) {
+  const char* v = std::getenv(name);
+  return v && *v && std::strcmp(v, "0") != 0;
+}
+bool log_enabled() { return env_flag("STENCIL_LOG"); }
+
+const DeviceInfo& device_info() {
+  static DeviceInfo info;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) {
+      if (p.multiProcessorCount > 0) info.cus = p.multiProcessorCount;
+      const double clk = p.clockRate > 0 ? p.clockRate * 1e3 : 2.4e9;
+      info.valu_lane_ops = (double)info.cus * 4 * 16 * clk;
+    }
+  });
+  return info;
+}
+
+static int round_up(int v, int m) { return (v + m - 1) / m * m; }
+static int floor_to(int v, int m) { return v / m * m; }
+static int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+Geom2D geom2d(int K, int nx, int ny, int seg) {
+  Geom2D g;
+  g.K = K;
+  const int W = 64 * kTb2dV;
+  g.kr = round_up(K, 4);
+  g.cs = floor_to(W - K - g.kr, 4);
+  g.ntx = ceil_div(nx, g.cs);
+  g.seg = std::max(1, std::min(seg, ny));
+  g.nseg = ceil_div(ny, g.seg);
+  return g;
+}
+
+Geom3D geom3d(int K, bool adj, int nx, int ny, int nz, int segz) {
+  Geom3D g;
+  g.K = K;
+  const int WX = 64 * kTb3dV;
+  const int WY = (adj ? kTb3dAdjR * kTb3dAdjNW : kTb3dR * kTb3dNW);
+  g.krx = round_up(K, 2);
+  g.csx = floor_to(WX - K - g.krx, 2);
+  g.kry = K;
+  g.csy = WY - 2 * K;
+  g.ntx = ceil_div(nx, g.csx);
+  g.nty = ceil_div(ny, g.csy);
+  g.segz = std::max(1, std::min(segz, nz));
+  g.nsegz = ceil_div(nz, g.segz);
+  return g;
+}
+
+// The paper's model (Eq. 6-8) counts external-memory cells including the overlapped halos;
+// on the GPU a pass also costs VALU time for the redundantly computed halo cells, so a pass is
+// priced as max(memory, arithmetic) after wave quantisation, plus a launch overhead.
+double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj) {
+  const DeviceInfo& d = device_info();
+  const int W = 64 * kTb2dV;
+  const long passes = (T + g.K - 1) / g.K;
+  const double tiles = (double)g.ntx * g.nseg;
+  const double rows = (double)g.seg + 2.0 * g.K;  // streamed rows per tile
+  const int nread = (hot && !adj) ? 2 : 1;
+  const double bytes = tiles * rows * W * 4.0 * nread + (double)nx * ny * 4.0 * (adj && hot ? 3 : 1);
+  const double ops_per_cell = (adj ? 5.5 : 5.5) + (hot && !adj ? 1.25 : 0.0);
+  const double ops = tiles * rows * W * g.K * ops_per_cell;
+  const double slots = (double)d.cus * 4 * 2;  // two 64-lane waves per SIMD
+  const double rounds = std::ceil(tiles / slots);
+  const double quant = tiles / (rounds * slots);
+  const double tm = bytes / (d.hbm_gbs * 1e9 * d.achievable_frac);
+  const double ta = ops / (d.valu_lane_ops * 0.8) / quant;
+  return passes * (std::max(tm, ta) + 4e-6);
+}
+
+double model_time_3d(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj) {
+  const DeviceInfo& d = device_info();
+  const int WX = 64 * kTb3dV;
+  const int WY = adj ? kTb3dAdjR * kTb3dAdjNW : kTb3dR * kTb3dNW;
+  const long passes = (T + g.K - 1) / g.K;
+  const double tiles = (double)g.ntx * g.nty * g.nsegz;
+  const double planes = (double)g.segz + 2.0 * g.K;
+  const int nread = (hot && !adj) ? 2 : 1;
+  const double bytes = tiles * planes * WX * WY * 4.0 * nread + (double)nx * ny * nz * 4.0 * (adj && hot ? 3 : 1);
+  const double ops = tiles * planes * WX * WY * g.K * (7.5 + (hot && !adj ? 2.0 : 0.0));
+  const double slots = (double)d.cus * 1;  // one 512-thread workgroup per CU at these register counts
+  const double rounds = std::ceil(tiles / slots);
+  const double quant = tiles / (rounds * slots);
+  const double tm = bytes / (d.hbm_gbs * 1e9 * d.achievable_frac);
+  const double ta = ops / (d.valu_lane_ops * 0.6) / quant;
+  return passes * (std::max(tm, ta) + 4e-6);
+}
+
+int pick_seg2d(int K, int nx, int ny, int waves_per_cu) {
+  const DeviceInfo& d = device_info();
+  const Geom2D g0 = geom2d(K, nx, ny, ny);
+  const long slots = (long)d.cus * waves_per_cu;
+  // smallest number of y-tiles that fills the device at least once, rounded so the last round
+  // of waves is as full as possible; never segments shorter than 4K rows where avoidable
+  int best_seg = ny;
+  double best = 1e300;
+  for (int nseg = 1; nseg <= std::max(1, ny / std::max(1, 2 * K)); ++nseg) {
+    const int seg = ceil_div(ny, nseg);
+    const int real = ceil_div(ny, seg);
+    const double tiles = (double)g0.ntx * real;
+    const double rounds = std::ceil(tiles / slots);
+    const double per_tile = seg + 2.0 * K + 2.0;  // streamed rows incl. pipeline fill
+    const double cost = rounds * per_tile;        // time ~ rounds x rows per wave
+    if (cost < best * 0.999) {
+      best = cost;
+      best_seg = seg;
+    }
+    if (tiles > 64.0 * slots) break;
+  }
+  return best_seg;
+}
+
+int pick_segz3d(int K, bool adj, int nx, int ny, int nz, int wgs_per_cu) {
+  const DeviceInfo& d = device_info();
+  const Geom3D g0 = geom3d(K, adj, nx, ny, nz, nz);
+  const long slots = (long)d.cus * wgs_per_cu;
+  int best = nz;
+  double bestc = 1e300;
+  for (int ns = 1; ns <= std::max(1, nz / std::max(1, 2 * K)); ++ns) {
+    const int segz = ceil_div(nz, ns);
+    const int real = ceil_div(nz, segz);
+    const double tiles = (double)g0.ntx * g0.nty * real;
+    const double rounds = std::ceil(tiles / slots);
+    const double cost = rounds * (segz + 2.0 * K + 2.0);
+    if (cost < bestc * 0.999) {
+      bestc = cost;
+      best = segz;
+    }
+    if (tiles > 64.0 * slots) break;
+  }
+  return best;
+}
+
+DevCoef dev_coef(const stencil_coeffs_t& c, bool adjoint) {
+  DevCoef d;
+  d.c0 = c.cc;
+  if (!adjoint) {
+    d.wx_m = c.cw; d.wx_p = c.ce; d.wy_m = c.cn; d.wy_p = c.cs; d.wz_m = c.cb; d.wz_p = c.ca;
+  } else {
+    d.wx_m = c.ce; d.wx_p = c.cw; d.wy_m = c.cs; d.wy_p = c.cn; d.wz_m = c.ca; d.wz_p = c.cb;
+  }
+  d.cp = c.cp;
+  d.kamb = c.c_amb * c.t_amb;  // rounded once in FP32
+  return d;
+}
+
+bool coeffs_finite(const stencil_coeffs_t& c) {
+  const float v[] = {c.cc, c.cw, c.ce, c.cn, c.cs, c.cb, c.ca, c.cp, c.c_amb, c.t_amb};
+  for (float x : v)
+    if (!std::isfinite(x)) return false;
+  return true;
+}
+
+}  // namespace stn
+
+using namespace stn;
+
+namespace {
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// Fault injection for tests of the error paths: STENCIL_FAULT_INJECT=<pass index> makes the
+// pass scheduler report a HIP error before launching that pass (no device work is skipped
+// silently: the call returns STENCIL_ERR_HIP).
+int fault_pass() {
+  const char* v = std::getenv("STENCIL_FAULT_INJECT");
+  return v && *v ? std::atoi(v) : -1;
+}
+
+KMode fwd_mode(const stencil_plan_s* p) { return p->form == STENCIL_HOTSPOT ? KM_HOT : KM_DIFF; }
+
+// Smallest instantiated K >= k.
+int inst_k_for(int ndim, KMode m, int k) {
+  const int* ks;
+  const int n = tb_instantiated(ndim, m, &ks);
+  for (int i = 0; i < n; ++i)
+    if (ks[i] >= k) return ks[i];
+  return ks[n - 1];
+}
+
+// One pass of keff fused steps from src to dst.
+hipError_t run_pass(const stencil_plan_s* p, KMode m, int K, int keff, const float* src, float* dst,
+                    const float* power, float* gp, const DevCoef& cf) {
+  const bool full = (keff == K);
+  if (p->ndim == 2) {
+    const Geom2D g = geom2d(K, p->nx, p->ny, p->tuning.seg_len);
+    Tb2dArgs a;
+    a.src = src; a.dst = dst; a.power = power; a.gp = gp;
+    a.nx = p->nx; a.ny = p->ny; a.keff = keff;
+    a.cs = g.cs; a.kr = g.kr; a.ntx = g.ntx; a.seg = g.seg; a.nseg = g.nseg;
+    a.aligned = ((p->nx & 3) == 0) && aligned16(src) && aligned16(dst) && (!power || aligned16(power)) ? 1 : 0;
+    a.cf = cf;
+    return launch_tb2d(K, m, full, a, p->stream);
+  }
+  const bool adj = (m == KM_ADJ || m == KM_ADJ_ACC);
+  const Geom3D g = geom3d(K, adj, p->nx, p->ny, p->nz, p->tuning.seg_len);
+  Tb3dArgs a;
+  a.src = src; a.dst = dst; a.power = power; a.gp = gp;
+  a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.keff = keff;
+  a.csx = g.csx; a.csy = g.csy; a.krx = g.krx; a.kry = g.kry; a.ntx = g.ntx; a.nty = g.nty;
+  a.segz = g.segz; a.nsegz = g.nsegz;
+  a.aligned = ((p->nx & 1) == 0) && ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 7) == 0 ? 1 : 0;
+  a.cf = cf;
+  return launch_tb3d(K, m, full, a, p->stream);
+}
+
+hipError_t run_plain_step(const stencil_plan_s* p, KMode m, const float* src, float* dst, const float* power,
+                          float* gp, const DevCoef& cf) {
+  PlainArgs a;
+  a.src = src; a.dst = dst; a.power = power; a.gp = gp;
+  a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.ndim = p->ndim;
+  a.chunks = (p->nx + 1023) / 1024;
+  a.vec = ((p->nx & 3) == 0) && aligned16(src) && aligned16(dst) && (!power || aligned16(power)) &&
+          (!gp || aligned16(gp)) ? 1 : 0;
+  a.cf = cf;
+  return launch_plain(m, a, p->stream);
+}
+
+// Split T steps into passes of at most kmax steps (the first passes full).
+std::vector<int> split_steps(int T, int kmax) {
+  std::vector<int> v;
+  for (int done = 0; done < T; done += kmax) v.push_back(std::min(kmax, T - done));
+  return v;
+}
+
+// Run the pass sequence `steps` starting from `first_src` (holding x_0), ending in `out`.
+// `alt` is the second ping-pong buffer.  If first_src == out and the pass count is odd, the
+// input is copied to alt first.  gp (adjoint accumulation) is passed to every pass.
+stencil_status_t run_sequence(stencil_plan_s* p, KMode m, bool plain, int K, const std::vector<int>& steps,
+                              const float* first_src, float* out, float* alt, const float* power, float* gp,
+                              const DevCoef& cf, int* pass_counter) {
+  const size_t bytes = p->cells * sizeof(float);
+  const int P = (int)steps.size();
+  if (P == 0) {
+    if (first_src != out) {
+      hipError_t e = hipMemcpyAsync(out, first_src, bytes, hipMemcpyDeviceToDevice, p->stream);
+      if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    }
+    return STENCIL_OK;
+  }
+  const float* src = first_src;
+  // Pass i writes `out` when (P - 1 - i) is even.
+  if (first_src == out && (P % 2) == 1) {
+    hipError_t e = hipMemcpyAsync(alt, out, bytes, hipMemcpyDeviceToDevice, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    src = alt;
+  }
+  const int fi = fault_pass();
+  for (int i = 0; i < P; ++i) {
+    float* dst = ((P - 1 - i) % 2 == 0) ? out : alt;
+    if (dst == src) return fail(STENCIL_ERR_INTERNAL, "pass scheduler produced an in-place pass");
+    if (fi >= 0 && *pass_counter == fi) {
+      ++*pass_counter;
+      return fail(STENCIL_ERR_HIP, "injected fault (STENCIL_FAULT_INJECT) at pass " + std::to_string(fi));
+    }
+    ++*pass_counter;
+    hipError_t e;
+    if (plain) {
+      e = run_plain_step(p, m, src, dst, power, gp, cf);  // plain passes are single steps
+    } else {
+      e = run_pass(p, m, K, steps[i], src, dst, power, gp, cf);
+    }
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    src = dst;
+  }
+  return STENCIL_OK;
+}
+
+// Kernel/K selection for a forward or adjoint run of the plan.
+void resolve_k(const stencil_plan_s* p, KMode m, int* K, bool* plain) {
+  *plain = (p->tuning.variant == 1);
+  int k = p->tuning.k > 0 ? p->tuning.k : 1;
+  const int kmax = tb_max_k(p->ndim, m);
+  if (k > kmax) k = kmax;
+  *K = inst_k_for(p->ndim, m, k);
+}
+
+struct TuneKey {
+  int form, ndim, nx, ny, nz;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(form, ndim, nx, ny, nz) < std::tie(o.form, o.ndim, o.nx, o.ny, o.nz);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, stencil_tuning_t> g_tune_cache;
+
+// Model-ranked candidates, the best few timed on scratch memory.
+stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out) {
+  const TuneKey key{p->form, p->ndim, p->nx, p->ny, p->nz};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      *out = it->second;
+      return STENCIL_OK;
+    }
+  }
+  const bool hot = p->form == STENCIL_HOTSPOT;
+  const KMode m = hot ? KM_HOT : KM_DIFF;
+  const long Tref = 240;  // a step count divisible by every instantiated k
+  struct Cand {
+    int K, seg;
+    double model;
+  };
+  std::vector<Cand> cands;
+  const int* ks;
+  const int nk = tb_instantiated(p->ndim, m, &ks);
+  for (int i = 0; i < nk; ++i) {
+    const int K = ks[i];
+    if (p->ndim == 2) {
+      for (int wpc : {4, 8, 12, 16}) {
+        const int seg = pick_seg2d(K, p->nx, p->ny, wpc);
+        const Geom2D g = geom2d(K, p->nx, p->ny, seg);
+        cands.push_back({K, seg, model_time_2d(g, p->nx, p->ny, Tref, hot, false)});
+      }
+    } else {
+      for (int wpc : {1, 2, 4}) {
+        const int segz = pick_segz3d(K, false, p->nx, p->ny, p->nz, wpc);
+        const Geom3D g = geom3d(K, false, p->nx, p->ny, p->nz, segz);
+        cands.push_back({K, segz, model_time_3d(g, p->nx, p->ny, p->nz, Tref, hot, false)});
+      }
+    }
+  }
+  std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.model < b.model; });
+  // remove duplicates
+  std::vector<Cand> uniq;
+  for (const Cand& c : cands) {
+    bool dup = false;
+    for (const Cand& u : uniq) dup |= (u.K == c.K && u.seg == c.seg);
+    if (!dup) uniq.push_back(c);
+  }
+  stencil_tuning_t best = p->tuning;
+  best.variant = 2;
+  best.k = uniq[0].K;
+  best.seg_len = uniq[0].seg;
+  const bool timed = !env_flag("STENCIL_MODEL_ONLY") && p->cells >= (size_t)1 << 16;
+  if (timed) {
+    // time the top candidates: two passes each on scratch + a temporary buffer
+    float* tmp = nullptr;
+    if (hipMalloc(&tmp, p->cells * sizeof(float)) == hipSuccess) {
+      launch_fill(tmp, p->cells, 0.5f, p->stream);
+      launch_fill(p->scratch, p->cells, 0.5f, p->stream);
+      stencil_coeffs_t c{};
+      c.cc = 0.5f; c.cw = c.ce = c.cn = c.cs = 0.125f; c.cb = c.ca = 0.0f;
+      const DevCoef cf = dev_coef(c, false);
+      hipEvent_t e0, e1;
+      hipEventCreate(&e0);
+      hipEventCreate(&e1);
+      double best_rate = 0;
+      const int ntop = std::min<int>(5, (int)uniq.size());
+      for (int i = 0; i < ntop; ++i) {
+        stencil_plan_s q = *p;
+        q.tuning.k = uniq[i].K;
+        q.tuning.seg_len = uniq[i].seg;
+        // warm-up pass, then two timed passes
+        run_pass(&q, m, uniq[i].K, uniq[i].K, tmp, p->scratch, hot ? tmp : nullptr, nullptr, cf);
+        hipEventRecord(e0, p->stream);
+        run_pass(&q, m, uniq[i].K, uniq[i].K, p->scratch, tmp, hot ? p->scratch : nullptr, nullptr, cf);
+        run_pass(&q, m, uniq[i].K, uniq[i].K, tmp, p->scratch, hot ? tmp : nullptr, nullptr, cf);
+        hipEventRecord(e1, p->stream);
+        hipEventSynchronize(e1);
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        const double rate = 2.0 * uniq[i].K * (double)p->cells / (ms * 1e-3);  // cell updates / s
+        if (log_enabled())
+          std::fprintf(stderr, "[stencil] tune K=%d seg=%d model=%.3g ms measured=%.1f GCell/s\n", uniq[i].K,
+                       uniq[i].seg, uniq[i].model * 1e3, rate * 1e-9);
+        if (rate > best_rate) {
+          best_rate = rate;
+          best.k = uniq[i].K;
+          best.seg_len = uniq[i].seg;
+        }
+      }
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      hipStreamSynchronize(p->stream);
+      hipFree(tmp);
+      hipGetLastError();
+    }
+  }
+  if (log_enabled())
+    std::fprintf(stderr, "[stencil] plan form=%d ndim=%d %dx%dx%d -> k=%d seg=%d\n", p->form, p->ndim, p->nx, p->ny,
+                 p->nz, best.k, best.seg_len);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
+  *out = best;
+  return STENCIL_OK;
+}
+
+stencil_status_t check_plan(stencil_plan_t plan) {
+  if (!plan) return fail(STENCIL_ERR_INVALID_ARG, "plan is NULL");
+  return STENCIL_OK;
+}
+
+stencil_status_t set_device(const stencil_plan_s* p) {
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return STENCIL_OK;
+}
+
+void free_ckpts(stencil_plan_s* p) {
+  for (float* c : p->ckpts) hipFree(c);
+  p->ckpts.clear();
+  p->ckpt_every = 0;
+  p->ckpt_T = -1;
+}
+
+// Forward with optional checkpoints; the work behind stencil_run and stencil_run_ckpt.
+stencil_status_t forward(stencil_plan_s* p, float* grid, const float* power, const stencil_coeffs_t* coeffs, int T,
+                         int ckpt_every, bool keep_ckpts) {
+  if (!grid) return fail(STENCIL_ERR_INVALID_ARG, "grid is NULL");
+  if (!coeffs) return fail(STENCIL_ERR_INVALID_ARG, "coeffs is NULL");
+  if (T < 0) return fail(STENCIL_ERR_INVALID_ARG, "T must be >= 0");
+  if (!coeffs_finite(*coeffs)) return fail(STENCIL_ERR_INVALID_ARG, "coefficients must be finite");
+  if (p->form == STENCIL_HOTSPOT && !power) return fail(STENCIL_ERR_INVALID_ARG, "hotspot needs a power map");
+  if ((reinterpret_cast<uintptr_t>(grid) & 3) || (power && (reinterpret_cast<uintptr_t>(power) & 3)))
+    return fail(STENCIL_ERR_INVALID_ARG, "buffers must be 4-byte aligned");
+  if (power == grid) return fail(STENCIL_ERR_INVALID_ARG, "power must not alias grid");
+  stencil_status_t st = set_device(p);
+  if (st != STENCIL_OK) return st;
+  const KMode m = fwd_mode(p);
+  const DevCoef cf = dev_coef(*coeffs, false);
+  const float* pw = (p->form == STENCIL_HOTSPOT) ? power : nullptr;
+  int K;
+  bool plain;
+  resolve_k(p, m, &K, &plain);
+  const int kpass = plain ? 1 : std::min(K, std::max(1, p->tuning.k));
+  int counter = 0;
+  if (!keep_ckpts) {
+    return run_sequence(p, m, plain, K, split_steps(T, kpass), grid, grid, p->scratch, pw, nullptr, cf, &counter);
+  }
+  // checkpointed run: x_{j*ce} saved before segment j; each segment starts from its checkpoint
+  if (ckpt_every <= 0) ckpt_every = std::max(1, (int)std::lround(std::sqrt((double)std::max(T, 1))));
+  const int nck = T > 0 ? (T - 1) / ckpt_every + 1 : 0;
+  if ((int)p->ckpts.size() != nck) free_ckpts(p);  // reuse the store when the count matches
+  for (int j = (int)p->ckpts.size(); j < nck; ++j) {
+    float* c = nullptr;
+    hipError_t e = hipMalloc(&c, p->cells * sizeof(float));
+    if (e != hipSuccess) {
+      free_ckpts(p);
+      hipGetLastError();
+      return fail(STENCIL_ERR_OUT_OF_MEMORY, "checkpoint allocation failed");
+    }
+    p->ckpts.push_back(c);
+  }
+  p->ckpt_every = ckpt_every;
+  p->ckpt_T = T;
+  for (int j = 0; j < nck; ++j) {
+    hipError_t e = hipMemcpyAsync(p->ckpts[j], grid, p->cells * sizeof(float), hipMemcpyDeviceToDevice, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+    const int seg_T = std::min(ckpt_every, T - j * ckpt_every);
+    // start from the checkpoint copy so no parity copy is needed
+    st = run_sequence(p, m, plain, K, split_steps(seg_T, kpass), p->ckpts[j], grid, p->scratch, pw, nullptr, cf,
+                      &counter);
+    if (st != STENCIL_OK) return st;
+  }
+  return STENCIL_OK;
+}
+
+}  // namespace
+
+// Device-side bitwise comparison used by the recompute check.
+hipError_t launch_count_mismatch(const float* a, const float* b, size_t n, int* counter, hipStream_t s);
+
+extern "C" {
+
+const char* stencil_status_string(stencil_status_t s) {
+  switch (s) {
+    case STENCIL_OK: return "STENCIL_OK";
+    case STENCIL_ERR_INVALID_ARG: return "STENCIL_ERR_INVALID_ARG";
+    case STENCIL_ERR_UNSUPPORTED: return "STENCIL_ERR_UNSUPPORTED";
+    case STENCIL_ERR_OUT_OF_MEMORY: return "STENCIL_ERR_OUT_OF_MEMORY";
+    case STENCIL_ERR_HIP: return "STENCIL_ERR_HIP";
+    case STENCIL_ERR_INTERNAL: return "STENCIL_ERR_INTERNAL";
+  }
+  return "STENCIL_ERR_UNKNOWN";
+}
+
+const char* stencil_last_error(void) { return g_last_error.c_str(); }
+
+stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int ndim, int nx, int ny, int nz,
+                                const stencil_tuning_t* tuning, void* hip_stream) {
+  if (!out) return fail(STENCIL_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (form != STENCIL_DIFFUSION && form != STENCIL_HOTSPOT) return fail(STENCIL_ERR_INVALID_ARG, "unknown form");
+  if (ndim != 2 && ndim != 3) return fail(STENCIL_ERR_INVALID_ARG, "ndim must be 2 or 3");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(STENCIL_ERR_INVALID_ARG, "grid dimensions must be >= 1");
+  if (ndim == 2 && nz != 1) return fail(STENCIL_ERR_INVALID_ARG, "2D grids need nz == 1");
+  const double cells = (double)nx * ny * nz;
+  if (cells > 9.0e18 / sizeof(float)) return fail(STENCIL_ERR_INVALID_ARG, "grid too large");
+  if ((long)nx * ny > 0x7fffffffL && ndim == 3) return fail(STENCIL_ERR_UNSUPPORTED, "plane larger than 2^31 cells");
+  if (tuning) {
+    if (tuning->variant < 0 || tuning->variant > 2 || tuning->k < 0 || tuning->vec < 0 || tuning->bsize_x < 0 ||
+        tuning->bsize_y < 0 || tuning->seg_len < 0)
+      return fail(STENCIL_ERR_INVALID_ARG, "tuning fields must be >= 0 (variant 0..2)");
+    if (tuning->vec != 0 && tuning->vec != (ndim == 2 ? kTb2dV : kTb3dV))
+      return fail(STENCIL_ERR_UNSUPPORTED, "vec is fixed by the kernel instantiation (2D: 4, 3D: 2)");
+  }
+  stencil_plan_s* p = new (std::nothrow) stencil_plan_s();
+  if (!p) return fail(STENCIL_ERR_OUT_OF_MEMORY, "host allocation failed");
+  p->form = form;
+  p->ndim = ndim;
+  p->nx = nx;
+  p->ny = ny;
+  p->nz = nz;
+  p->cells = (size_t)nx * ny * nz;
+  p->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  e = hipMalloc(&p->scratch, p->cells * sizeof(float));
+  if (e != hipSuccess) {
+    delete p;
+    hipGetLastError();
+    return fail(STENCIL_ERR_OUT_OF_MEMORY, "scratch allocation failed");
+  }
+  stencil_tuning_t t{};
+  if (tuning) t = *tuning;
+  p->tuning = t;
+  const KMode m = form == STENCIL_HOTSPOT ? KM_HOT : KM_DIFF;
+  if (t.variant == 1) {
+    p->tuning.k = 1;
+  } else if (t.k == 0 || t.seg_len == 0) {
+    stencil_tuning_t tuned;
+    if (t.k != 0) {
+      // k fixed by the caller: only the segment length is chosen
+      const int K = inst_k_for(ndim, m, std::min(t.k, tb_max_k(ndim, m)));
+      tuned = t;
+      tuned.k = std::min(t.k, tb_max_k(ndim, m));
+      tuned.seg_len = ndim == 2 ? pick_seg2d(K, nx, ny, 8) : pick_segz3d(K, false, nx, ny, nz, 1);
+    } else {
+      stencil_status_t st = autotune(p, &tuned);
+      if (st != STENCIL_OK) {
+        hipFree(p->scratch);
+        delete p;
+        return st;
+      }
+      if (t.seg_len != 0) tuned.seg_len = t.seg_len;
+    }
+    p->tuning = tuned;
+    p->tuning.variant = 2;
+  } else {
+    p->tuning.variant = 2;
+    p->tuning.k = std::min(t.k, tb_max_k(ndim, m));
+  }
+  p->tuning.vec = ndim == 2 ? kTb2dV : kTb3dV;
+  p->tuning.bsize_x = 64 * p->tuning.vec;
+  p->tuning.bsize_y = ndim == 2 ? 0 : kTb3dR * kTb3dNW;
+  *out = p;
+  return STENCIL_OK;
+}
+
+stencil_status_t stencil_get_tuning(stencil_plan_t plan, stencil_tuning_t* out) {
+  if (!plan || !out) return fail(STENCIL_ERR_INVALID_ARG, "NULL argument");
+  *out = plan->tuning;
+  return STENCIL_OK;
+}
+
+void stencil_destroy(stencil_plan_t plan) {
+  if (!plan) return;
+  hipSetDevice(plan->device);
+  hipStreamSynchronize(plan->stream);
+  free_ckpts(plan);
+  hipFree(plan->scratch);
+  hipFree(plan->verify_buf);
+  hipFree(plan->mismatch);
+  delete plan;
+}
+
+stencil_status_t stencil_run(stencil_plan_t plan, float* grid, const float* power, const stencil_coeffs_t* coeffs,
+                             int T) {
+  stencil_status_t st = check_plan(plan);
+  if (st != STENCIL_OK) return st;
+  return forward(plan, grid, power, coeffs, T, 0, false);
+}
+
+stencil_status_t stencil_run_ckpt(stencil_plan_t plan, float* grid, const float* power,
+                                  const stencil_coeffs_t* coeffs, int T, int ckpt_every) {
+  stencil_status_t st = check_plan(plan);
+  if (st != STENCIL_OK) return st;
+  if (ckpt_every < 0) return fail(STENCIL_ERR_INVALID_ARG, "ckpt_every must be >= 0");
+  return forward(plan, grid, power, coeffs, T, ckpt_every, true);
+}
+
+stencil_status_t stencil_adjoint(stencil_plan_t p, const float* cot, const float* power,
+                                 const stencil_coeffs_t* coeffs, int T, float* grad_x0, float* grad_power,
+                                 int recompute) {
+  stencil_status_t st = check_plan(p);
+  if (st != STENCIL_OK) return st;
+  if (!cot || !grad_x0) return fail(STENCIL_ERR_INVALID_ARG, "cotangent and grad_x0 are required");
+  if (!coeffs) return fail(STENCIL_ERR_INVALID_ARG, "coeffs is NULL");
+  if (T < 0) return fail(STENCIL_ERR_INVALID_ARG, "T must be >= 0");
+  if (!coeffs_finite(*coeffs)) return fail(STENCIL_ERR_INVALID_ARG, "coefficients must be finite");
+  if (grad_x0 == cot || grad_power == cot || (grad_power && grad_power == grad_x0))
+    return fail(STENCIL_ERR_INVALID_ARG, "outputs must not alias the cotangent or each other");
+  if (recompute != 0 && recompute != 1) return fail(STENCIL_ERR_INVALID_ARG, "recompute must be 0 or 1");
+  if (recompute) {
+    if (p->ckpt_T != T || p->ckpts.empty())
+      return fail(STENCIL_ERR_INVALID_ARG, "recompute needs checkpoints of a stencil_run_ckpt with the same T");
+    if (p->form == STENCIL_HOTSPOT && !power) return fail(STENCIL_ERR_INVALID_ARG, "recompute of hotspot needs power");
+  }
+  st = set_device(p);
+  if (st != STENCIL_OK) return st;
+  const bool hot = p->form == STENCIL_HOTSPOT;
+  float* gp = hot ? grad_power : nullptr;
+  const KMode m = gp ? KM_ADJ_ACC : KM_ADJ;
+  const DevCoef cf = dev_coef(*coeffs, true);
+  if (gp) {
+    hipError_t e = launch_fill(gp, p->cells, 0.0f, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "fill");
+  } else if (grad_power) {
+    hipError_t e = launch_fill(grad_power, p->cells, 0.0f, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "fill");
+  }
+  const bool plain = (p->tuning.variant == 1);
+  int K = inst_k_for(p->ndim, m, std::min(std::max(1, p->tuning.k), tb_max_k(p->ndim, m)));
+  const int kpass = plain ? 1 : K;
+  int counter = 0;
+  if (!recompute) {
+    return run_sequence(p, m, plain, K, split_steps(T, kpass), cot, grad_x0, p->scratch, nullptr, gp, cf, &counter);
+  }
+  // Segment-wise reverse sweep: for segment j (last to first) recompute x from checkpoint j,
+  // check it reproduces checkpoint j+1 bit for bit, then run the adjoint over the segment.
+  if (!p->verify_buf) {
+    hipError_t e = hipMalloc(&p->verify_buf, p->cells * sizeof(float));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    e = hipMalloc(&p->mismatch, sizeof(int));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+  }
+  hipError_t e = launch_fill_int(p->mismatch, 1, 0, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "fill");
+  const int ce = p->ckpt_every;
+  const int nck = (int)p->ckpts.size();
+  const KMode fm = fwd_mode(p);
+  const DevCoef fcf = dev_coef(*coeffs, false);
+  int Kf;
+  bool plainf;
+  resolve_k(p, fm, &Kf, &plainf);
+  const int kfp = plainf ? 1 : std::min(Kf, std::max(1, p->tuning.k));
+  const float* lam_src = cot;
+  for (int j = nck - 1; j >= 0; --j) {
+    const int seg_T = std::min(ce, T - j * ce);
+    // recompute the segment into verify_buf (scratch is the ping-pong partner)
+    st = run_sequence(p, fm, plainf, Kf, split_steps(seg_T, kfp), p->ckpts[j], p->verify_buf, p->scratch,
+                      hot ? power : nullptr, nullptr, fcf, &counter);
+    if (st != STENCIL_OK) return st;
+    if (j + 1 < nck) {
+      e = launch_count_mismatch(p->verify_buf, p->ckpts[j + 1], p->cells, p->mismatch, p->stream);
+      if (e != hipSuccess) return hip_fail(e, "mismatch kernel");
+    }
+    // adjoint over this segment: lam_src -> grad_x0 (ping-pong partner scratch)
+    st = run_sequence(p, m, plain, K, split_steps(seg_T, kpass), lam_src, grad_x0, p->scratch, nullptr, gp, cf,
+                      &counter);
+    if (st != STENCIL_OK) return st;
+    lam_src = grad_x0;
+  }
+  if (nck == 0) {
+    e = hipMemcpyAsync(grad_x0, cot, p->cells * sizeof(float), hipMemcpyDeviceToDevice, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  }
+  int mism = 0;
+  e = hipMemcpyAsync(&mism, p->mismatch, sizeof(int), hipMemcpyDeviceToHost, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (mism != 0)
+    return fail(STENCIL_ERR_INTERNAL, "recomputed segment differs from stored checkpoint in " + std::to_string(mism) +
+                                          " cells");
+  return STENCIL_OK;
+}
+
+stencil_status_t stencil_model_estimate(const stencil_model_params_t* q, stencil_model_result_t* r) {
+  if (!q || !r) return fail(STENCIL_ERR_INVALID_ARG, "NULL argument");
+  if ((q->ndim != 2 && q->ndim != 3) || q->rad < 1 || q->par_vec < 1 || q->par_time < 1 || q->f_max_hz <= 0 ||
+      q->size_cell < 1 || q->num_read < 0 || q->num_write < 0 || q->bsize_x < 1 || q->dim_x < 1 || q->dim_y < 1 ||
+      q->iter < 0 || q->th_max_gbs <= 0 || (q->ndim == 3 && (q->bsize_y < 1 || q->dim_z < 1)))
+    return fail(STENCIL_ERR_INVALID_ARG, "invalid model parameters");
+  const double nacc = q->num_read + q->num_write;
+  // Eq. 3
+  r->th_mem_gbs = std::min(q->f_max_hz * q->par_vec * q->size_cell * nacc / 1e9, q->th_max_gbs);
+  // Eq. 2, 4, 5
+  const long halo = (long)q->rad * q->par_time;
+  r->csize_x = q->bsize_x - 2 * halo;
+  r->csize_y = q->ndim == 3 ? q->bsize_y - 2 * halo : 0;
+  if (r->csize_x < 1 || (q->ndim == 3 && r->csize_y < 1))
+    return fail(STENCIL_ERR_INVALID_ARG, "halo leaves an empty compute block");
+  r->bnum_x = (q->dim_x + r->csize_x - 1) / r->csize_x;
+  r->bnum_y = q->ndim == 3 ? (q->dim_y + r->csize_y - 1) / r->csize_y : 0;
+  // Eq. 6 and 7: traversed cells per dimension minus the out-of-bound ones
+  const double trav_x = (double)r->bnum_x * r->csize_x + 2.0 * halo;
+  double size_input;
+  if (q->ndim == 2) {
+    r->t_cell = (double)r->bnum_x * q->bsize_x * q->dim_y;
+    r->t_read = (r->t_cell - (trav_x - q->dim_x) * q->dim_y) * q->num_read;
+    size_input = (double)q->dim_x * q->dim_y;
+  } else {
+    const double trav_y = (double)r->bnum_y * r->csize_y + 2.0 * halo;
+    r->t_cell = (double)r->bnum_x * q->bsize_x * r->bnum_y * q->bsize_y * q->dim_z;
+    r->t_read = ((double)r->bnum_x * q->bsize_x - (trav_x - q->dim_x)) *
+                ((double)r->bnum_y * q->bsize_y - (trav_y - q->dim_y)) * q->dim_z * q->num_read;
+    size_input = (double)q->dim_x * q->dim_y * q->dim_z;
+  }
+  r->t_write = size_input * q->num_write;
+  // Eq. 8, 9
+  const double passes = (double)((q->iter + q->par_time - 1) / q->par_time);
+  r->run_time_s = passes * (r->t_read + r->t_write) * q->size_cell / (1e9 * r->th_mem_gbs);
+  r->throughput_gbs = r->run_time_s > 0 ? nacc * size_input * q->size_cell * q->iter / (1e9 * r->run_time_s) : 0.0;
+  return STENCIL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// runtime.hpp -- host-side internals shared by the runtime translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <string>
+#include <vector>
+#include "../../include/stencil.h"
+#include "launch.hpp"
+
+namespace stn {
+
+// Thread-local error detail behind stencil_last_error().
+void set_error(const std::string& msg);
+stencil_status_t fail(stencil_status_t st, const std::string& msg);
+stencil_status_t hip_fail(hipError_t e, const char* what);
+bool env_flag(const char* name);
+bool log_enabled();
+
+// Device facts used by the cost model (queried once, with published MI355X fallbacks).
+struct DeviceInfo {
+  int cus = 256;
+  double hbm_gbs = 8000.0;      // peak HBM3E bandwidth
+  double achievable_frac = 0.72;
+  double valu_lane_ops = 256.0 * 4 * 16 * 2.4e9;  // CUs x SIMDs x lanes x clock (non-packed FP32)
+};
+const DeviceInfo& device_info();
+
+// Geometry of one temporal-blocked pass (fixed by the instantiated K and the grid).
+struct Geom2D {
+  int K = 0, cs = 0, kr = 0, ntx = 0, seg = 0, nseg = 0;
+};
+struct Geom3D {
+  int K = 0, csx = 0, csy = 0, krx = 0, kry = 0, ntx = 0, nty = 0, segz = 0, nsegz = 0;
+};
+Geom2D geom2d(int K, int nx, int ny, int seg);
+Geom3D geom3d(int K, bool adj, int nx, int ny, int nz, int segz);
+// Model time (seconds) of T steps with the given geometry.
+double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj);
+double model_time_3d(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj);
+// Choose segment lengths that balance the tile count against the device's concurrency.
+int pick_seg2d(int K, int nx, int ny, int waves_per_cu);
+int pick_segz3d(int K, bool adj, int nx, int ny, int nz, int wgs_per_cu);
+
+DevCoef dev_coef(const stencil_coeffs_t& c, bool adjoint);
+bool coeffs_finite(const stencil_coeffs_t& c);
+
+}  // namespace stn
+
+struct stencil_plan_s {
+  stencil_form_t form;
+  int ndim, nx, ny, nz;
+  size_t cells;
+  hipStream_t stream;
+  int device;
+  stencil_tuning_t tuning;  // resolved
+  float* scratch = nullptr;
+  // checkpoints of the last stencil_run_ckpt
+  std::vector<float*> ckpts;
+  int ckpt_every = 0;
+  int ckpt_T = -1;
+  // recompute verification
+  float* verify_buf = nullptr;
+  int* mismatch = nullptr;
+};

@@ -1,0 +1,300 @@
+// tb2d.hpp -- temporal-blocked 2D star stencil, one wavefront per overlapped tile.
+//
+// Method (paper Sections 3.1, 3.2; Eq. 2, Eq. 4, Eq. 5): the grid is cut into spatial blocks
+// along x that overlap by a halo of k cells per side (k = fused time steps of one pass); each
+// block streams along y and applies k consecutive time steps before anything goes back to
+// memory.  Step s of the block trails step s-1 by one row, so no block ever waits for
+// another; halo cells are computed redundantly and only the compute block is stored.
+//
+// gfx950 mapping (not the paper's FPGA pipeline):
+//   * One 64-lane wavefront owns a window of 64*V columns; lane l holds columns
+//     [ws + l*V, ws + l*V + V) of every row it touches, so each row of the window is one
+//     16-byte vector access per lane (coalesced, aligned when nx % 4 == 0).
+//   * The k time levels live in registers as a 3-row rotating window per level (the
+//     register analogue of the paper's shift register, Eq. 1): level s computes row r-s
+//     while level 0 receives row r.  The row loop is unrolled by three so the rotation is
+//     pure register renaming.
+//   * x-neighbours across lanes come from DPP wave shifts; y-neighbours are the rotating
+//     rows, so no LDS traffic is needed for the temperature field.
+//   * Hotspot: the time-invariant source q = fma(cp, p, kamb) of each row is formed once
+//     when the power row arrives and parked in a per-wave LDS ring of k+1 rows, from which
+//     each of the k levels reads it.
+//   * Clamp-to-edge (Section 5.1) is applied at every fused level by substituting the
+//     cell's own value for an out-of-grid neighbour.  Tiles that touch no grid edge take a
+//     code path with no boundary code at all (wave-uniform dispatch).
+//   * Adjoint mode applies the transposed operator: mirrored weights, zero contribution
+//     from outside the grid, and a self term with the weight of the direction that leaves
+//     the grid; sum_s lambda_s is carried along the level pipeline and added to grad_p once
+//     per pass.
+//   * Passes with fewer than K steps (the tail of T, Section 3.2) run the same kernel with
+//     the levels past keff simply forwarding their input row.
+#pragma once
+#include "device_common.hpp"
+
+struct Tb2dArgs {
+  const float* src;
+  float* dst;
+  const float* power;  // forward hotspot only
+  float* gp;           // adjoint hotspot: grad_p accumulator (read-modify-write); else null
+  int nx, ny;
+  int keff;            // steps fused in this pass, 1..K
+  int cs;              // output columns per tile (multiple of 4)
+  int kr;              // left halo of the window (>= K, multiple of 4)
+  int ntx;             // tiles along x
+  int seg;             // output rows per tile
+  int nseg;            // tiles along y
+  int aligned;         // 1: nx % 4 == 0 and 16-byte aligned buffers (vector access in interior tiles)
+  DevCoef cf;
+};
+
+template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL>
+struct Tb2dTile {
+  static_assert(V == 4 || V == 2 || V == 1, "V");
+  static constexpr int W = 64 * V;    // window width
+  static constexpr int RING = K + 1;  // hotspot source rows kept in LDS
+
+  const Tb2dArgs& a;
+  const int lane;
+  int ws, ox0, ox1, y0, y1;
+  float S[3][K][V];  // rotating rows of levels 0..K-1
+  float Lb[3][V];    // prefetched input rows
+  float Pb[3][V];    // prefetched power rows
+  float Pp[K][V];    // adjoint: running sums carried along the level pipeline
+  float cxm[V], cxp[V];
+  bool isL[V], isR[V];
+  float* ring;       // this wave's LDS ring (HOT forward)
+  int slot0;         // ring slot of the current input row
+
+  __device__ __forceinline__ Tb2dTile(const Tb2dArgs& args, int ln, float* lds) : a(args), lane(ln), ring(lds) {}
+
+  template <bool VEC>
+  __device__ __forceinline__ void load_row(int r, float (&dstv)[V], const float* base) const {
+    const int jr = clampi(r, 0, a.ny - 1);
+    const float* rowp = base + (size_t)jr * a.nx;
+    const int x0 = ws + lane * V;
+    if constexpr (VEC && V == 4) {
+      const float4 t = *reinterpret_cast<const float4*>(rowp + x0);
+      dstv[0] = t.x; dstv[1] = t.y; dstv[2] = t.z; dstv[3] = t.w;
+    } else if constexpr (VEC && V == 2) {
+      const float2 t = *reinterpret_cast<const float2*>(rowp + x0);
+      dstv[0] = t.x; dstv[1] = t.y;
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) dstv[v] = rowp[clampi(x0 + v, 0, a.nx - 1)];
+    }
+  }
+
+  template <bool VEC>
+  __device__ __forceinline__ void prefetch(int r, int b) {
+    load_row<VEC>(r, Lb[b], a.src);
+    if constexpr (HOT && !ADJ) load_row<VEC>(r, Pb[b], a.power);
+  }
+
+  // One fused level: out = stencil(rows y-1, y, y+1) at row j.
+  template <bool XE, bool YE>
+  __device__ __forceinline__ void level(const float (&Pr)[V], const float (&Cr)[V], const float (&Nr)[V],
+                                        float (&o)[V], int j, int qslot) const {
+    const float wl = from_lower(Cr[V - 1]);
+    const float eu = from_upper(Cr[0]);
+    const bool top = YE && (j == 0);
+    const bool bot = YE && (j == a.ny - 1);
+    float cym = a.cf.wy_m, cyp = a.cf.wy_p;
+    if constexpr (ADJ && YE) {
+      if (top) cym = a.cf.wy_p;
+      if (bot) cyp = a.cf.wy_m;
+    }
+    float q[V];
+    if constexpr (HOT && !ADJ) {
+      const float* qp = ring + qslot * W + lane * V;
+      if constexpr (V == 4) {
+        const float4 t = *reinterpret_cast<const float4*>(qp);
+        q[0] = t.x; q[1] = t.y; q[2] = t.z; q[3] = t.w;
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) q[v] = qp[v];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const float c = Cr[v];
+      float xm = (v > 0) ? Cr[v - 1] : wl;
+      float xp = (v < V - 1) ? Cr[v + 1] : eu;
+      float ym = Pr[v], yp = Nr[v];
+      float wxm = a.cf.wx_m, wxp = a.cf.wx_p;
+      if constexpr (XE) {
+        xm = isL[v] ? c : xm;
+        xp = isR[v] ? c : xp;
+        wxm = cxm[v];
+        wxp = cxp[v];
+      }
+      if constexpr (YE) {
+        ym = top ? c : ym;
+        yp = bot ? c : yp;
+      }
+      float acc = upd2(a.cf.c0, c, wxm, xm, wxp, xp, cyp, yp, cym, ym);
+      if constexpr (HOT && !ADJ) acc = acc + q[v];
+      o[v] = acc;
+    }
+  }
+
+  template <bool XE>
+  __device__ __forceinline__ void store_row(int j, const float (&o)[V], float* base) const {
+    float* rowp = base + (size_t)j * a.nx;
+    const int x0 = ws + lane * V;
+    if constexpr (!XE && V == 4) {
+      if (a.aligned) {
+        if (x0 >= ox0 && x0 < ox1) *reinterpret_cast<float4*>(rowp + x0) = make_float4(o[0], o[1], o[2], o[3]);
+        return;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      if (x0 + v >= ox0 && x0 + v < ox1) rowp[x0 + v] = o[v];
+  }
+
+  template <bool XE>
+  __device__ __forceinline__ void accum_gp(int j, const float (&e)[V]) const {
+    float* rowp = a.gp + (size_t)j * a.nx;
+    const int x0 = ws + lane * V;
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      if (x0 + v >= ox0 && x0 + v < ox1) rowp[x0 + v] = __builtin_fmaf(a.cf.cp, e[v], rowp[x0 + v]);
+  }
+
+  // One iteration of the streaming loop: input row r arrives, level s computes row r-s.
+  template <int ROT, bool XE, bool YE, bool VEC>
+  __device__ __forceinline__ void step(int r) {
+    float (&P)[K][V] = S[ROT % 3];
+    float (&C)[K][V] = S[(ROT + 1) % 3];
+    float (&N)[K][V] = S[(ROT + 2) % 3];
+#pragma unroll
+    for (int v = 0; v < V; ++v) N[0][v] = Lb[ROT][v];
+    if constexpr (HOT && !ADJ) {
+      float* qp = ring + slot0 * W + lane * V;
+#pragma unroll
+      for (int v = 0; v < V; ++v) qp[v] = __builtin_fmaf(a.cf.cp, Pb[ROT][v], a.cf.kamb);
+    }
+    prefetch<VEC>(r + 3, ROT);
+
+    float Pn[K][V];
+    (void)Pn;
+#pragma unroll
+    for (int s = 1; s <= K; ++s) {
+      const int j = r - s;
+      int qs = 0;
+      if constexpr (HOT && !ADJ) {
+        qs = slot0 - s;
+        if (qs < 0) qs += RING;
+      }
+      float o[V];
+      if (FULL || s <= a.keff) {
+        level<XE, YE>(P[s - 1], C[s - 1], N[s - 1], o, j, qs);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) o[v] = C[s - 1][v];
+      }
+      if constexpr (ACC) {
+        if (s < K) {
+          const bool add = FULL ? (s < K) : (s < a.keff);
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            const float prev = (s == 1) ? C[0][v] : Pp[s - 1][v];
+            Pn[s][v] = add ? prev + o[v] : prev;
+          }
+        }
+      }
+      if (s < K) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) N[s][v] = o[v];
+      } else {
+        if (j >= y0 && j < y1) {
+          store_row<XE>(j, o, a.dst);
+          if constexpr (ACC) {
+            float e[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) e[v] = (K == 1) ? C[0][v] : Pp[K - 1][v];
+            accum_gp<XE>(j, e);
+          }
+        }
+      }
+    }
+    if constexpr (ACC) {
+#pragma unroll
+      for (int s = 1; s < K; ++s)
+#pragma unroll
+        for (int v = 0; v < V; ++v) Pp[s][v] = Pn[s][v];
+    }
+    if constexpr (HOT && !ADJ) slot0 = (slot0 + 1 == RING) ? 0 : slot0 + 1;
+  }
+
+  template <bool XE, bool YE, bool VEC>
+  __device__ __forceinline__ void run() {
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int s = 0; s < K; ++s)
+#pragma unroll
+        for (int v = 0; v < V; ++v) S[b][s][v] = 0.0f;
+    if constexpr (ACC) {
+#pragma unroll
+      for (int s = 0; s < K; ++s)
+#pragma unroll
+        for (int v = 0; v < V; ++v) Pp[s][v] = 0.0f;
+    }
+    const int keff = FULL ? K : a.keff;
+    const int r0 = y0 - keff;
+    int nit = (y1 - y0) + keff + K;
+    nit = (nit + 2) / 3 * 3;  // extra iterations only touch rows outside [y0, y1)
+    slot0 = 0;
+    prefetch<VEC>(r0 + 0, 0);
+    prefetch<VEC>(r0 + 1, 1);
+    prefetch<VEC>(r0 + 2, 2);
+    for (int it = 0; it < nit; it += 3) {
+      step<0, XE, YE, VEC>(r0 + it);
+      step<1, XE, YE, VEC>(r0 + it + 1);
+      step<2, XE, YE, VEC>(r0 + it + 2);
+    }
+  }
+
+  __device__ __forceinline__ void process(int tile) {
+    const int tx = tile % a.ntx;
+    const int sg = tile / a.ntx;
+    ox0 = tx * a.cs;
+    ox1 = min(ox0 + a.cs, a.nx);
+    ws = ox0 - a.kr;
+    y0 = sg * a.seg;
+    y1 = min(y0 + a.seg, a.ny);
+    const bool xe = (ws < 0) || (ws + W > a.nx);
+    const int keff = FULL ? K : a.keff;
+    const bool ye = (y0 - keff <= 0) || (y1 + keff >= a.ny);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int x = ws + lane * V + v;
+      isL[v] = (x == 0);
+      isR[v] = (x == a.nx - 1);
+      cxm[v] = a.cf.wx_m;
+      cxp[v] = a.cf.wx_p;
+      if constexpr (ADJ) {
+        if (isL[v]) cxm[v] = a.cf.wx_p;
+        if (isR[v]) cxp[v] = a.cf.wx_m;
+      }
+    }
+    if (xe) {
+      if (ye) run<true, true, false>(); else run<true, false, false>();
+    } else if (a.aligned) {
+      if (ye) run<false, true, true>(); else run<false, false, true>();
+    } else {
+      if (ye) run<false, true, false>(); else run<false, false, false>();
+    }
+  }
+};
+
+template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL>
+__global__ __launch_bounds__(64) void tb2d_kernel(Tb2dArgs a) {
+  constexpr int RING = (HOT && !ADJ) ? (K + 1) : 1;
+  __shared__ __align__(16) float ring[RING * 64 * V];
+  const int ntiles = a.ntx * a.nseg;
+  const int tile = xcd_remap(blockIdx.x, ntiles);
+  Tb2dTile<K, V, HOT, ADJ, ACC, FULL> t(a, threadIdx.x, ring);
+  t.process(tile);
+}

@@ -1,0 +1,379 @@
+// tb3d.hpp -- temporal-blocked 3D star stencil: x-y tiles streamed along z ("2.5D").
+//
+// Method (paper Sections 3.1, 3.2; Eq. 2, 4, 5): 2D spatial blocking in x and y with
+// overlapping halos of k cells, streaming (no blocking) along z, and k consecutive time steps
+// applied to a block before it returns to memory; step s trails step s-1 by one plane.
+//
+// gfx950 mapping:
+//   * A workgroup of NW wavefronts owns a window of (64*V) x (R*NW) cells in x-y.  Lane l
+//     of wave w holds the V x R patch x in [xw + l*V, +V), y in [yw + w*R, +R) of every plane,
+//     so each row of a plane is one coalesced 8-byte access per lane.
+//   * The k time levels are a 3-plane rotating window per level held in registers (the
+//     register analogue of the paper's 3D shift register, Eq. 1); the plane loop is unrolled
+//     by three so the rotation is register renaming.
+//   * In-plane neighbours: x across lanes by DPP wave shifts, y inside a lane's R rows
+//     directly, and y across waves through LDS: each wave publishes the top and bottom rows
+//     of every new level plane, one barrier per plane makes them visible (double-buffered by
+//     plane parity), so all k levels of a plane share one barrier.
+//   * z-neighbours are the rotating planes.  Clamp-to-edge is applied per level by using
+//     the cell's own value for an out-of-grid neighbour; tiles that touch no x/y edge run
+//     code with no boundary handling, and the z edges cost only on the few planes that meet
+//     them.
+//   * Hotspot: the source q = fma(cp, p, kamb) is re-formed per level from the power plane
+//     (an L2 hit after the first level), keeping registers for the k-level window.
+//   * Adjoint: transposed operator (mirrored weights, zero outside the grid, self term with
+//     the weight of the leaving direction); sum_s lambda_s travels with the pipeline and is
+//     added to grad_p once per pass.
+#pragma once
+#include "device_common.hpp"
+
+struct Tb3dArgs {
+  const float* src;
+  float* dst;
+  const float* power;  // forward hotspot
+  float* gp;           // adjoint hotspot accumulator or null
+  int nx, ny, nz;
+  int keff;
+  int csx, csy;        // output cells per tile in x and y
+  int krx, kry;        // window offsets (window start = tile start - kr)
+  int ntx, nty;        // tiles in x, y
+  int segz, nsegz;     // output planes per tile, tiles along z
+  int aligned;         // 1: nx even and 8-byte aligned buffers (vector access in interior tiles)
+  DevCoef cf;
+};
+
+template <int K, int V, int R, int NW, bool HOT, bool ADJ, bool ACC, bool FULL>
+struct Tb3dTile {
+  static constexpr int WX = 64 * V;
+  static constexpr int WY = R * NW;
+  const Tb3dArgs& a;
+  const int lane, wave;
+  int xw, yw, ox0, ox1, oy0, oy1, z0, z1;
+  float S[3][K][R][V];
+  float Lb[R][V];     // next input plane (loaded one iteration ahead)
+  float Pp[K][R][V];
+  float cxm[V], cxp[V];
+  bool isL[V], isR[V];
+  bool rowTop[R], rowBot[R];  // wave-uniform: strip row is grid row 0 / ny-1
+  float* hal;                 // LDS: [2][K][NW][2][WX]
+
+  __device__ __forceinline__ Tb3dTile(const Tb3dArgs& args, int ln, int wv, float* lds)
+      : a(args), lane(ln), wave(wv), hal(lds) {}
+
+  __device__ __forceinline__ float* hrow(int buf, int lev, int w, int which) const {
+    return hal + ((((buf * K + lev) * NW + w) * 2 + which) * WX);
+  }
+
+  template <bool XE>
+  __device__ __forceinline__ void load_plane(int z, float (&d)[R][V], const float* base) const {
+    const int zc = clampi(z, 0, a.nz - 1);
+    const float* pl = base + (size_t)zc * a.ny * a.nx;
+    const int x0 = xw + lane * V;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int y = clampi(yw + wave * R + r, 0, a.ny - 1);
+      const float* rowp = pl + (size_t)y * a.nx;
+      if constexpr (!XE && V == 2) {
+        const float2 t = *reinterpret_cast<const float2*>(rowp + x0);
+        d[r][0] = t.x; d[r][1] = t.y;
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) d[r][v] = rowp[XE ? clampi(x0 + v, 0, a.nx - 1) : x0 + v];
+      }
+    }
+  }
+
+  __device__ __forceinline__ void publish(int buf, int lev, const float (&pl)[R][V]) const {
+    float* t = hrow(buf, lev, wave, 0) + lane * V;
+    float* b = hrow(buf, lev, wave, 1) + lane * V;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      t[v] = pl[0][v];
+      b[v] = pl[R - 1][v];
+    }
+  }
+
+  // level: out plane j from (Pl = plane j-1, Cl = plane j, Nl = plane j+1) of the level below;
+  // Cl's cross-wave neighbour rows come from LDS buffer rbuf.
+  template <bool XE, bool YE, bool ZE>
+  __device__ __forceinline__ void level(const float (&Pl)[R][V], const float (&Cl)[R][V], const float (&Nl)[R][V],
+                                        float (&o)[R][V], int lev_in, int rbuf, int j) const {
+    float hn[V], hs[V];
+    {
+      const int wn = wave > 0 ? wave - 1 : 0;
+      const int wsn = wave < NW - 1 ? wave + 1 : NW - 1;
+      const float* pn = hrow(rbuf, lev_in, wn, 1) + lane * V;
+      const float* ps = hrow(rbuf, lev_in, wsn, 0) + lane * V;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        hn[v] = pn[v];
+        hs[v] = ps[v];
+      }
+    }
+    const bool zlo = ZE && (j == 0);
+    const bool zhi = ZE && (j == a.nz - 1);
+    float czm = a.cf.wz_m, czp = a.cf.wz_p;
+    if constexpr (ADJ && ZE) {
+      if (zlo) czm = a.cf.wz_p;
+      if (zhi) czp = a.cf.wz_m;
+    }
+    float q[R][V];
+    if constexpr (HOT && !ADJ) {
+      const int zc = clampi(j, 0, a.nz - 1);
+      const float* pl = a.power + (size_t)zc * a.ny * a.nx;
+      const int x0 = xw + lane * V;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int y = clampi(yw + wave * R + r, 0, a.ny - 1);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const int x = XE ? clampi(x0 + v, 0, a.nx - 1) : x0 + v;
+          q[r][v] = __builtin_fmaf(a.cf.cp, pl[(size_t)y * a.nx + x], a.cf.kamb);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float wl = from_lower(Cl[r][V - 1]);
+      const float eu = from_upper(Cl[r][0]);
+      float cym = a.cf.wy_m, cyp = a.cf.wy_p;
+      if constexpr (ADJ && YE) {
+        if (rowTop[r]) cym = a.cf.wy_p;
+        if (rowBot[r]) cyp = a.cf.wy_m;
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const float c = Cl[r][v];
+        float xm = (v > 0) ? Cl[r][v - 1] : wl;
+        float xp = (v < V - 1) ? Cl[r][v + 1] : eu;
+        float ym = (r > 0) ? Cl[r - 1][v] : hn[v];
+        float yp = (r < R - 1) ? Cl[r + 1][v] : hs[v];
+        float zm = Pl[r][v], zp = Nl[r][v];
+        float wxm = a.cf.wx_m, wxp = a.cf.wx_p;
+        if constexpr (XE) {
+          xm = isL[v] ? c : xm;
+          xp = isR[v] ? c : xp;
+          wxm = cxm[v];
+          wxp = cxp[v];
+        }
+        if constexpr (YE) {
+          ym = rowTop[r] ? c : ym;
+          yp = rowBot[r] ? c : yp;
+        }
+        if constexpr (ZE) {
+          zm = zlo ? c : zm;
+          zp = zhi ? c : zp;
+        }
+        float acc = upd2(a.cf.c0, c, wxm, xm, wxp, xp, cyp, yp, cym, ym);
+        acc = __builtin_fmaf(czm, zm, acc);
+        acc = __builtin_fmaf(czp, zp, acc);
+        if constexpr (HOT && !ADJ) acc = acc + q[r][v];
+        o[r][v] = acc;
+      }
+    }
+  }
+
+  template <bool XE>
+  __device__ __forceinline__ void store_plane(int j, const float (&o)[R][V]) const {
+    float* pl = a.dst + (size_t)j * a.ny * a.nx;
+    const int x0 = xw + lane * V;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int y = yw + wave * R + r;
+      if (y < oy0 || y >= oy1) continue;
+      float* rowp = pl + (size_t)y * a.nx;
+      if constexpr (!XE && V == 2) {
+        if (x0 >= ox0 && x0 < ox1) *reinterpret_cast<float2*>(rowp + x0) = make_float2(o[r][0], o[r][1]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          if (x0 + v >= ox0 && x0 + v < ox1) rowp[x0 + v] = o[r][v];
+      }
+    }
+  }
+
+  __device__ __forceinline__ void accum_gp(int j, const float (&e)[R][V]) const {
+    float* pl = a.gp + (size_t)j * a.ny * a.nx;
+    const int x0 = xw + lane * V;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int y = yw + wave * R + r;
+      if (y < oy0 || y >= oy1) continue;
+      float* rowp = pl + (size_t)y * a.nx;
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (x0 + v >= ox0 && x0 + v < ox1) rowp[x0 + v] = __builtin_fmaf(a.cf.cp, e[r][v], rowp[x0 + v]);
+    }
+  }
+
+  // Iteration with input plane r: level s computes plane r - s.  The level-u plane made in
+  // this iteration is published in LDS buffer wbuf; the planes consumed as centres were
+  // published in the previous iteration (buffer wbuf ^ 1).
+  template <int ROT, bool XE, bool YE, bool ZE>
+  __device__ __forceinline__ void step(int r, int wbuf) {
+    float (&P)[K][R][V] = S[ROT % 3];
+    float (&C)[K][R][V] = S[(ROT + 1) % 3];
+    float (&N)[K][R][V] = S[(ROT + 2) % 3];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+      for (int v = 0; v < V; ++v) N[0][rr][v] = Lb[rr][v];
+    load_plane<XE>(r + 1, Lb, a.src);
+    publish(wbuf, 0, N[0]);
+    const int rbuf = wbuf ^ 1;
+    float Pn[K][R][V];
+    (void)Pn;
+#pragma unroll
+    for (int s = 1; s <= K; ++s) {
+      const int j = r - s;
+      float o[R][V];
+      if (FULL || s <= a.keff) {
+        level<XE, YE, ZE>(P[s - 1], C[s - 1], N[s - 1], o, s - 1, rbuf, j);
+      } else {
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+          for (int v = 0; v < V; ++v) o[rr][v] = C[s - 1][rr][v];
+      }
+      if constexpr (ACC) {
+        if (s < K) {
+          const bool add = FULL ? true : (s < a.keff);
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              const float prev = (s == 1) ? C[0][rr][v] : Pp[s - 1][rr][v];
+              Pn[s][rr][v] = add ? prev + o[rr][v] : prev;
+            }
+        }
+      }
+      if (s < K) {
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+          for (int v = 0; v < V; ++v) N[s][rr][v] = o[rr][v];
+        publish(wbuf, s, o);
+      } else if (j >= z0 && j < z1) {
+        store_plane<XE>(j, o);
+        if constexpr (ACC) {
+          float e[R][V];
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+            for (int v = 0; v < V; ++v) e[rr][v] = (K == 1) ? C[0][rr][v] : Pp[K - 1][rr][v];
+          accum_gp(j, e);
+        }
+      }
+    }
+    if constexpr (ACC) {
+#pragma unroll
+      for (int s = 1; s < K; ++s)
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+          for (int v = 0; v < V; ++v) Pp[s][rr][v] = Pn[s][rr][v];
+    }
+    __syncthreads();
+  }
+
+  template <bool XE, bool YE>
+  __device__ __forceinline__ void run() {
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int s = 0; s < K; ++s)
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+          for (int v = 0; v < V; ++v) S[b][s][rr][v] = 0.0f;
+    if constexpr (ACC) {
+#pragma unroll
+      for (int s = 0; s < K; ++s)
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+          for (int v = 0; v < V; ++v) Pp[s][rr][v] = 0.0f;
+    }
+    const int keff = FULL ? K : a.keff;
+    const int r0 = z0 - keff;
+    int nit = (z1 - z0) + keff + K;
+    nit = (nit + 2) / 3 * 3;
+    load_plane<XE>(r0, Lb, a.src);
+    // Groups of three iterations that compute a plane at a z edge form a prefix (z = 0) and
+    // a suffix (z = nz-1) of the loop; they run a body with z-edge handling, the rest a body
+    // without it.  Separate loops (rather than a branch inside one loop) keep the register
+    // allocation of the hot body free of merge copies.
+    int it = 0, wbuf = 0;
+    auto edge = [&](int i) {
+      const int r = r0 + i;
+      return (r - K <= 0 && r + 1 >= 0) || (r - K <= a.nz - 1 && r + 1 >= a.nz - 1);
+    };
+    for (; it < nit && edge(it); it += 3) {
+      step<0, XE, YE, true>(r0 + it, wbuf);
+      step<1, XE, YE, true>(r0 + it + 1, wbuf ^ 1);
+      step<2, XE, YE, true>(r0 + it + 2, wbuf);
+      wbuf ^= 1;
+    }
+    for (; it < nit && !edge(it); it += 3) {
+      step<0, XE, YE, false>(r0 + it, wbuf);
+      step<1, XE, YE, false>(r0 + it + 1, wbuf ^ 1);
+      step<2, XE, YE, false>(r0 + it + 2, wbuf);
+      wbuf ^= 1;
+    }
+    for (; it < nit; it += 3) {
+      step<0, XE, YE, true>(r0 + it, wbuf);
+      step<1, XE, YE, true>(r0 + it + 1, wbuf ^ 1);
+      step<2, XE, YE, true>(r0 + it + 2, wbuf);
+      wbuf ^= 1;
+    }
+  }
+
+  __device__ __forceinline__ void process(int tile) {
+    const int tx = tile % a.ntx;
+    const int rest = tile / a.ntx;
+    const int ty = rest % a.nty;
+    const int tz = rest / a.nty;
+    ox0 = tx * a.csx;
+    ox1 = min(ox0 + a.csx, a.nx);
+    oy0 = ty * a.csy;
+    oy1 = min(oy0 + a.csy, a.ny);
+    xw = ox0 - a.krx;
+    yw = oy0 - a.kry;
+    z0 = tz * a.segz;
+    z1 = min(z0 + a.segz, a.nz);
+    const bool xe = !a.aligned || (xw < 0) || (xw + WX > a.nx);
+    const bool ye = (yw < 0) || (yw + WY > a.ny);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int x = xw + lane * V + v;
+      isL[v] = (x == 0);
+      isR[v] = (x == a.nx - 1);
+      cxm[v] = a.cf.wx_m;
+      cxp[v] = a.cf.wx_p;
+      if constexpr (ADJ) {
+        if (isL[v]) cxm[v] = a.cf.wx_p;
+        if (isR[v]) cxp[v] = a.cf.wx_m;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int y = yw + wave * R + r;
+      rowTop[r] = (y == 0);
+      rowBot[r] = (y == a.ny - 1);
+    }
+    if (xe) {
+      if (ye) run<true, true>(); else run<true, false>();
+    } else {
+      if (ye) run<false, true>(); else run<false, false>();
+    }
+  }
+};
+
+template <int K, int V, int R, int NW, bool HOT, bool ADJ, bool ACC, bool FULL>
+__global__ __launch_bounds__(64 * NW) void tb3d_kernel(Tb3dArgs a) {
+  __shared__ __align__(16) float hal[2 * K * NW * 2 * 64 * V];
+  const int ntiles = a.ntx * a.nty * a.nsegz;
+  const int tile = xcd_remap(blockIdx.x, ntiles);
+  Tb3dTile<K, V, R, NW, HOT, ADJ, ACC, FULL> t(a, threadIdx.x & 63, threadIdx.x >> 6, hal);
+  t.process(tile);
+}
