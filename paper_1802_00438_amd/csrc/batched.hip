@@ -41,31 +41,48 @@ struct BItem {
   int g, p, tile, keff;
 };
 
+// Every lane of the wave spins on the same flag; the loaded value is made wave-uniform
+// (readfirstlane) so that the loop exit is a scalar branch.  Had the exit been left as a
+// per-lane condition, the compiler would treat the loop as divergent and could let lanes
+// leave it at different iterations.
 __device__ __forceinline__ void wait_flag(const int* f, int want) {
-  while (ld_acquire(f) < want) __builtin_amdgcn_s_sleep(2);
+  for (;;) {
+    const int v = __builtin_amdgcn_readfirstlane(ld_acquire(f));
+    if (v >= want) break;
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// Claim the next work item for the whole workgroup, with no lane-divergent branch: every
+// lane of the claiming wave issues the atomic (lane 0 adds 1, the others 0) and the result is
+// taken from lane 0 with readfirstlane.  Divergent "if (threadIdx.x == 0)" blocks around the
+// claim and the release would let the compiler restructure the persistent loop so that lane 0
+// and lanes 1..63 run different loop nests; with the per-item control flow kept uniform, the
+// loop is one scalar loop and every lane runs every trip.
+__device__ __forceinline__ int wave_claim(int* counter) {
+  const int lane = __lane_id();
+  return __builtin_amdgcn_readfirstlane(atomicAdd(counter, lane == 0 ? 1 : 0));
+}
+
+__device__ __forceinline__ void wait_neighbours(const int* flags, int off, int tx, int ty, int ntx, int nty, int p) {
+  if (p == 0) return;
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int x = tx + dx, y = ty + dy;
+      if (x < 0 || y < 0 || x >= ntx || y >= nty) continue;
+      wait_flag(flags + off + y * ntx + x, p);
+    }
 }
 
 __global__ __launch_bounds__(64) void batched2d_kernel(const BGrid* __restrict__ grids, const BItem* __restrict__ items,
                                                        int nitems, int* counter, int* flags) {
-  __shared__ int sh;
   for (;;) {
-    if (threadIdx.x == 0) sh = atomicAdd(counter, 1);
-    __syncthreads();
-    const int it = sh;
-    __syncthreads();
+    const int it = wave_claim(counter);
     if (it >= nitems) break;
     const BItem w = items[it];
     const BGrid& g = grids[w.g];
     const int tx = w.tile % g.ntx, ty = w.tile / g.ntx;
-    if (threadIdx.x == 0 && w.p > 0) {
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int x = tx + dx, y = ty + dy;
-          if (x < 0 || y < 0 || x >= g.ntx || y >= g.nseg) continue;
-          wait_flag(flags + g.flag_off + y * g.ntx + x, w.p);
-        }
-    }
-    __syncthreads();
+    wait_neighbours(flags, g.flag_off, tx, ty, g.ntx, g.nseg, w.p);
     Tb2dArgs a;
     a.src = g.buf[w.p & 1];
     a.dst = g.buf[(w.p + 1) & 1];
@@ -79,11 +96,9 @@ __global__ __launch_bounds__(64) void batched2d_kernel(const BGrid* __restrict__
       Tb2dTile<kBatchK2, kTb2dV, false, false, false, false> t(a, threadIdx.x, nullptr);
       t.process(w.tile);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
-      st_release(flags + g.flag_off + w.tile, w.p + 1);
-    }
+    // all lanes publish the same flag value (release orders the wave's stores before it)
+    __threadfence();
+    st_release(flags + g.flag_off + w.tile, w.p + 1);
   }
 }
 
@@ -92,24 +107,17 @@ __global__ __launch_bounds__(64 * kTb3dNW) void batched3d_kernel(const BGrid* __
                                                                  int* counter, int* flags) {
   __shared__ __align__(16) float hal[2 * kBatchK3 * kTb3dNW * 2 * 64 * kTb3dV];
   __shared__ int sh;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (;;) {
-    if (threadIdx.x == 0) sh = atomicAdd(counter, 1);
+    if (wave == 0) sh = wave_claim(counter);  // wave-uniform branch
     __syncthreads();
-    const int it = sh;
+    const int it = __builtin_amdgcn_readfirstlane(sh);
     __syncthreads();
     if (it >= nitems) break;
     const BItem w = items[it];
     const BGrid& g = grids[w.g];
     const int tx = w.tile % g.ntx, ty = w.tile / g.ntx;
-    if (threadIdx.x == 0 && w.p > 0) {
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int x = tx + dx, y = ty + dy;
-          if (x < 0 || y < 0 || x >= g.ntx || y >= g.nty) continue;
-          wait_flag(flags + g.flag_off + y * g.ntx + x, w.p);
-        }
-    }
-    __syncthreads();
+    wait_neighbours(flags, g.flag_off, tx, ty, g.ntx, g.nty, w.p);
     Tb3dArgs a;
     a.src = g.buf[w.p & 1];
     a.dst = g.buf[(w.p + 1) & 1];
@@ -125,8 +133,8 @@ __global__ __launch_bounds__(64 * kTb3dNW) void batched3d_kernel(const BGrid* __
                                                                                  hal);
       t.process(w.tile);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
+    __syncthreads();  // every wave's stores of this item precede wave 0's release
+    if (wave == 0) {
       __threadfence();
       st_release(flags + g.flag_off + w.tile, w.p + 1);
     }
