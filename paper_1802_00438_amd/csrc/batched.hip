@@ -31,7 +31,7 @@ struct BGrid {
   float* buf[2];  // buf[0] = caller's grid, buf[1] = scratch
   int nx, ny, nz;
   int cs, kr, ntx, seg, nseg;           // 2D geometry
-  int csx, csy, krx, kry, nty;          // 3D geometry (ntx shared)
+  int csx, csy, krx, kry, nty, segz, nsegz;  // 3D geometry (ntx shared)
   int flag_off;
   int aligned;
   DevCoef cf;
@@ -41,13 +41,13 @@ struct BItem {
   int g, p, tile, keff;
 };
 
-// Every lane of the wave spins on the same flag; the loaded value is made wave-uniform
-// (readfirstlane) so that the loop exit is a scalar branch.  Had the exit been left as a
-// per-lane condition, the compiler would treat the loop as divergent and could let lanes
-// leave it at different iterations.
+// Every lane of the wave spins on the same flag with relaxed agent-scope loads; the loaded
+// value is made wave-uniform (readfirstlane) so that the loop exit is a scalar branch.  One
+// acquire fence after all of an item's waits (wait_neighbours) orders the item's reads after
+// the producers' release stores.
 __device__ __forceinline__ void wait_flag(const int* f, int want) {
   for (;;) {
-    const int v = __builtin_amdgcn_readfirstlane(ld_acquire(f));
+    const int v = __builtin_amdgcn_readfirstlane(__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     if (v >= want) break;
     __builtin_amdgcn_s_sleep(2);
   }
@@ -72,6 +72,7 @@ __device__ __forceinline__ void wait_neighbours(const int* flags, int off, int t
       if (x < 0 || y < 0 || x >= ntx || y >= nty) continue;
       wait_flag(flags + off + y * ntx + x, p);
     }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 __global__ __launch_bounds__(64) void batched2d_kernel(const BGrid* __restrict__ grids, const BItem* __restrict__ items,
@@ -97,7 +98,6 @@ __global__ __launch_bounds__(64) void batched2d_kernel(const BGrid* __restrict__
       t.process(w.tile);
     }
     // all lanes publish the same flag value (release orders the wave's stores before it)
-    __threadfence();
     st_release(flags + g.flag_off + w.tile, w.p + 1);
   }
 }
@@ -116,8 +116,14 @@ __global__ __launch_bounds__(64 * kTb3dNW) void batched3d_kernel(const BGrid* __
     if (it >= nitems) break;
     const BItem w = items[it];
     const BGrid& g = grids[w.g];
-    const int tx = w.tile % g.ntx, ty = w.tile / g.ntx;
-    wait_neighbours(flags, g.flag_off, tx, ty, g.ntx, g.nty, w.p);
+    const int tx = w.tile % g.ntx, rest = w.tile / g.ntx, ty = rest % g.nty, tz = rest / g.nty;
+    if (w.p > 0) {
+      for (int dz = -1; dz <= 1; ++dz) {
+        const int z = tz + dz;
+        if (z < 0 || z >= g.nsegz) continue;
+        wait_neighbours(flags, g.flag_off + z * g.ntx * g.nty, tx, ty, g.ntx, g.nty, w.p);
+      }
+    }
     Tb3dArgs a;
     a.src = g.buf[w.p & 1];
     a.dst = g.buf[(w.p + 1) & 1];
@@ -125,7 +131,7 @@ __global__ __launch_bounds__(64 * kTb3dNW) void batched3d_kernel(const BGrid* __
     a.gp = nullptr;
     a.nx = g.nx; a.ny = g.ny; a.nz = g.nz; a.keff = w.keff;
     a.csx = g.csx; a.csy = g.csy; a.krx = g.krx; a.kry = g.kry; a.ntx = g.ntx; a.nty = g.nty;
-    a.segz = g.nz; a.nsegz = 1;
+    a.segz = g.segz; a.nsegz = g.nsegz;
     a.aligned = g.aligned;
     a.cf = g.cf;
     {
@@ -134,10 +140,7 @@ __global__ __launch_bounds__(64 * kTb3dNW) void batched3d_kernel(const BGrid* __
       t.process(w.tile);
     }
     __syncthreads();  // every wave's stores of this item precede wave 0's release
-    if (wave == 0) {
-      __threadfence();
-      st_release(flags + g.flag_off + w.tile, w.p + 1);
-    }
+    if (wave == 0) st_release(flags + g.flag_off + w.tile, w.p + 1);
   }
 }
 
@@ -235,23 +238,27 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
       double best = 1e300;
       int bestk = kBatchK2;
       for (int k : {4, 8, 12, 16}) {
-        const int seg = pick_seg2d(kBatchK2, g.nx, g.ny, 8);
+        const int seg = std::min(g.ny, 512);
         Geom2D gg = geom2d(kBatchK2, g.nx, g.ny, seg);
         gg.K = k;  // price k fused steps on the fixed window
         const double t = model_time_2d(gg, g.nx, g.ny, it.T, false, false);
         if (t < best) { best = t; bestk = k; }
       }
-      const int seg = std::max(pick_seg2d(kBatchK2, g.nx, g.ny, 8), kBatchK2);
+      // items of a batch share the device, so each item is a long y-segment (at least 512
+      // rows or the whole grid): few, large items keep the per-item flag traffic negligible
+      const int seg = std::min(g.ny, std::max(512, kBatchK2));
       const Geom2D gg = geom2d(kBatchK2, g.nx, g.ny, seg);
       g.cs = gg.cs; g.kr = gg.kr; g.ntx = gg.ntx; g.seg = gg.seg; g.nseg = gg.nseg;
       g.aligned = ((g.nx & 3) == 0) && ((reinterpret_cast<uintptr_t>(g.buf[0]) | reinterpret_cast<uintptr_t>(s)) & 15) == 0;
       ntiles[i] = gg.ntx * gg.nseg;
       steps[i] = even_split(it.T, bestk);
     } else {
-      const Geom3D gg = geom3d(kBatchK3, false, g.nx, g.ny, g.nz, g.nz);
+      // z-segments of 64 planes (at least the halo) give the 3D list enough items per pass
+      const Geom3D gg = geom3d(kBatchK3, false, g.nx, g.ny, g.nz, std::min(g.nz, 64));
       g.csx = gg.csx; g.csy = gg.csy; g.krx = gg.krx; g.kry = gg.kry; g.ntx = gg.ntx; g.nty = gg.nty;
+      g.segz = gg.segz; g.nsegz = gg.nsegz;
       g.aligned = ((g.nx & 1) == 0) && ((reinterpret_cast<uintptr_t>(g.buf[0]) | reinterpret_cast<uintptr_t>(s)) & 7) == 0;
-      ntiles[i] = gg.ntx * gg.nty;
+      ntiles[i] = gg.ntx * gg.nty * gg.nsegz;
       steps[i] = even_split(it.T, kBatchK3);
     }
     g.flag_off = nflags;

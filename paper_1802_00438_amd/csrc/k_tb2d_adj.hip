@@ -10,5 +10,5 @@
       else TB_LAUNCH2D(K, false, true, false, false, a, s);                           \
     }
 hipError_t launch_tb2d_adj(int K, bool acc, bool full, const Tb2dArgs& a, hipStream_t s) {
-  switch (K) { C(4) C(8) default: return hipErrorInvalidValue; }
+  switch (K) { C(4) C(8) C(12) default: return hipErrorInvalidValue; }
 }

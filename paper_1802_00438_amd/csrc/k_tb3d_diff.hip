@@ -3,5 +3,5 @@
 #define C(K) case K: if (full) TB_LAUNCH3D(K, kTb3dR, kTb3dNW, false, false, false, true, a, s); \
                      else TB_LAUNCH3D(K, kTb3dR, kTb3dNW, false, false, false, false, a, s);
 hipError_t launch_tb3d_diff(int K, bool full, const Tb3dArgs& a, hipStream_t s) {
-  switch (K) { C(1) C(2) C(3) C(4) default: return hipErrorInvalidValue; }
+  switch (K) { C(1) C(2) C(3) C(4) C(5) C(6) default: return hipErrorInvalidValue; }
 }

@@ -15,20 +15,22 @@ __global__ void fill_int_kernel(int* p, size_t n, int v) {
 
 
 namespace {
-const int kK2F[] = {4, 8, 12, 16};
-const int kK2A[] = {4, 8};
-const int kK3D[] = {1, 2, 3, 4};
-const int kK3H[] = {1, 2, 3};
+const int kK2D[] = {4, 8, 12, 16, 20, 24};
+const int kK2H[] = {4, 8, 12, 16};
+const int kK2A[] = {4, 8, 12};
+const int kK3D[] = {1, 2, 3, 4, 5, 6};
+const int kK3H[] = {1, 2, 3, 4};
 const int kK3A[] = {1, 2, 3, 4};
 }  // namespace
 
 int tb_instantiated(int ndim, KMode m, const int** ks) {
   if (ndim == 2) {
-    if (m == KM_DIFF || m == KM_HOT) { *ks = kK2F; return 4; }
-    *ks = kK2A; return 2;
+    if (m == KM_DIFF) { *ks = kK2D; return 6; }
+    if (m == KM_HOT) { *ks = kK2H; return 4; }
+    *ks = kK2A; return 3;
   }
-  if (m == KM_DIFF) { *ks = kK3D; return 4; }
-  if (m == KM_HOT) { *ks = kK3H; return 3; }
+  if (m == KM_DIFF) { *ks = kK3D; return 6; }
+  if (m == KM_HOT) { *ks = kK3H; return 4; }
   *ks = kK3A; return 4;
 }
 
@@ -59,7 +61,7 @@ hipError_t launch_tb3d(int K, KMode m, bool full, const Tb3dArgs& a, hipStream_t
 }
 
 hipError_t launch_plain(KMode m, const PlainArgs& a, hipStream_t s) {
-  const int nb = a.chunks * a.ny * a.nz;
+  const int nb = plain_blocks(a);
   switch (m) {
     case KM_DIFF: hipLaunchKernelGGL((plain_kernel<false, false, false>), dim3(nb), dim3(256), 0, s, a); break;
     case KM_HOT: hipLaunchKernelGGL((plain_kernel<true, false, false>), dim3(nb), dim3(256), 0, s, a); break;

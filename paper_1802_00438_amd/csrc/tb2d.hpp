@@ -10,12 +10,18 @@
 //   * One 64-lane wavefront owns a window of 64*V columns; lane l holds columns
 //     [ws + l*V, ws + l*V + V) of every row it touches, so each row of the window is one
 //     16-byte vector access per lane (coalesced, aligned when nx % 4 == 0).
-//   * The k time levels live in registers as a 3-row rotating window per level (the
-//     register analogue of the paper's shift register, Eq. 1): level s computes row r-s
-//     while level 0 receives row r.  The row loop is unrolled by three so the rotation is
-//     pure register renaming.
-//   * x-neighbours across lanes come from DPP wave shifts; y-neighbours are the rotating
-//     rows, so no LDS traffic is needed for the temperature field.
+//   * The tile streams its rows bottom-up.  Level s (1..K) computes row r+s while level 0
+//     receives row r, from rows r+s+1 (below, y+1), r+s (centre) and r+s-1 (above, y-1) of
+//     level s-1.  The canonical term order (centre, x-1, x+1, y+1, y-1) puts the row that
+//     arrived first (y+1) before the row that arrives last (y-1), so each iteration runs in
+//     two phases: (1) for every level, fold the centre row and the oldest row into a partial
+//     sum, which frees the oldest row's registers; (2) walking up the levels, add the y-1
+//     term from the row the level below has just produced.  Each level therefore keeps two
+//     rows in registers (centre, and oldest/partial/newest in turn) -- the register analogue
+//     of the paper's shift register (Eq. 1) -- and the row loop, unrolled by two, renames
+//     them without copies.
+//   * x-neighbours across lanes come from DPP wave shifts; no LDS traffic is needed for the
+//     temperature field.
 //   * Hotspot: the time-invariant source q = fma(cp, p, kamb) of each row is formed once
 //     when the power row arrives and parked in a per-wave LDS ring of k+1 rows, from which
 //     each of the k levels reads it.
@@ -49,16 +55,16 @@ struct Tb2dArgs {
 
 template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL>
 struct Tb2dTile {
-  static_assert(V == 4 || V == 2 || V == 1, "V");
+  static_assert(V == 4 || V == 8, "V");
   static constexpr int W = 64 * V;    // window width
   static constexpr int RING = K + 1;  // hotspot source rows kept in LDS
 
   const Tb2dArgs& a;
   const int lane;
   int ws, ox0, ox1, y0, y1;
-  float S[3][K][V];  // rotating rows of levels 0..K-1
-  float Lb[3][V];    // prefetched input rows
-  float Pb[3][V];    // prefetched power rows
+  float S[2][K][V];  // per level: [0] and [1] alternate between "centre" and "oldest/new"
+  float Lb[2][V];    // prefetched input rows
+  float Pb[2][V];    // prefetched power rows
   float Pp[K][V];    // adjoint: running sums carried along the level pipeline
   float cxm[V], cxp[V];
   bool isL[V], isR[V];
@@ -72,12 +78,12 @@ struct Tb2dTile {
     const int jr = clampi(r, 0, a.ny - 1);
     const float* rowp = base + (size_t)jr * a.nx;
     const int x0 = ws + lane * V;
-    if constexpr (VEC && V == 4) {
-      const float4 t = *reinterpret_cast<const float4*>(rowp + x0);
-      dstv[0] = t.x; dstv[1] = t.y; dstv[2] = t.z; dstv[3] = t.w;
-    } else if constexpr (VEC && V == 2) {
-      const float2 t = *reinterpret_cast<const float2*>(rowp + x0);
-      dstv[0] = t.x; dstv[1] = t.y;
+    if constexpr (VEC) {
+#pragma unroll
+      for (int h = 0; h < V; h += 4) {
+        const float4 t = *reinterpret_cast<const float4*>(rowp + x0 + h);
+        dstv[h] = t.x; dstv[h + 1] = t.y; dstv[h + 2] = t.z; dstv[h + 3] = t.w;
+      }
     } else {
 #pragma unroll
       for (int v = 0; v < V; ++v) dstv[v] = rowp[clampi(x0 + v, 0, a.nx - 1)];
@@ -90,36 +96,22 @@ struct Tb2dTile {
     if constexpr (HOT && !ADJ) load_row<VEC>(r, Pb[b], a.power);
   }
 
-  // One fused level: out = stencil(rows y-1, y, y+1) at row j.
+  // Phase 1 of a level: centre, x-1, x+1 and y+1 terms of row j (oldest row Pr = y+1).
   template <bool XE, bool YE>
-  __device__ __forceinline__ void level(const float (&Pr)[V], const float (&Cr)[V], const float (&Nr)[V],
-                                        float (&o)[V], int j, int qslot) const {
+  __device__ __forceinline__ void partial(const float (&Pr)[V], const float (&Cr)[V], float (&o)[V], int j) const {
     const float wl = from_lower(Cr[V - 1]);
     const float eu = from_upper(Cr[0]);
-    const bool top = YE && (j == 0);
-    const bool bot = YE && (j == a.ny - 1);
-    float cym = a.cf.wy_m, cyp = a.cf.wy_p;
+    const bool bot = YE && (j == a.ny - 1);  // y+1 leaves the grid
+    float cyp = a.cf.wy_p;
     if constexpr (ADJ && YE) {
-      if (top) cym = a.cf.wy_p;
       if (bot) cyp = a.cf.wy_m;
-    }
-    float q[V];
-    if constexpr (HOT && !ADJ) {
-      const float* qp = ring + qslot * W + lane * V;
-      if constexpr (V == 4) {
-        const float4 t = *reinterpret_cast<const float4*>(qp);
-        q[0] = t.x; q[1] = t.y; q[2] = t.z; q[3] = t.w;
-      } else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) q[v] = qp[v];
-      }
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const float c = Cr[v];
       float xm = (v > 0) ? Cr[v - 1] : wl;
       float xp = (v < V - 1) ? Cr[v + 1] : eu;
-      float ym = Pr[v], yp = Nr[v];
+      float yp = Pr[v];
       float wxm = a.cf.wx_m, wxp = a.cf.wx_p;
       if constexpr (XE) {
         xm = isL[v] ? c : xm;
@@ -127,11 +119,38 @@ struct Tb2dTile {
         wxm = cxm[v];
         wxp = cxp[v];
       }
-      if constexpr (YE) {
-        ym = top ? c : ym;
-        yp = bot ? c : yp;
+      if constexpr (YE) yp = bot ? c : yp;
+      float acc = a.cf.c0 * c;
+      acc = __builtin_fmaf(wxm, xm, acc);
+      acc = __builtin_fmaf(wxp, xp, acc);
+      acc = __builtin_fmaf(cyp, yp, acc);
+      o[v] = acc;
+    }
+  }
+
+  // Phase 2 of a level: add the y-1 term (newest row Nr of the level below), then the source.
+  template <bool YE>
+  __device__ __forceinline__ void finish(const float (&Nr)[V], const float (&Cr)[V], float (&o)[V], int j,
+                                         int qslot) const {
+    const bool top = YE && (j == 0);  // y-1 leaves the grid
+    float cym = a.cf.wy_m;
+    if constexpr (ADJ && YE) {
+      if (top) cym = a.cf.wy_p;
+    }
+    float q[V];
+    if constexpr (HOT && !ADJ) {
+      const float* qp = ring + qslot * W + lane * V;
+#pragma unroll
+      for (int h = 0; h < V; h += 4) {
+        const float4 t = *reinterpret_cast<const float4*>(qp + h);
+        q[h] = t.x; q[h + 1] = t.y; q[h + 2] = t.z; q[h + 3] = t.w;
       }
-      float acc = upd2(a.cf.c0, c, wxm, xm, wxp, xp, cyp, yp, cym, ym);
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      float ym = Nr[v];
+      if constexpr (YE) ym = top ? Cr[v] : ym;
+      float acc = __builtin_fmaf(cym, ym, o[v]);
       if constexpr (HOT && !ADJ) acc = acc + q[v];
       o[v] = acc;
     }
@@ -141,9 +160,11 @@ struct Tb2dTile {
   __device__ __forceinline__ void store_row(int j, const float (&o)[V], float* base) const {
     float* rowp = base + (size_t)j * a.nx;
     const int x0 = ws + lane * V;
-    if constexpr (!XE && V == 4) {
-      if (a.aligned) {
-        if (x0 >= ox0 && x0 < ox1) *reinterpret_cast<float4*>(rowp + x0) = make_float4(o[0], o[1], o[2], o[3]);
+    if constexpr (!XE) {
+      if (a.aligned && x0 >= ox0 && x0 + V <= ox1) {
+#pragma unroll
+        for (int h = 0; h < V; h += 4)
+          *reinterpret_cast<float4*>(rowp + x0 + h) = make_float4(o[h], o[h + 1], o[h + 2], o[h + 3]);
         return;
       }
     }
@@ -161,41 +182,61 @@ struct Tb2dTile {
       if (x0 + v >= ox0 && x0 + v < ox1) rowp[x0 + v] = __builtin_fmaf(a.cf.cp, e[v], rowp[x0 + v]);
   }
 
-  // One iteration of the streaming loop: input row r arrives, level s computes row r-s.
+  // One iteration: input row r arrives (rows stream downwards in index), level s makes row r+s.
   template <int ROT, bool XE, bool YE, bool VEC>
   __device__ __forceinline__ void step(int r) {
-    float (&P)[K][V] = S[ROT % 3];
-    float (&C)[K][V] = S[(ROT + 1) % 3];
-    float (&N)[K][V] = S[(ROT + 2) % 3];
+    float (&X)[K][V] = S[ROT];      // oldest rows on entry; partial sums; newest rows on exit
+    float (&C)[K][V] = S[ROT ^ 1];  // centre rows
+    const int keff = FULL ? K : a.keff;
+    // ---- phase 1, top level first: partial[s] (row r+s) replaces X[s] once X[s] is used
+    float part_top[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) N[0][v] = Lb[ROT][v];
+    for (int s = K; s >= 1; --s) {
+      const int j = r + s;
+      float o[V];
+      if (FULL || s <= keff) {
+        partial<XE, YE>(X[s - 1], C[s - 1], o, j);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) o[v] = 0.0f;  // surplus level: overwritten in phase 2
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        if (s == K) part_top[v] = o[v];
+        else X[s][v] = o[v];
+      }
+    }
+    // ---- phase 2, bottom level first
+#pragma unroll
+    for (int v = 0; v < V; ++v) X[0][v] = Lb[ROT][v];
     if constexpr (HOT && !ADJ) {
       float* qp = ring + slot0 * W + lane * V;
 #pragma unroll
       for (int v = 0; v < V; ++v) qp[v] = __builtin_fmaf(a.cf.cp, Pb[ROT][v], a.cf.kamb);
     }
-    prefetch<VEC>(r + 3, ROT);
-
+    prefetch<VEC>(r - 2, ROT);
     float Pn[K][V];
     (void)Pn;
 #pragma unroll
     for (int s = 1; s <= K; ++s) {
-      const int j = r - s;
+      const int j = r + s;
       int qs = 0;
       if constexpr (HOT && !ADJ) {
         qs = slot0 - s;
         if (qs < 0) qs += RING;
       }
       float o[V];
-      if (FULL || s <= a.keff) {
-        level<XE, YE>(P[s - 1], C[s - 1], N[s - 1], o, j, qs);
+#pragma unroll
+      for (int v = 0; v < V; ++v) o[v] = (s == K) ? part_top[v] : X[s][v];
+      if (FULL || s <= keff) {
+        finish<YE>(X[s - 1], C[s - 1], o, j, qs);
       } else {
 #pragma unroll
-        for (int v = 0; v < V; ++v) o[v] = C[s - 1][v];
+        for (int v = 0; v < V; ++v) o[v] = C[s - 1][v];  // surplus level: forward its input row
       }
       if constexpr (ACC) {
         if (s < K) {
-          const bool add = FULL ? (s < K) : (s < a.keff);
+          const bool add = FULL ? true : (s < keff);
 #pragma unroll
           for (int v = 0; v < V; ++v) {
             const float prev = (s == 1) ? C[0][v] : Pp[s - 1][v];
@@ -205,16 +246,14 @@ struct Tb2dTile {
       }
       if (s < K) {
 #pragma unroll
-        for (int v = 0; v < V; ++v) N[s][v] = o[v];
-      } else {
-        if (j >= y0 && j < y1) {
-          store_row<XE>(j, o, a.dst);
-          if constexpr (ACC) {
-            float e[V];
+        for (int v = 0; v < V; ++v) X[s][v] = o[v];
+      } else if (j >= y0 && j < y1) {
+        store_row<XE>(j, o, a.dst);
+        if constexpr (ACC) {
+          float e[V];
 #pragma unroll
-            for (int v = 0; v < V; ++v) e[v] = (K == 1) ? C[0][v] : Pp[K - 1][v];
-            accum_gp<XE>(j, e);
-          }
+          for (int v = 0; v < V; ++v) e[v] = (K == 1) ? C[0][v] : Pp[K - 1][v];
+          accum_gp<XE>(j, e);
         }
       }
     }
@@ -230,7 +269,7 @@ struct Tb2dTile {
   template <bool XE, bool YE, bool VEC>
   __device__ __forceinline__ void run() {
 #pragma unroll
-    for (int b = 0; b < 3; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int s = 0; s < K; ++s)
 #pragma unroll
@@ -242,17 +281,16 @@ struct Tb2dTile {
         for (int v = 0; v < V; ++v) Pp[s][v] = 0.0f;
     }
     const int keff = FULL ? K : a.keff;
-    const int r0 = y0 - keff;
+    // input rows from y1-1+keff down to y0-keff; level K emits row r+K
+    const int r0 = y1 - 1 + keff;
     int nit = (y1 - y0) + keff + K;
-    nit = (nit + 2) / 3 * 3;  // extra iterations only touch rows outside [y0, y1)
+    nit = (nit + 1) & ~1;  // the extra iteration only touches rows outside [y0, y1)
     slot0 = 0;
-    prefetch<VEC>(r0 + 0, 0);
-    prefetch<VEC>(r0 + 1, 1);
-    prefetch<VEC>(r0 + 2, 2);
-    for (int it = 0; it < nit; it += 3) {
-      step<0, XE, YE, VEC>(r0 + it);
-      step<1, XE, YE, VEC>(r0 + it + 1);
-      step<2, XE, YE, VEC>(r0 + it + 2);
+    prefetch<VEC>(r0, 0);
+    prefetch<VEC>(r0 - 1, 1);
+    for (int it = 0; it < nit; it += 2) {
+      step<0, XE, YE, VEC>(r0 - it);
+      step<1, XE, YE, VEC>(r0 - it - 1);
     }
   }
 

@@ -8,17 +8,22 @@
 //   * A workgroup of NW wavefronts owns a window of (64*V) x (R*NW) cells in x-y.  Lane l
 //     of wave w holds the V x R patch x in [xw + l*V, +V), y in [yw + w*R, +R) of every plane,
 //     so each row of a plane is one coalesced 8-byte access per lane.
-//   * The k time levels are a 3-plane rotating window per level held in registers (the
-//     register analogue of the paper's 3D shift register, Eq. 1); the plane loop is unrolled
-//     by three so the rotation is register renaming.
+//   * Planes stream upwards in z.  Level s (1..K) computes plane r-s while level 0 receives
+//     plane r.  The canonical term order (centre, x-1, x+1, y+1, y-1, z-1, z+1) ends with the
+//     plane that arrived first (z-1) followed by the plane that arrives last (z+1), so each
+//     iteration runs in two phases: (1) for every level, fold the centre plane (with its
+//     in-plane neighbours) and the oldest plane into a partial sum, freeing the oldest
+//     plane's registers; (2) walking up the levels, add the z+1 term from the plane the level
+//     below has just produced.  Each level keeps two planes in registers (the register
+//     analogue of the paper's 3D shift register, Eq. 1); the plane loop, unrolled by two,
+//     renames them without copies.
 //   * In-plane neighbours: x across lanes by DPP wave shifts, y inside a lane's R rows
-//     directly, and y across waves through LDS: each wave publishes the top and bottom rows
-//     of every new level plane, one barrier per plane makes them visible (double-buffered by
-//     plane parity), so all k levels of a plane share one barrier.
-//   * z-neighbours are the rotating planes.  Clamp-to-edge is applied per level by using
-//     the cell's own value for an out-of-grid neighbour; tiles that touch no x/y edge run
-//     code with no boundary handling, and the z edges cost only on the few planes that meet
-//     them.
+//     directly, and y across waves through LDS: every new level plane publishes its first
+//     and last rows, and one barrier per plane (double-buffered by plane parity) makes them
+//     visible to the next plane's phase 1, for all k levels at once.
+//   * Clamp-to-edge is applied per level by using the cell's own value for an out-of-grid
+//     neighbour; tiles that touch no x/y edge run code with no boundary handling, and the z
+//     edges cost only on the few planes that meet them.
 //   * Hotspot: the source q = fma(cp, p, kamb) is re-formed per level from the power plane
 //     (an L2 hit after the first level), keeping registers for the k-level window.
 //   * Adjoint: transposed operator (mirrored weights, zero outside the grid, self term with
@@ -49,8 +54,8 @@ struct Tb3dTile {
   const Tb3dArgs& a;
   const int lane, wave;
   int xw, yw, ox0, ox1, oy0, oy1, z0, z1;
-  float S[3][K][R][V];
-  float Lb[R][V];     // next input plane (loaded one iteration ahead)
+  float S[2][K][R][V];  // per level: centre plane and oldest/partial/newest plane, alternating
+  float Lb[R][V];       // next input plane (loaded one iteration ahead)
   float Pp[K][R][V];
   float cxm[V], cxp[V];
   bool isL[V], isR[V];
@@ -93,11 +98,11 @@ struct Tb3dTile {
     }
   }
 
-  // level: out plane j from (Pl = plane j-1, Cl = plane j, Nl = plane j+1) of the level below;
-  // Cl's cross-wave neighbour rows come from LDS buffer rbuf.
+  // Phase 1: in-plane terms of centre plane Cl (cross-wave rows from LDS buffer rbuf) and the
+  // z-1 term of the oldest plane Pl, for output plane j.
   template <bool XE, bool YE, bool ZE>
-  __device__ __forceinline__ void level(const float (&Pl)[R][V], const float (&Cl)[R][V], const float (&Nl)[R][V],
-                                        float (&o)[R][V], int lev_in, int rbuf, int j) const {
+  __device__ __forceinline__ void partial(const float (&Pl)[R][V], const float (&Cl)[R][V], float (&o)[R][V],
+                                          int lev_in, int rbuf, int j) const {
     float hn[V], hs[V];
     {
       const int wn = wave > 0 ? wave - 1 : 0;
@@ -111,26 +116,9 @@ struct Tb3dTile {
       }
     }
     const bool zlo = ZE && (j == 0);
-    const bool zhi = ZE && (j == a.nz - 1);
-    float czm = a.cf.wz_m, czp = a.cf.wz_p;
+    float czm = a.cf.wz_m;
     if constexpr (ADJ && ZE) {
       if (zlo) czm = a.cf.wz_p;
-      if (zhi) czp = a.cf.wz_m;
-    }
-    float q[R][V];
-    if constexpr (HOT && !ADJ) {
-      const int zc = clampi(j, 0, a.nz - 1);
-      const float* pl = a.power + (size_t)zc * a.ny * a.nx;
-      const int x0 = xw + lane * V;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int y = clampi(yw + wave * R + r, 0, a.ny - 1);
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          const int x = XE ? clampi(x0 + v, 0, a.nx - 1) : x0 + v;
-          q[r][v] = __builtin_fmaf(a.cf.cp, pl[(size_t)y * a.nx + x], a.cf.kamb);
-        }
-      }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -148,7 +136,7 @@ struct Tb3dTile {
         float xp = (v < V - 1) ? Cl[r][v + 1] : eu;
         float ym = (r > 0) ? Cl[r - 1][v] : hn[v];
         float yp = (r < R - 1) ? Cl[r + 1][v] : hs[v];
-        float zm = Pl[r][v], zp = Nl[r][v];
+        float zm = Pl[r][v];
         float wxm = a.cf.wx_m, wxp = a.cf.wx_p;
         if constexpr (XE) {
           xm = isL[v] ? c : xm;
@@ -160,17 +148,53 @@ struct Tb3dTile {
           ym = rowTop[r] ? c : ym;
           yp = rowBot[r] ? c : yp;
         }
-        if constexpr (ZE) {
-          zm = zlo ? c : zm;
-          zp = zhi ? c : zp;
-        }
+        if constexpr (ZE) zm = zlo ? c : zm;
         float acc = upd2(a.cf.c0, c, wxm, xm, wxp, xp, cyp, yp, cym, ym);
         acc = __builtin_fmaf(czm, zm, acc);
-        acc = __builtin_fmaf(czp, zp, acc);
-        if constexpr (HOT && !ADJ) acc = acc + q[r][v];
         o[r][v] = acc;
       }
     }
+  }
+
+  // Phase 2: z+1 term from the newest plane Nl of the level below, then the source.
+  template <bool XE, bool ZE>
+  __device__ __forceinline__ void finish(const float (&Nl)[R][V], const float (&Cl)[R][V], float (&o)[R][V],
+                                         int j) const {
+    const bool zhi = ZE && (j == a.nz - 1);
+    float czp = a.cf.wz_p;
+    if constexpr (ADJ && ZE) {
+      if (zhi) czp = a.cf.wz_m;
+    }
+    float q[R][V];
+    if constexpr (HOT && !ADJ) {
+      const int zc = clampi(j, 0, a.nz - 1);
+      const float* pl = a.power + (size_t)zc * a.ny * a.nx;
+      const int x0 = xw + lane * V;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int y = clampi(yw + wave * R + r, 0, a.ny - 1);
+        const float* rowp = pl + (size_t)y * a.nx;
+        if constexpr (!XE && V == 2) {
+          const float2 t = *reinterpret_cast<const float2*>(rowp + x0);
+          q[r][0] = __builtin_fmaf(a.cf.cp, t.x, a.cf.kamb);
+          q[r][1] = __builtin_fmaf(a.cf.cp, t.y, a.cf.kamb);
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+            q[r][v] = __builtin_fmaf(a.cf.cp, rowp[XE ? clampi(x0 + v, 0, a.nx - 1) : x0 + v], a.cf.kamb);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        float zp = Nl[r][v];
+        if constexpr (ZE) zp = zhi ? Cl[r][v] : zp;
+        float acc = __builtin_fmaf(czp, zp, o[r][v]);
+        if constexpr (HOT && !ADJ) acc = acc + q[r][v];
+        o[r][v] = acc;
+      }
   }
 
   template <bool XE>
@@ -182,8 +206,8 @@ struct Tb3dTile {
       const int y = yw + wave * R + r;
       if (y < oy0 || y >= oy1) continue;
       float* rowp = pl + (size_t)y * a.nx;
-      if constexpr (!XE && V == 2) {
-        if (x0 >= ox0 && x0 < ox1) *reinterpret_cast<float2*>(rowp + x0) = make_float2(o[r][0], o[r][1]);
+      if (!XE && V == 2 && x0 >= ox0 && x0 + V <= ox1) {
+        *reinterpret_cast<float2*>(rowp + x0) = make_float2(o[r][0], o[r][V - 1]);
       } else {
 #pragma unroll
         for (int v = 0; v < V; ++v)
@@ -206,29 +230,53 @@ struct Tb3dTile {
     }
   }
 
-  // Iteration with input plane r: level s computes plane r - s.  The level-u plane made in
-  // this iteration is published in LDS buffer wbuf; the planes consumed as centres were
-  // published in the previous iteration (buffer wbuf ^ 1).
+  // Iteration with input plane r: level s computes plane r - s.  Planes made in this
+  // iteration publish their edge rows in LDS buffer ROT; phase 1 reads the centre planes'
+  // edge rows published in the previous iteration (buffer ROT ^ 1).
   template <int ROT, bool XE, bool YE, bool ZE>
-  __device__ __forceinline__ void step(int r, int wbuf) {
-    float (&P)[K][R][V] = S[ROT % 3];
-    float (&C)[K][R][V] = S[(ROT + 1) % 3];
-    float (&N)[K][R][V] = S[(ROT + 2) % 3];
+  __device__ __forceinline__ void step(int r) {
+    float (&X)[K][R][V] = S[ROT];      // oldest planes on entry, partial sums, newest on exit
+    float (&C)[K][R][V] = S[ROT ^ 1];  // centre planes
+    const int keff = FULL ? K : a.keff;
+    float part_top[R][V];
+#pragma unroll
+    for (int s = K; s >= 1; --s) {
+      const int j = r - s;
+      float o[R][V];
+      if (FULL || s <= keff) {
+        partial<XE, YE, ZE>(X[s - 1], C[s - 1], o, s - 1, ROT ^ 1, j);
+      } else {
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+          for (int v = 0; v < V; ++v) o[rr][v] = 0.0f;
+      }
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          if (s == K) part_top[rr][v] = o[rr][v];
+          else X[s][rr][v] = o[rr][v];
+        }
+    }
 #pragma unroll
     for (int rr = 0; rr < R; ++rr)
 #pragma unroll
-      for (int v = 0; v < V; ++v) N[0][rr][v] = Lb[rr][v];
+      for (int v = 0; v < V; ++v) X[0][rr][v] = Lb[rr][v];
     load_plane<XE>(r + 1, Lb, a.src);
-    publish(wbuf, 0, N[0]);
-    const int rbuf = wbuf ^ 1;
+    publish(ROT, 0, X[0]);
     float Pn[K][R][V];
     (void)Pn;
 #pragma unroll
     for (int s = 1; s <= K; ++s) {
       const int j = r - s;
       float o[R][V];
-      if (FULL || s <= a.keff) {
-        level<XE, YE, ZE>(P[s - 1], C[s - 1], N[s - 1], o, s - 1, rbuf, j);
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+        for (int v = 0; v < V; ++v) o[rr][v] = (s == K) ? part_top[rr][v] : X[s][rr][v];
+      if (FULL || s <= keff) {
+        finish<XE, ZE>(X[s - 1], C[s - 1], o, j);
       } else {
 #pragma unroll
         for (int rr = 0; rr < R; ++rr)
@@ -237,7 +285,7 @@ struct Tb3dTile {
       }
       if constexpr (ACC) {
         if (s < K) {
-          const bool add = FULL ? true : (s < a.keff);
+          const bool add = FULL ? true : (s < keff);
 #pragma unroll
           for (int rr = 0; rr < R; ++rr)
 #pragma unroll
@@ -251,8 +299,8 @@ struct Tb3dTile {
 #pragma unroll
         for (int rr = 0; rr < R; ++rr)
 #pragma unroll
-          for (int v = 0; v < V; ++v) N[s][rr][v] = o[rr][v];
-        publish(wbuf, s, o);
+          for (int v = 0; v < V; ++v) X[s][rr][v] = o[rr][v];
+        publish(ROT, s, o);
       } else if (j >= z0 && j < z1) {
         store_plane<XE>(j, o);
         if constexpr (ACC) {
@@ -279,7 +327,7 @@ struct Tb3dTile {
   template <bool XE, bool YE>
   __device__ __forceinline__ void run() {
 #pragma unroll
-    for (int b = 0; b < 3; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int s = 0; s < K; ++s)
 #pragma unroll
@@ -297,34 +345,28 @@ struct Tb3dTile {
     const int keff = FULL ? K : a.keff;
     const int r0 = z0 - keff;
     int nit = (z1 - z0) + keff + K;
-    nit = (nit + 2) / 3 * 3;
+    nit = (nit + 1) & ~1;
     load_plane<XE>(r0, Lb, a.src);
-    // Groups of three iterations that compute a plane at a z edge form a prefix (z = 0) and
-    // a suffix (z = nz-1) of the loop; they run a body with z-edge handling, the rest a body
-    // without it.  Separate loops (rather than a branch inside one loop) keep the register
-    // allocation of the hot body free of merge copies.
-    int it = 0, wbuf = 0;
+    // Pairs of iterations that compute a plane at a z edge form a prefix (z = 0) and a suffix
+    // (z = nz-1) of the loop; they run a body with z-edge handling, the rest a body without
+    // it.  Separate loops (rather than a branch inside one loop) keep the register allocation
+    // of the hot body free of merge copies.
+    int it = 0;
     auto edge = [&](int i) {
       const int r = r0 + i;
-      return (r - K <= 0 && r + 1 >= 0) || (r - K <= a.nz - 1 && r + 1 >= a.nz - 1);
+      return (r - K <= 0 && r >= 0) || (r - K <= a.nz - 1 && r >= a.nz - 1);
     };
-    for (; it < nit && edge(it); it += 3) {
-      step<0, XE, YE, true>(r0 + it, wbuf);
-      step<1, XE, YE, true>(r0 + it + 1, wbuf ^ 1);
-      step<2, XE, YE, true>(r0 + it + 2, wbuf);
-      wbuf ^= 1;
+    for (; it < nit && edge(it); it += 2) {
+      step<0, XE, YE, true>(r0 + it);
+      step<1, XE, YE, true>(r0 + it + 1);
     }
-    for (; it < nit && !edge(it); it += 3) {
-      step<0, XE, YE, false>(r0 + it, wbuf);
-      step<1, XE, YE, false>(r0 + it + 1, wbuf ^ 1);
-      step<2, XE, YE, false>(r0 + it + 2, wbuf);
-      wbuf ^= 1;
+    for (; it < nit && !edge(it); it += 2) {
+      step<0, XE, YE, false>(r0 + it);
+      step<1, XE, YE, false>(r0 + it + 1);
     }
-    for (; it < nit; it += 3) {
-      step<0, XE, YE, true>(r0 + it, wbuf);
-      step<1, XE, YE, true>(r0 + it + 1, wbuf ^ 1);
-      step<2, XE, YE, true>(r0 + it + 2, wbuf);
-      wbuf ^= 1;
+    for (; it < nit; it += 2) {
+      step<0, XE, YE, true>(r0 + it);
+      step<1, XE, YE, true>(r0 + it + 1);
     }
   }
 
@@ -374,6 +416,7 @@ __global__ __launch_bounds__(64 * NW) void tb3d_kernel(Tb3dArgs a) {
   __shared__ __align__(16) float hal[2 * K * NW * 2 * 64 * V];
   const int ntiles = a.ntx * a.nty * a.nsegz;
   const int tile = xcd_remap(blockIdx.x, ntiles);
-  Tb3dTile<K, V, R, NW, HOT, ADJ, ACC, FULL> t(a, threadIdx.x & 63, threadIdx.x >> 6, hal);
+  Tb3dTile<K, V, R, NW, HOT, ADJ, ACC, FULL> t(a, threadIdx.x & 63, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+                                                hal);
   t.process(tile);
 }

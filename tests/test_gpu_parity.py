@@ -66,7 +66,7 @@ SHAPES_2D = [(256, 256), (131, 257), (1, 300), (300, 1), (5, 7), (3, 1000), (700
 
 
 @pytest.mark.parametrize("shape", SHAPES_2D)
-@pytest.mark.parametrize("k", [4, 8, 12, 16])
+@pytest.mark.parametrize("k", [4, 8, 12, 16, 20, 24])
 def test_forward_2d_diffusion_all_k(shape, k):
     x0 = uniform(shape, 0.0, 1.0, 1000 + k)
     for T in sorted({0, 1, k - 1, k, k + 1, 3 * k + 2}):
@@ -108,7 +108,7 @@ SHAPES_3D = [(6, 6, 6), (1, 40, 37), (20, 1, 33), (9, 70, 130), (33, 50, 129), (
 
 
 @pytest.mark.parametrize("shape", SHAPES_3D)
-@pytest.mark.parametrize("k", [1, 2, 3, 4])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
 def test_forward_3d_diffusion_all_k(shape, k):
     x0 = uniform(shape, 0.0, 1.0, 3000 + k)
     for T in sorted({0, 1, k, k + 1, 3 * k + 2}):
@@ -116,7 +116,7 @@ def test_forward_3d_diffusion_all_k(shape, k):
 
 
 @pytest.mark.parametrize("shape", [(6, 6, 6), (17, 45, 131), (1, 60, 61)])
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_forward_3d_hotspot_all_k(shape, k):
     x0 = uniform(shape, 300.0, 350.0, 4000 + k)
     p = uniform(shape, 0.0, 1e-3, 4001 + k)
@@ -153,12 +153,12 @@ def gpu_adjoint(g, cf, T, form, tuning=None, recompute=0, x0=None, power=None, c
                                              ((1, 50), "AH2", HOTSPOT), ((40, 1), "A2", DIFFUSION),
                                              ((9, 70, 130), "A3", DIFFUSION), ((13, 45, 61), "AH3", HOTSPOT),
                                              ((1, 20, 30), "AH3", HOTSPOT), ((5, 1, 9), "A3", DIFFUSION)])
-@pytest.mark.parametrize("variant", [1, 2])
-def test_adjoint_matches_oracle(shape, cset, form, variant):
+@pytest.mark.parametrize("variant,k2,k3", [(1, 0, 0), (2, 4, 1), (2, 8, 2), (2, 12, 3), (2, 12, 4)])
+def test_adjoint_matches_oracle(shape, cset, form, variant, k2, k3):
     cf = SETS[cset]
     g = uniform(shape, -1.0, 1.0, 5000)
     for T in (1, 5, 13):
-        gx, gp = gpu_adjoint(g, cf, T, form, tuning={"variant": variant, "k": 4 if len(shape) == 2 else 3,
+        gx, gp = gpu_adjoint(g, cf, T, form, tuning={"variant": variant, "k": k2 if len(shape) == 2 else k3,
                                                      "seg_len": 20})
         rx, rp = oracle.adjoint(g, cf, T, form=form)
         assert normrel(gx, rx) <= TOL, (shape, cset, T)
