@@ -14,9 +14,10 @@
  *     every direction and at every step (Section 5.1).
  *   - One time step (Section 2.1, Table 2) reads every cell from one buffer and writes
  *       out = cc*c + cw*w + ce*e + cs*s + cn*n [+ cb*b + ca*a]   (diffusion)
- *       out = (same weighted sum) + q,  q = fma(cp, p, c_amb*t_amb)  (hotspot)
- *     evaluated as the FMA chain c, w, e, s, n, b, a then + q, with k_amb = c_amb*t_amb
- *     rounded once in FP32.  Steps are Jacobi (out-of-place, ping-pong).
+ *       out = q + (same weighted sum),  q = fma(cp, p, c_amb*t_amb)  (hotspot)
+ *     evaluated as the FMA chain c, w, e, s, n, b, a; for hotspot the chain starts from
+ *     fma(cc, c, q), with k_amb = c_amb*t_amb rounded once in FP32.  Steps are Jacobi
+ *     (out-of-place, ping-pong).
  *   - Pointers named "device" must be device memory of the current HIP device, 16-byte
  *     aligned for the fast path (4-byte aligned is accepted), and must not alias each
  *     other.  The caller owns them and keeps them alive until the stream work completes.

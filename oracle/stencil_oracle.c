@@ -21,10 +21,11 @@
  *     boundary cell itself (clamp-to-edge), in every direction and at every step.
  *
  * Evaluation order (the paper does not fix one; this is the reading used throughout):
- *   acc = cc*c; acc = fma(cw,w,acc); acc = fma(ce,e,acc); acc = fma(cs,s,acc);
- *   acc = fma(cn,n,acc); [3D: acc = fma(cb,b,acc); acc = fma(ca,a,acc)];
- *   hotspot: acc = acc + q, with the time-invariant source q = fma(cp, p, k_amb) and
- *            k_amb = c_amb*t_amb rounded once in the working precision.
+ *   diffusion: acc = cc*c;
+ *   hotspot:   acc = fma(cc, c, q), where the time-invariant source q = fma(cp, p, k_amb)
+ *              (k_amb = c_amb*t_amb rounded once in the working precision) starts the sum;
+ *   then acc = fma(cw,w,acc); acc = fma(ce,e,acc); acc = fma(cs,s,acc); acc = fma(cn,n,acc);
+ *   [3D: acc = fma(cb,b,acc); acc = fma(ca,a,acc)].
  * Two instantiations are built from the same text: FP64 (coefficients promoted from their
  * FP32 values) and FP32.  Compile with -ffp-contract=off so no other fusion happens.
  *
@@ -96,7 +97,7 @@ int oracle_num_threads(void) {
           const REAL* qr = q ? q + (z * ny + y) * nx : NULL;                                  \
           for (long x = 0; x < nx; ++x) {                                                     \
             const long xm = clampl(x - 1, 0, nx - 1), xp = clampl(x + 1, 0, nx - 1);          \
-            REAL acc = cc * row[x];                                                           \
+            REAL acc = qr ? FMA(cc, row[x], qr[x]) : cc * row[x];                             \
             acc = FMA(cw, row[xm], acc);                                                      \
             acc = FMA(ce, row[xp], acc);                                                      \
             acc = FMA(cs, rs[x], acc);                                                        \
@@ -105,7 +106,6 @@ int oracle_num_threads(void) {
               acc = FMA(cb, rb[x], acc);                                                      \
               acc = FMA(ca, ra[x], acc);                                                      \
             }                                                                                 \
-            if (qr) acc = acc + qr[x];                                                        \
             out[x] = acc;                                                                     \
           }                                                                                   \
         }                                                                                     \
