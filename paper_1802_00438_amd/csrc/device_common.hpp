@@ -13,10 +13,18 @@ struct DevCoef {
 };
 
 // The canonical evaluation order of one cell update: centre, x-1, x+1, y+1, y-1, z-1, z+1
-// (the term order of Table 2), every step an FP32 fused multiply-add.
+// (the term order of Table 2), every step an FP32 fused multiply-add.  The hotspot source q
+// (time-invariant) starts the sum: acc = fma(c0, c, q); diffusion starts from c0 * c.
+template <bool SRC>
+__device__ __forceinline__ float centre_term(float c0, float c, float q) {
+  if constexpr (SRC) return __builtin_fmaf(c0, c, q);
+  else return c0 * c;
+}
+
+template <bool SRC = false>
 __device__ __forceinline__ float upd2(float c0, float c, float wxm, float xm, float wxp, float xp,
-                                      float wyp, float yp, float wym, float ym) {
-  float acc = c0 * c;
+                                      float wyp, float yp, float wym, float ym, float q = 0.0f) {
+  float acc = centre_term<SRC>(c0, c, q);
   acc = __builtin_fmaf(wxm, xm, acc);
   acc = __builtin_fmaf(wxp, xp, acc);
   acc = __builtin_fmaf(wyp, yp, acc);

@@ -34,10 +34,13 @@ hipError_t launch_tb3d_diff(int K, bool full, const Tb3dArgs& a, hipStream_t s);
 hipError_t launch_tb3d_hot(int K, bool full, const Tb3dArgs& a, hipStream_t s);
 hipError_t launch_tb3d_adj(int K, bool acc, bool full, const Tb3dArgs& a, hipStream_t s);
 
+// Rows in flight per wave: four for diffusion, two where the hotspot source ring or the
+// adjoint's running sums already take the registers (three resp. two waves per SIMD).
+#define TB2D_DEPTH(HOT, ADJ) (((HOT) || (ADJ)) ? 2 : 4)
 #define TB_LAUNCH2D(K, HOT, ADJ, ACC, FULL, a, s)                                                       \
   do {                                                                                                  \
-    hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL>), dim3((a).ntx * (a).nseg), dim3(64), \
-                       0, s, a);                                                                        \
+    hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL, TB2D_DEPTH(HOT, ADJ)>),             \
+                       dim3((a).ntx * (a).nseg), dim3(64), 0, s, a);                                    \
     return hipGetLastError();                                                                           \
   } while (0)
 #define TB_LAUNCH3D(K, R, NW, HOT, ADJ, ACC, FULL, a, s)                                               \

@@ -93,6 +93,8 @@ __global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
         if (rr) wxp = a.cf.wx_m;
       }
       float acc;
+      float q = 0.0f;
+      if constexpr (HOT && !ADJ) q = __builtin_fmaf(a.cf.cp, p4[v], a.cf.kamb);
       if (a.ndim == 2) {
         // streamed axis is y: prv = row y-1, nxt = row y+1
         float cym = a.cf.wy_m, cyp = a.cf.wy_p;
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
           if (slo) cym = a.cf.wy_p;
           if (shi) cyp = a.cf.wy_m;
         }
-        acc = upd2(a.cf.c0, c, wxm, xm, wxp, xp, cyp, shi ? c : nxt[v], cym, slo ? c : prv[v]);
+        acc = upd2<HOT && !ADJ>(a.cf.c0, c, wxm, xm, wxp, xp, cyp, shi ? c : nxt[v], cym, slo ? c : prv[v], q);
       } else {
         float cym = a.cf.wy_m, cyp = a.cf.wy_p, czm = a.cf.wz_m, czp = a.cf.wz_p;
         if constexpr (ADJ) {
@@ -109,11 +111,10 @@ __global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
           if (slo) czm = a.cf.wz_p;
           if (shi) czp = a.cf.wz_m;
         }
-        acc = upd2(a.cf.c0, c, wxm, xm, wxp, xp, cyp, bot ? c : ys[v], cym, top ? c : yn[v]);
+        acc = upd2<HOT && !ADJ>(a.cf.c0, c, wxm, xm, wxp, xp, cyp, bot ? c : ys[v], cym, top ? c : yn[v], q);
         acc = __builtin_fmaf(czm, slo ? c : prv[v], acc);
         acc = __builtin_fmaf(czp, shi ? c : nxt[v], acc);
       }
-      if constexpr (HOT && !ADJ) acc = acc + __builtin_fmaf(a.cf.cp, p4[v], a.cf.kamb);
       o[v] = acc;
       if constexpr (ACC) g4[v] = __builtin_fmaf(a.cf.cp, c, g4[v]);
     }

@@ -344,7 +344,14 @@ stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out) {
   for (int i = 0; i < nk; ++i) {
     const int K = ks[i];
     if (p->ndim == 2) {
-      for (int wpc : {4, 8, 12, 16}) {
+      // segment lengths that keep several waves per SIMD busy; odd multiples of 32 rows avoid
+      // every tile starting on the same power-of-two row stride
+      for (int seg : {96, 128, 160, 192, 224, 288, 352, 480, 608}) {
+        if (seg < 2 * K && seg < p->ny) continue;
+        const Geom2D g = geom2d(K, p->nx, p->ny, seg);
+        cands.push_back({K, g.seg, model_time_2d(g, p->nx, p->ny, Tref, hot, false)});
+      }
+      for (int wpc : {8, 12}) {
         const int seg = pick_seg2d(K, p->nx, p->ny, wpc);
         const Geom2D g = geom2d(K, p->nx, p->ny, seg);
         cands.push_back({K, seg, model_time_2d(g, p->nx, p->ny, Tref, hot, false)});
@@ -354,6 +361,11 @@ stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out) {
         const int segz = pick_segz3d(K, false, p->nx, p->ny, p->nz, wpc);
         const Geom3D g = geom3d(K, false, p->nx, p->ny, p->nz, segz);
         cands.push_back({K, segz, model_time_3d(g, p->nx, p->ny, p->nz, Tref, hot, false)});
+      }
+      for (int segz : {32, 48, 64, 96, 128, 192, 256}) {
+        if (segz > p->nz) continue;
+        const Geom3D g = geom3d(K, false, p->nx, p->ny, p->nz, segz);
+        cands.push_back({K, g.segz, model_time_3d(g, p->nx, p->ny, p->nz, Tref, hot, false)});
       }
     }
   }
@@ -371,48 +383,69 @@ stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out) {
   best.seg_len = uniq[0].seg;
   const bool timed = !env_flag("STENCIL_MODEL_ONLY") && p->cells >= (size_t)1 << 16;
   if (timed) {
-    // time the top candidates: two passes each on scratch + a temporary buffer
+    // Time the top candidates on scratch memory.
+    // Hotspot trials read a power map of their own: sharing the source buffer would hide a
+    // third of the pass's HBM reads and favour small k.
     float* tmp = nullptr;
-    if (hipMalloc(&tmp, p->cells * sizeof(float)) == hipSuccess) {
+    float* pw = nullptr;
+    const bool have = hipMalloc(&tmp, p->cells * sizeof(float)) == hipSuccess &&
+                      (!hot || hipMalloc(&pw, p->cells * sizeof(float)) == hipSuccess);
+    if (have) {
       launch_fill(tmp, p->cells, 0.5f, p->stream);
       launch_fill(p->scratch, p->cells, 0.5f, p->stream);
+      if (pw) launch_fill(pw, p->cells, 0.0f, p->stream);
       stencil_coeffs_t c{};
       c.cc = 0.5f; c.cw = c.ce = c.cn = c.cs = 0.125f; c.cb = c.ca = 0.0f;
       const DevCoef cf = dev_coef(c, false);
       hipEvent_t e0, e1;
       hipEventCreate(&e0);
       hipEventCreate(&e1);
-      double best_rate = 0;
-      const int ntop = std::min<int>(5, (int)uniq.size());
-      for (int i = 0; i < ntop; ++i) {
+      const int ntop = std::min<int>(12, (int)uniq.size());
+      // Each candidate runs `reps` back-to-back passes (at least ~4 ms of work at 3.5e12
+      // updates/s, so launch gaps and timer resolution stay small), in two rounds over the
+      // list after a warm-up that brings the clocks up; the best of the two rounds counts.
+      auto time_cand = [&](const Cand& cd) -> double {
         stencil_plan_s q = *p;
-        q.tuning.k = uniq[i].K;
-        q.tuning.seg_len = uniq[i].seg;
-        // warm-up pass, then two timed passes
-        run_pass(&q, m, uniq[i].K, uniq[i].K, tmp, p->scratch, hot ? tmp : nullptr, nullptr, cf);
+        q.tuning.k = cd.K;
+        q.tuning.seg_len = cd.seg;
+        const double per_pass = (double)cd.K * (double)p->cells;
+        const int reps = std::max(2, std::min(64, (int)std::ceil(1.4e10 / per_pass)));
+        run_pass(&q, m, cd.K, cd.K, tmp, p->scratch, pw, nullptr, cf);
         hipEventRecord(e0, p->stream);
-        run_pass(&q, m, uniq[i].K, uniq[i].K, p->scratch, tmp, hot ? p->scratch : nullptr, nullptr, cf);
-        run_pass(&q, m, uniq[i].K, uniq[i].K, tmp, p->scratch, hot ? tmp : nullptr, nullptr, cf);
+        for (int r = 0; r < reps; ++r) {
+          const bool even = (r % 2) == 0;
+          float* s = even ? p->scratch : tmp;
+          float* d = even ? tmp : p->scratch;
+          run_pass(&q, m, cd.K, cd.K, s, d, pw, nullptr, cf);
+        }
         hipEventRecord(e1, p->stream);
         hipEventSynchronize(e1);
         float ms = 0;
         hipEventElapsedTime(&ms, e0, e1);
-        const double rate = 2.0 * uniq[i].K * (double)p->cells / (ms * 1e-3);  // cell updates / s
+        return ms > 0 ? reps * per_pass / (ms * 1e-3) : 0.0;  // cell updates / s
+      };
+      for (int w = 0; w < 3; ++w) time_cand(uniq[0]);
+      std::vector<double> rate(ntop, 0.0);
+      for (int round = 0; round < 2; ++round)
+        for (int i = 0; i < ntop; ++i) rate[i] = std::max(rate[i], time_cand(uniq[i]));
+      double best_rate = 0;
+      for (int i = 0; i < ntop; ++i) {
         if (log_enabled())
           std::fprintf(stderr, "[stencil] tune K=%d seg=%d model=%.3g ms measured=%.1f GCell/s\n", uniq[i].K,
-                       uniq[i].seg, uniq[i].model * 1e3, rate * 1e-9);
-        if (rate > best_rate) {
-          best_rate = rate;
+                       uniq[i].seg, uniq[i].model * 1e3, rate[i] * 1e-9);
+        if (rate[i] > best_rate) {
+          best_rate = rate[i];
           best.k = uniq[i].K;
           best.seg_len = uniq[i].seg;
         }
       }
       hipEventDestroy(e0);
       hipEventDestroy(e1);
-      hipStreamSynchronize(p->stream);
-      hipFree(tmp);
-      hipGetLastError();
     }
+    hipStreamSynchronize(p->stream);
+    if (tmp) hipFree(tmp);
+    if (pw) hipFree(pw);
+    hipGetLastError();
   }
   if (log_enabled())
     std::fprintf(stderr, "[stencil] plan form=%d ndim=%d %dx%dx%d -> k=%d seg=%d\n", p->form, p->ndim, p->nx, p->ny,

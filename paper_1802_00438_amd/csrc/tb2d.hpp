@@ -53,9 +53,10 @@ struct Tb2dArgs {
   DevCoef cf;
 };
 
-template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL>
+template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL, int D = 2>
 struct Tb2dTile {
   static_assert(V == 4 || V == 8, "V");
+  static_assert(D == 2 || D == 4 || D == 6, "prefetch depth must be even");
   static constexpr int W = 64 * V;    // window width
   static constexpr int RING = K + 1;  // hotspot source rows kept in LDS
 
@@ -63,8 +64,8 @@ struct Tb2dTile {
   const int lane;
   int ws, ox0, ox1, y0, y1;
   float S[2][K][V];  // per level: [0] and [1] alternate between "centre" and "oldest/new"
-  float Lb[2][V];    // prefetched input rows
-  float Pb[2][V];    // prefetched power rows
+  float Lb[D][V];    // prefetched input rows (D rows in flight)
+  float Pb[D][V];    // prefetched power rows
   float Pp[K][V];    // adjoint: running sums carried along the level pipeline
   float cxm[V], cxp[V];
   bool isL[V], isR[V];
@@ -96,9 +97,24 @@ struct Tb2dTile {
     if constexpr (HOT && !ADJ) load_row<VEC>(r, Pb[b], a.power);
   }
 
-  // Phase 1 of a level: centre, x-1, x+1 and y+1 terms of row j (oldest row Pr = y+1).
+  // Source row of level s (row r+s entered the ring s iterations ago).
+  __device__ __forceinline__ void read_q(int s, float (&q)[V]) const {
+    if constexpr (HOT && !ADJ) {
+      int qs = slot0 - s;
+      if (qs < 0) qs += RING;
+      const float* qp = ring + qs * W + lane * V;
+#pragma unroll
+      for (int h = 0; h < V; h += 4) {
+        const float4 t = *reinterpret_cast<const float4*>(qp + h);
+        q[h] = t.x; q[h + 1] = t.y; q[h + 2] = t.z; q[h + 3] = t.w;
+      }
+    }
+  }
+
+  // Phase 1 of a level: source, centre, x-1, x+1 and y+1 terms of row j (oldest row Pr = y+1).
   template <bool XE, bool YE>
-  __device__ __forceinline__ void partial(const float (&Pr)[V], const float (&Cr)[V], float (&o)[V], int j) const {
+  __device__ __forceinline__ void partial(const float (&Pr)[V], const float (&Cr)[V], float (&o)[V], int j,
+                                          const float (&q)[V]) const {
     const float wl = from_lower(Cr[V - 1]);
     const float eu = from_upper(Cr[0]);
     const bool bot = YE && (j == a.ny - 1);  // y+1 leaves the grid
@@ -120,7 +136,7 @@ struct Tb2dTile {
         wxp = cxp[v];
       }
       if constexpr (YE) yp = bot ? c : yp;
-      float acc = a.cf.c0 * c;
+      float acc = centre_term<HOT && !ADJ>(a.cf.c0, c, (HOT && !ADJ) ? q[v] : 0.0f);
       acc = __builtin_fmaf(wxm, xm, acc);
       acc = __builtin_fmaf(wxp, xp, acc);
       acc = __builtin_fmaf(cyp, yp, acc);
@@ -128,31 +144,19 @@ struct Tb2dTile {
     }
   }
 
-  // Phase 2 of a level: add the y-1 term (newest row Nr of the level below), then the source.
+  // Phase 2 of a level: add the y-1 term (newest row Nr of the level below).
   template <bool YE>
-  __device__ __forceinline__ void finish(const float (&Nr)[V], const float (&Cr)[V], float (&o)[V], int j,
-                                         int qslot) const {
+  __device__ __forceinline__ void finish(const float (&Nr)[V], const float (&Cr)[V], float (&o)[V], int j) const {
     const bool top = YE && (j == 0);  // y-1 leaves the grid
     float cym = a.cf.wy_m;
     if constexpr (ADJ && YE) {
       if (top) cym = a.cf.wy_p;
     }
-    float q[V];
-    if constexpr (HOT && !ADJ) {
-      const float* qp = ring + qslot * W + lane * V;
-#pragma unroll
-      for (int h = 0; h < V; h += 4) {
-        const float4 t = *reinterpret_cast<const float4*>(qp + h);
-        q[h] = t.x; q[h + 1] = t.y; q[h + 2] = t.z; q[h + 3] = t.w;
-      }
-    }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       float ym = Nr[v];
       if constexpr (YE) ym = top ? Cr[v] : ym;
-      float acc = __builtin_fmaf(cym, ym, o[v]);
-      if constexpr (HOT && !ADJ) acc = acc + q[v];
-      o[v] = acc;
+      o[v] = __builtin_fmaf(cym, ym, o[v]);
     }
   }
 
@@ -183,19 +187,29 @@ struct Tb2dTile {
   }
 
   // One iteration: input row r arrives (rows stream downwards in index), level s makes row r+s.
-  template <int ROT, bool XE, bool YE, bool VEC>
+  // LB is the prefetch slot of row r (the loop is unrolled by D, a multiple of the state period 2).
+  template <int LB, bool XE, bool YE, bool VEC>
   __device__ __forceinline__ void step(int r) {
+    constexpr int ROT = LB & 1;
     float (&X)[K][V] = S[ROT];      // oldest rows on entry; partial sums; newest rows on exit
     float (&C)[K][V] = S[ROT ^ 1];  // centre rows
     const int keff = FULL ? K : a.keff;
     // ---- phase 1, top level first: partial[s] (row r+s) replaces X[s] once X[s] is used
     float part_top[V];
+    // source rows are read one level ahead so that only two of them are live at a time
+    float qc[V], qn[V];
+    (void)qc;
+    (void)qn;
+    read_q(K, qc);
 #pragma unroll
     for (int s = K; s >= 1; --s) {
       const int j = r + s;
+      if constexpr (HOT && !ADJ) {
+        if (s > 1) read_q(s - 1, qn);
+      }
       float o[V];
       if (FULL || s <= keff) {
-        partial<XE, YE>(X[s - 1], C[s - 1], o, j);
+        partial<XE, YE>(X[s - 1], C[s - 1], o, j, qc);
       } else {
 #pragma unroll
         for (int v = 0; v < V; ++v) o[v] = 0.0f;  // surplus level: overwritten in phase 2
@@ -205,31 +219,30 @@ struct Tb2dTile {
         if (s == K) part_top[v] = o[v];
         else X[s][v] = o[v];
       }
+      if constexpr (HOT && !ADJ) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) qc[v] = qn[v];
+      }
     }
     // ---- phase 2, bottom level first
 #pragma unroll
-    for (int v = 0; v < V; ++v) X[0][v] = Lb[ROT][v];
+    for (int v = 0; v < V; ++v) X[0][v] = Lb[LB][v];
     if constexpr (HOT && !ADJ) {
       float* qp = ring + slot0 * W + lane * V;
 #pragma unroll
-      for (int v = 0; v < V; ++v) qp[v] = __builtin_fmaf(a.cf.cp, Pb[ROT][v], a.cf.kamb);
+      for (int v = 0; v < V; ++v) qp[v] = __builtin_fmaf(a.cf.cp, Pb[LB][v], a.cf.kamb);
     }
-    prefetch<VEC>(r - 2, ROT);
+    prefetch<VEC>(r - D, LB);
     float Pn[K][V];
     (void)Pn;
 #pragma unroll
     for (int s = 1; s <= K; ++s) {
       const int j = r + s;
-      int qs = 0;
-      if constexpr (HOT && !ADJ) {
-        qs = slot0 - s;
-        if (qs < 0) qs += RING;
-      }
       float o[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) o[v] = (s == K) ? part_top[v] : X[s][v];
       if (FULL || s <= keff) {
-        finish<YE>(X[s - 1], C[s - 1], o, j, qs);
+        finish<YE>(X[s - 1], C[s - 1], o, j);
       } else {
 #pragma unroll
         for (int v = 0; v < V; ++v) o[v] = C[s - 1][v];  // surplus level: forward its input row
@@ -284,13 +297,21 @@ struct Tb2dTile {
     // input rows from y1-1+keff down to y0-keff; level K emits row r+K
     const int r0 = y1 - 1 + keff;
     int nit = (y1 - y0) + keff + K;
-    nit = (nit + 1) & ~1;  // the extra iteration only touches rows outside [y0, y1)
+    nit = (nit + D - 1) / D * D;  // the extra iterations only touch rows outside [y0, y1)
     slot0 = 0;
-    prefetch<VEC>(r0, 0);
-    prefetch<VEC>(r0 - 1, 1);
-    for (int it = 0; it < nit; it += 2) {
+#pragma unroll
+    for (int b = 0; b < D; ++b) prefetch<VEC>(r0 - b, b);
+    for (int it = 0; it < nit; it += D) {
       step<0, XE, YE, VEC>(r0 - it);
       step<1, XE, YE, VEC>(r0 - it - 1);
+      if constexpr (D >= 4) {
+        step<2 % D, XE, YE, VEC>(r0 - it - 2);
+        step<3 % D, XE, YE, VEC>(r0 - it - 3);
+      }
+      if constexpr (D >= 6) {
+        step<4 % D, XE, YE, VEC>(r0 - it - 4);
+        step<5 % D, XE, YE, VEC>(r0 - it - 5);
+      }
     }
   }
 
@@ -327,12 +348,12 @@ struct Tb2dTile {
   }
 };
 
-template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL>
+template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL, int D = 2>
 __global__ __launch_bounds__(64) void tb2d_kernel(Tb2dArgs a) {
   constexpr int RING = (HOT && !ADJ) ? (K + 1) : 1;
   __shared__ __align__(16) float ring[RING * 64 * V];
   const int ntiles = a.ntx * a.nseg;
   const int tile = xcd_remap(blockIdx.x, ntiles);
-  Tb2dTile<K, V, HOT, ADJ, ACC, FULL> t(a, threadIdx.x, ring);
+  Tb2dTile<K, V, HOT, ADJ, ACC, FULL, D> t(a, threadIdx.x, ring);
   t.process(tile);
 }

@@ -98,11 +98,33 @@ struct Tb3dTile {
     }
   }
 
-  // Phase 1: in-plane terms of centre plane Cl (cross-wave rows from LDS buffer rbuf) and the
-  // z-1 term of the oldest plane Pl, for output plane j.
+  // Phase 1: source, in-plane terms of centre plane Cl (cross-wave rows from LDS buffer rbuf)
+  // and the z-1 term of the oldest plane Pl, for output plane j.
   template <bool XE, bool YE, bool ZE>
   __device__ __forceinline__ void partial(const float (&Pl)[R][V], const float (&Cl)[R][V], float (&o)[R][V],
                                           int lev_in, int rbuf, int j) const {
+    float q[R][V];
+    (void)q;
+    if constexpr (HOT && !ADJ) {
+      const int zc = clampi(j, 0, a.nz - 1);
+      const float* pl = a.power + (size_t)zc * a.ny * a.nx;
+      const int x0 = xw + lane * V;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int y = clampi(yw + wave * R + r, 0, a.ny - 1);
+        const float* rowp = pl + (size_t)y * a.nx;
+        if constexpr (!XE && V == 2) {
+          const float2 t = *reinterpret_cast<const float2*>(rowp + x0);
+          q[r][0] = __builtin_fmaf(a.cf.cp, t.x, a.cf.kamb);
+          q[r][1] = __builtin_fmaf(a.cf.cp, t.y, a.cf.kamb);
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+            q[r][v] = __builtin_fmaf(a.cf.cp, rowp[XE ? clampi(x0 + v, 0, a.nx - 1) : x0 + v], a.cf.kamb);
+        }
+      }
+    }
+
     float hn[V], hs[V];
     {
       const int wn = wave > 0 ? wave - 1 : 0;
@@ -149,15 +171,16 @@ struct Tb3dTile {
           yp = rowBot[r] ? c : yp;
         }
         if constexpr (ZE) zm = zlo ? c : zm;
-        float acc = upd2(a.cf.c0, c, wxm, xm, wxp, xp, cyp, yp, cym, ym);
+        float acc = upd2<HOT && !ADJ>(a.cf.c0, c, wxm, xm, wxp, xp, cyp, yp, cym, ym,
+                                      (HOT && !ADJ) ? q[r][v] : 0.0f);
         acc = __builtin_fmaf(czm, zm, acc);
         o[r][v] = acc;
       }
     }
   }
 
-  // Phase 2: z+1 term from the newest plane Nl of the level below, then the source.
-  template <bool XE, bool ZE>
+  // Phase 2: z+1 term from the newest plane Nl of the level below.
+  template <bool ZE>
   __device__ __forceinline__ void finish(const float (&Nl)[R][V], const float (&Cl)[R][V], float (&o)[R][V],
                                          int j) const {
     const bool zhi = ZE && (j == a.nz - 1);
@@ -165,35 +188,13 @@ struct Tb3dTile {
     if constexpr (ADJ && ZE) {
       if (zhi) czp = a.cf.wz_m;
     }
-    float q[R][V];
-    if constexpr (HOT && !ADJ) {
-      const int zc = clampi(j, 0, a.nz - 1);
-      const float* pl = a.power + (size_t)zc * a.ny * a.nx;
-      const int x0 = xw + lane * V;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int y = clampi(yw + wave * R + r, 0, a.ny - 1);
-        const float* rowp = pl + (size_t)y * a.nx;
-        if constexpr (!XE && V == 2) {
-          const float2 t = *reinterpret_cast<const float2*>(rowp + x0);
-          q[r][0] = __builtin_fmaf(a.cf.cp, t.x, a.cf.kamb);
-          q[r][1] = __builtin_fmaf(a.cf.cp, t.y, a.cf.kamb);
-        } else {
-#pragma unroll
-          for (int v = 0; v < V; ++v)
-            q[r][v] = __builtin_fmaf(a.cf.cp, rowp[XE ? clampi(x0 + v, 0, a.nx - 1) : x0 + v], a.cf.kamb);
-        }
-      }
-    }
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         float zp = Nl[r][v];
         if constexpr (ZE) zp = zhi ? Cl[r][v] : zp;
-        float acc = __builtin_fmaf(czp, zp, o[r][v]);
-        if constexpr (HOT && !ADJ) acc = acc + q[r][v];
-        o[r][v] = acc;
+        o[r][v] = __builtin_fmaf(czp, zp, o[r][v]);
       }
   }
 
@@ -276,7 +277,7 @@ struct Tb3dTile {
 #pragma unroll
         for (int v = 0; v < V; ++v) o[rr][v] = (s == K) ? part_top[rr][v] : X[s][rr][v];
       if (FULL || s <= keff) {
-        finish<XE, ZE>(X[s - 1], C[s - 1], o, j);
+        finish<ZE>(X[s - 1], C[s - 1], o, j);
       } else {
 #pragma unroll
         for (int rr = 0; rr < R; ++rr)
