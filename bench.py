@@ -32,20 +32,56 @@ def log(msg):
 
 
 def tb2d_bytes_flops(nx, ny, K, keff, seg, hot=True):
-    """Algorithmic HBM bytes and executed FP32 FLOPs of one temporal-blocked 2D pass
-    (overlapped windows of 256 columns, halo K, segments of `seg` rows)."""
+    """Algorithmic HBM bytes and executed FP32 FLOPs of one temporal-blocked 2D pass with
+    keff fused steps (overlapped windows of 256 columns, halo K, segments of `seg` rows):
+    every window row is read once per pass (temperature, plus power for hotspot) and every
+    cell is written once."""
     W = 256
     kr = (K + 3) // 4 * 4
     cs = (W - K - kr) // 4 * 4
     ntx = math.ceil(nx / cs)
+    seg = max(1, min(seg, ny))
     nseg = math.ceil(ny / seg)
     rows = seg + 2 * keff
     nread = 2 if hot else 1
-    read_cells = ntx * nseg * rows * W  # each window row is read once per pass
+    read_cells = ntx * nseg * rows * W
     bytes_ = read_cells * 4 * nread + nx * ny * 4
-    flops_per = 10 if hot else 9  # mul + 4 fma (+ add of the source term), FMA = 2 FLOP
+    # per cell and level: hotspot fma(cc, c, q) + 4 fma; diffusion mul + 4 fma (FMA = 2 FLOP)
+    flops_per = 10 if hot else 9
     flops = ntx * nseg * W * (seg + keff) * keff * flops_per
     return bytes_, flops
+
+
+# Kernel sources whose hash identifies the measured build of the dominant kernel.
+TB2D_SOURCES = ["tb2d.hpp", "device_common.hpp", "k_tb2d_hot.hip"]
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "tb2d_hotspot_16384_hbm_counters.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TB2D_SOURCES:
+        with open(os.path.join(ROOT, "paper_1802_00438_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(K, seg):
+    """HBM bytes per launch of the dominant kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, each divided by what the counter reads per byte
+    of a plain device copy), or None if the summary is missing or was taken on another
+    kernel build or tile configuration."""
+    try:
+        with open(PMC_SUMMARY) as fh:
+            text = fh.read()
+        blob = text.split("<!-- counters-json -->")[1].split("<!-- /counters-json -->")[0]
+        rec = json.loads(blob.strip().strip("`").strip())
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("k") != K or rec.get("seg_len") != seg:
+        return None
+    return (rec["fetch_kib_per_dispatch"] * 1024.0 / rec["copy_fetch_factor"] +
+            rec["write_kib_per_dispatch"] * 1024.0 / rec["copy_write_factor"])
 
 
 def time_call(fn, stream, reps):
@@ -87,6 +123,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="main workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--k", type=int, default=0, help="fix the fused steps per pass (skips auto-tuning)")
+    ap.add_argument("--seg", type=int, default=0, help="fix the rows per tile pass (with --k)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="first copy one grid-sized buffer three times (a known-size kernel for "
+                         "calibrating memory counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the slab "
@@ -108,8 +149,19 @@ def main():
     x = torch.from_numpy(x_host).to(dev)
     p = torch.from_numpy(p_host).to(dev)
     del x_host
-    log("[bench] creating plan (auto-tune)")
-    plan = S.Plan(HOTSPOT, wl.shape)
+    if args.copy_calib:
+        dst = torch.empty_like(x)
+        for _ in range(3):
+            dst.copy_(x)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 3 copies of %d bytes" % (x.numel() * 4))
+        del dst
+    if args.k > 0:
+        log("[bench] creating plan (k=%d, seg=%d)" % (args.k, args.seg))
+        plan = S.Plan(HOTSPOT, wl.shape, {"variant": 2, "k": args.k, "seg_len": args.seg})
+    else:
+        log("[bench] creating plan (auto-tune)")
+        plan = S.Plan(HOTSPOT, wl.shape)
     tun = plan.tuning
     log("[bench] tuning %s" % tun)
     cf = wl.coeffs
@@ -134,32 +186,46 @@ def main():
     gcells = cells * wl.T / (ms * 1e-3) / 1e9
     log("[bench] main: %.3f ms per run, %.1f GCell/s (wall %.2f s)" % (ms, gcells, wall))
 
-    # dominant kernel: the temporal-blocked hotspot pass; its average launch duration over the
-    # timed region is the run time minus the parity copy, divided by the launches per run
+    # Dominant kernel: the full K-step temporal-blocked hotspot pass.  A run is T // K full
+    # passes plus, when K does not divide T, one shorter pass (on a smaller instantiation)
+    # and, for an odd pass count, a parity copy.  The copy and the short pass are timed on
+    # their own with the same events, and the full passes' average launch duration is what
+    # remains of the timed run divided by their number.
     K = tun["k"]
-    passes = math.ceil(wl.T / K)
-    copy_ms = 0.0
-    if passes % 2 == 1:
-        tmp = torch.empty_like(x)
-        copy_ms = time_call(lambda: tmp.copy_(x), stream, 5)
-        del tmp
-    kern_ms = (ms - copy_ms) / passes
-    full_bytes, full_flops = tb2d_bytes_flops(wl.nx, wl.ny, K, K, tun["seg_len"], hot=True)
-    gbs = full_bytes / (kern_ms * 1e-3) / 1e9
-    tflops = full_flops / (kern_ms * 1e-3) / 1e12
+    seg = tun["seg_len"]
+    n_full, rem = divmod(wl.T, K)
+    passes = n_full + (1 if rem else 0)
+    tmp = torch.empty_like(x)
+    copy_ms = time_call(lambda: tmp.copy_(x), stream, 5)
+    del tmp
+    short_ms = 0.0
+    if rem:
+        # a run of `rem` steps is one pass, preceded by the parity copy (one pass is odd)
+        short_ms = max(0.0, time_call(lambda: plan.run(x, cf, rem, p), stream, 5) - copy_ms)
+    kern_ms = (ms - (copy_ms if passes % 2 == 1 else 0.0) - short_ms) / n_full
+    launch_bytes, launch_flops = tb2d_bytes_flops(wl.nx, wl.ny, K, K, seg, hot=True)
+    gbs = launch_bytes / (kern_ms * 1e-3) / 1e9
+    tflops = launch_flops / (kern_ms * 1e-3) / 1e12
     frac_hbm = gbs / HBM_PEAK_GBS
     frac_alu = tflops / ALU_PEAK_TFLOPS
+    traffic_bytes = measured_traffic(K, seg)
     if frac_alu >= frac_hbm:
         roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
                 "frac": round(frac_alu, 4)}
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(frac_hbm, 4)}
-    roof["traffic"] = None
+    # measured HBM traffic per launch over the same average launch duration, in GB/s
+    roof["traffic"] = None if traffic_bytes is None else round(traffic_bytes / (kern_ms * 1e-3) / 1e9, 1)
     roof["kernel"] = "tb2d_kernel<K=%d,V=4,hotspot>" % K
     roof["avg_launch_ms"] = round(kern_ms, 4)
+    roof["launches_per_run"] = n_full
+    roof["algorithmic_bytes_per_launch"] = int(launch_bytes)
+    roof["traffic_bytes_per_launch"] = None if traffic_bytes is None else int(traffic_bytes)
     roof["hbm_gbs_algorithmic"] = round(gbs, 1)
     roof["tflops_executed"] = round(tflops, 3)
+    roof["frac_hbm"] = round(frac_hbm, 4)
+    roof["frac_alu"] = round(frac_alu, 4)
 
     out = {
         "metric": "GCell-updates/s & % HBM roofline (fwd, adjoint) vs plain 1-step/pass kernel",
@@ -175,7 +241,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "hotspot2d_16384", "nx": wl.nx, "ny": wl.ny, "T": wl.T, "coeffs": "H2",
-                   "k": K, "seg_len": tun["seg_len"], "bsize_x": tun["bsize_x"]},
+                   "k": K, "seg_len": seg, "bsize_x": tun["bsize_x"]},
         "pct_single_pass_roofline": round(100.0 * gcells / (HBM_PEAK_GBS / 12.0), 1),
         "effective_gbs_eq9": round(gcells * 12.0, 1),
         "effective_gflops_table2": round(gcells * 15.0, 1),

@@ -132,6 +132,7 @@ __global__ __launch_bounds__(64 * kTb3dNW) void batched3d_kernel(const BGrid* __
     a.nx = g.nx; a.ny = g.ny; a.nz = g.nz; a.keff = w.keff;
     a.csx = g.csx; a.csy = g.csy; a.krx = g.krx; a.kry = g.kry; a.ntx = g.ntx; a.nty = g.nty;
     a.segz = g.segz; a.nsegz = g.nsegz;
+    a.nwork = 0;
     a.aligned = g.aligned;
     a.cf = g.cf;
     {

@@ -10,7 +10,6 @@
 enum KMode { KM_DIFF = 0, KM_HOT = 1, KM_ADJ = 2, KM_ADJ_ACC = 3 };
 
 // Tile shapes of the temporal-blocked kernels.
-constexpr int kTb2dV = 4;                               // 256-column windows, one wave each
 constexpr int kTb3dV = 2, kTb3dR = 6, kTb3dNW = 8;       // forward: 128 x 48 x-y window, 512 threads
 constexpr int kTb3dAdjR = 4, kTb3dAdjNW = 8;            // adjoint: 128 x 32 window
 
@@ -34,18 +33,9 @@ hipError_t launch_tb3d_diff(int K, bool full, const Tb3dArgs& a, hipStream_t s);
 hipError_t launch_tb3d_hot(int K, bool full, const Tb3dArgs& a, hipStream_t s);
 hipError_t launch_tb3d_adj(int K, bool acc, bool full, const Tb3dArgs& a, hipStream_t s);
 
-// Rows in flight per wave: four for diffusion, two where the hotspot source ring or the
-// adjoint's running sums already take the registers (three resp. two waves per SIMD).
-#define TB2D_DEPTH(HOT, ADJ) (((HOT) || (ADJ)) ? 2 : 4)
-#define TB_LAUNCH2D(K, HOT, ADJ, ACC, FULL, a, s)                                                       \
-  do {                                                                                                  \
-    hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL, TB2D_DEPTH(HOT, ADJ)>),             \
-                       dim3((a).ntx * (a).nseg), dim3(64), 0, s, a);                                    \
-    return hipGetLastError();                                                                           \
-  } while (0)
 #define TB_LAUNCH3D(K, R, NW, HOT, ADJ, ACC, FULL, a, s)                                               \
   do {                                                                                                  \
-    hipLaunchKernelGGL((tb3d_kernel<K, kTb3dV, R, NW, HOT, ADJ, ACC, FULL>),                           \
-                       dim3((a).ntx * (a).nty * (a).nsegz), dim3(64 * NW), 0, s, a);                    \
+    hipLaunchKernelGGL((tb3d_kernel<K, kTb3dV, R, NW, HOT, ADJ, ACC, FULL, 1>),                        \
+                       dim3((a).nwork > 0 ? (a).nwork : (a).ntx * (a).nty * (a).nsegz), dim3(64 * NW), 0, s, a); \
     return hipGetLastError();                                                                           \
   } while (0)

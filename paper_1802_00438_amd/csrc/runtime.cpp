@@ -235,6 +235,7 @@ hipError_t run_pass(const stencil_plan_s* p, KMode m, int K, int keff, const flo
   a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.keff = keff;
   a.csx = g.csx; a.csy = g.csy; a.krx = g.krx; a.kry = g.kry; a.ntx = g.ntx; a.nty = g.nty;
   a.segz = g.segz; a.nsegz = g.nsegz;
+  a.nwork = 0;
   a.aligned = ((p->nx & 1) == 0) && ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 7) == 0 ? 1 : 0;
   a.cf = cf;
   return launch_tb3d(K, m, full, a, p->stream);
@@ -294,7 +295,10 @@ stencil_status_t run_sequence(stencil_plan_s* p, KMode m, bool plain, int K, con
     if (plain) {
       e = run_plain_step(p, m, src, dst, power, gp, cf);  // plain passes are single steps
     } else {
-      e = run_pass(p, m, K, steps[i], src, dst, power, gp, cf);
+      // a pass that fuses fewer steps than K runs on the smallest instantiation that holds
+      // them: surplus levels would only forward their input at the full pass's cost
+      const int Ki = steps[i] < K ? inst_k_for(p->ndim, m, steps[i]) : K;
+      e = run_pass(p, m, Ki, steps[i], src, dst, power, gp, cf);
     }
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     src = dst;

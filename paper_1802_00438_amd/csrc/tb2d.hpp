@@ -357,3 +357,16 @@ __global__ __launch_bounds__(64) void tb2d_kernel(Tb2dArgs a) {
   Tb2dTile<K, V, HOT, ADJ, ACC, FULL, D> t(a, threadIdx.x, ring);
   t.process(tile);
 }
+
+// Launch shape of the 2D kernels: 256-column windows (one wave, 4 cells per lane), one
+// workgroup per (x tile, row segment).
+constexpr int kTb2dV = 4;
+// Rows in flight per wave: four for diffusion, two where the hotspot source ring or the
+// adjoint's running sums already take the registers (three resp. two waves per SIMD).
+#define TB2D_DEPTH(HOT, ADJ) (((HOT) || (ADJ)) ? 2 : 4)
+#define TB_LAUNCH2D(K, HOT, ADJ, ACC, FULL, a, s)                                                       \
+  do {                                                                                                  \
+    hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL, TB2D_DEPTH(HOT, ADJ)>),             \
+                       dim3((a).ntx * (a).nseg), dim3(64), 0, s, a);                                    \
+    return hipGetLastError();                                                                           \
+  } while (0)

@@ -43,11 +43,12 @@ struct Tb3dArgs {
   int krx, kry;        // window offsets (window start = tile start - kr)
   int ntx, nty;        // tiles in x, y
   int segz, nsegz;     // output planes per tile, tiles along z
+  int nwork;           // > 0: balanced launch of nwork workgroups (see tb3d_kernel)
   int aligned;         // 1: nx even and 8-byte aligned buffers (vector access in interior tiles)
   DevCoef cf;
 };
 
-template <int K, int V, int R, int NW, bool HOT, bool ADJ, bool ACC, bool FULL>
+template <int K, int V, int R, int NW, bool HOT, bool ADJ, bool ACC, bool FULL, int PD = 1>
 struct Tb3dTile {
   static constexpr int WX = 64 * V;
   static constexpr int WY = R * NW;
@@ -55,7 +56,7 @@ struct Tb3dTile {
   const int lane, wave;
   int xw, yw, ox0, ox1, oy0, oy1, z0, z1;
   float S[2][K][R][V];  // per level: centre plane and oldest/partial/newest plane, alternating
-  float Lb[R][V];       // next input plane (loaded one iteration ahead)
+  float Lb[PD][R][V];   // next PD input planes (loaded PD iterations ahead)
   float Pp[K][R][V];
   float cxm[V], cxp[V];
   bool isL[V], isR[V];
@@ -207,8 +208,13 @@ struct Tb3dTile {
       const int y = yw + wave * R + r;
       if (y < oy0 || y >= oy1) continue;
       float* rowp = pl + (size_t)y * a.nx;
-      if (!XE && V == 2 && x0 >= ox0 && x0 + V <= ox1) {
-        *reinterpret_cast<float2*>(rowp + x0) = make_float2(o[r][0], o[r][V - 1]);
+      if (!XE && x0 >= ox0 && x0 + V <= ox1) {
+        if constexpr (V == 2) {
+          *reinterpret_cast<float2*>(rowp + x0) = make_float2(o[r][0], o[r][V - 1]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) rowp[x0 + v] = o[r][v];
+        }
       } else {
 #pragma unroll
         for (int v = 0; v < V; ++v)
@@ -260,11 +266,12 @@ struct Tb3dTile {
           else X[s][rr][v] = o[rr][v];
         }
     }
+    constexpr int LB = ROT % PD;  // plane r arrived in Lb[LB]; plane r + PD replaces it
 #pragma unroll
     for (int rr = 0; rr < R; ++rr)
 #pragma unroll
-      for (int v = 0; v < V; ++v) X[0][rr][v] = Lb[rr][v];
-    load_plane<XE>(r + 1, Lb, a.src);
+      for (int v = 0; v < V; ++v) X[0][rr][v] = Lb[LB][rr][v];
+    load_plane<XE>(r + PD, Lb[LB], a.src);
     publish(ROT, 0, X[0]);
     float Pn[K][R][V];
     (void)Pn;
@@ -347,7 +354,8 @@ struct Tb3dTile {
     const int r0 = z0 - keff;
     int nit = (z1 - z0) + keff + K;
     nit = (nit + 1) & ~1;
-    load_plane<XE>(r0, Lb, a.src);
+#pragma unroll
+    for (int d = 0; d < PD; ++d) load_plane<XE>(r0 + d, Lb[d], a.src);
     // Pairs of iterations that compute a plane at a z edge form a prefix (z = 0) and a suffix
     // (z = nz-1) of the loop; they run a body with z-edge handling, the rest a body without
     // it.  Separate loops (rather than a branch inside one loop) keep the register allocation
@@ -371,19 +379,25 @@ struct Tb3dTile {
     }
   }
 
+  // Tile `tile` of the (x, y, z-segment) tiling.
   __device__ __forceinline__ void process(int tile) {
     const int tx = tile % a.ntx;
     const int rest = tile / a.ntx;
     const int ty = rest % a.nty;
     const int tz = rest / a.nty;
+    process_column(tx, ty, tz * a.segz, min(tz * a.segz + a.segz, a.nz));
+  }
+
+  // Output planes [zs, ze) of the x-y column (tx, ty).
+  __device__ __forceinline__ void process_column(int tx, int ty, int zs, int ze) {
     ox0 = tx * a.csx;
     ox1 = min(ox0 + a.csx, a.nx);
     oy0 = ty * a.csy;
     oy1 = min(oy0 + a.csy, a.ny);
     xw = ox0 - a.krx;
     yw = oy0 - a.kry;
-    z0 = tz * a.segz;
-    z1 = min(z0 + a.segz, a.nz);
+    z0 = zs;
+    z1 = ze;
     const bool xe = !a.aligned || (xw < 0) || (xw + WX > a.nx);
     const bool ye = (yw < 0) || (yw + WY > a.ny);
 #pragma unroll
@@ -412,12 +426,29 @@ struct Tb3dTile {
   }
 };
 
-template <int K, int V, int R, int NW, bool HOT, bool ADJ, bool ACC, bool FULL>
+// Two launch shapes.  Tile launch: one workgroup per (x, y, z-segment) tile.  Balanced launch
+// (a.nwork > 0): the (column, plane) units of all x-y columns, column-major, are cut into
+// nwork equal contiguous shares; a workgroup streams its share as one or more column
+// segments, so every workgroup does the same work and the pipeline fill is paid once or twice
+// per workgroup instead of once per short tile.
+template <int K, int V, int R, int NW, bool HOT, bool ADJ, bool ACC, bool FULL, int PD>
 __global__ __launch_bounds__(64 * NW) void tb3d_kernel(Tb3dArgs a) {
   __shared__ __align__(16) float hal[2 * K * NW * 2 * 64 * V];
-  const int ntiles = a.ntx * a.nty * a.nsegz;
-  const int tile = xcd_remap(blockIdx.x, ntiles);
-  Tb3dTile<K, V, R, NW, HOT, ADJ, ACC, FULL> t(a, threadIdx.x & 63, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
-                                                hal);
-  t.process(tile);
+  Tb3dTile<K, V, R, NW, HOT, ADJ, ACC, FULL, PD> t(a, threadIdx.x & 63,
+                                                    __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), hal);
+  if (a.nwork == 0) {
+    t.process(xcd_remap(blockIdx.x, a.ntx * a.nty * a.nsegz));
+    return;
+  }
+  const int w = xcd_remap(blockIdx.x, a.nwork);
+  const long long units = (long long)a.ntx * a.nty * a.nz;
+  long long u = units * w / a.nwork;
+  const long long u1 = units * (w + 1) / a.nwork;
+  while (u < u1) {
+    const int col = (int)(u / a.nz);
+    const int zs = (int)(u - (long long)col * a.nz);
+    const int ze = (int)min((long long)a.nz, zs + (u1 - u));
+    t.process_column(col % a.ntx, col / a.ntx, zs, ze);
+    u += ze - zs;
+  }
 }
