@@ -44,6 +44,24 @@ __device__ __forceinline__ float from_upper(float x) {
                                                                0x130 /* wave_shl:1 */, 0xf, 0xf, true));
 }
 
+// The x-1 and x+1 terms of interior cells fused with their cross-lane move: acc + w * x of
+// lane i-1 (resp. i+1) as one v_fmac_f32 whose first source is read through DPP, the same
+// single-rounding FMA as fma(w, from_lower(x), acc).  The compiler does not form it by itself
+// because a DPP instruction cannot take its other operand from an SGPR, so the weight is
+// passed in a VGPR.  "s_nop 1" provides the two wait states a DPP read needs after a VALU
+// write of its source register.  End lanes read 0 and leave acc unchanged; they only ever
+// hold halo columns.
+__device__ __forceinline__ float fma_from_lower(float w, float x, float acc) {
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "+v"(acc) : "v"(x), "v"(w));
+  return acc;
+}
+__device__ __forceinline__ float fma_from_upper(float w, float x, float acc) {
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "+v"(acc) : "v"(x), "v"(w));
+  return acc;
+}
+
 // gfx950 dispatches consecutive workgroup ids round-robin over its 8 XCDs, each with a
 // private L2.  Remap so that each XCD receives a contiguous run of logical tile ids (and
 // so shares the overlapping halo reads of neighbouring tiles in its own L2).  Bijective

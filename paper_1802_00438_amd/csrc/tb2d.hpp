@@ -115,8 +115,11 @@ struct Tb2dTile {
   template <bool XE, bool YE>
   __device__ __forceinline__ void partial(const float (&Pr)[V], const float (&Cr)[V], float (&o)[V], int j,
                                           const float (&q)[V]) const {
-    const float wl = from_lower(Cr[V - 1]);
-    const float eu = from_upper(Cr[0]);
+    float wl = 0.0f, eu = 0.0f;
+    if constexpr (XE) {
+      wl = from_lower(Cr[V - 1]);
+      eu = from_upper(Cr[0]);
+    }
     const bool bot = YE && (j == a.ny - 1);  // y+1 leaves the grid
     float cyp = a.cf.wy_p;
     if constexpr (ADJ && YE) {
@@ -137,8 +140,13 @@ struct Tb2dTile {
       }
       if constexpr (YE) yp = bot ? c : yp;
       float acc = centre_term<HOT && !ADJ>(a.cf.c0, c, (HOT && !ADJ) ? q[v] : 0.0f);
-      acc = __builtin_fmaf(wxm, xm, acc);
-      acc = __builtin_fmaf(wxp, xp, acc);
+      if constexpr (XE) {
+        acc = __builtin_fmaf(wxm, xm, acc);
+        acc = __builtin_fmaf(wxp, xp, acc);
+      } else {
+        acc = (v > 0) ? __builtin_fmaf(wxm, xm, acc) : fma_from_lower(wxm, Cr[V - 1], acc);
+        acc = (v < V - 1) ? __builtin_fmaf(wxp, xp, acc) : fma_from_upper(wxp, Cr[0], acc);
+      }
       acc = __builtin_fmaf(cyp, yp, acc);
       o[v] = acc;
     }

@@ -145,8 +145,11 @@ struct Tb3dTile {
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const float wl = from_lower(Cl[r][V - 1]);
-      const float eu = from_upper(Cl[r][0]);
+      float wl = 0.0f, eu = 0.0f;
+      if constexpr (XE) {
+        wl = from_lower(Cl[r][V - 1]);
+        eu = from_upper(Cl[r][0]);
+      }
       float cym = a.cf.wy_m, cyp = a.cf.wy_p;
       if constexpr (ADJ && YE) {
         if (rowTop[r]) cym = a.cf.wy_p;
@@ -172,8 +175,16 @@ struct Tb3dTile {
           yp = rowBot[r] ? c : yp;
         }
         if constexpr (ZE) zm = zlo ? c : zm;
-        float acc = upd2<HOT && !ADJ>(a.cf.c0, c, wxm, xm, wxp, xp, cyp, yp, cym, ym,
-                                      (HOT && !ADJ) ? q[r][v] : 0.0f);
+        float acc;
+        if constexpr (XE) {
+          acc = upd2<HOT && !ADJ>(a.cf.c0, c, wxm, xm, wxp, xp, cyp, yp, cym, ym, (HOT && !ADJ) ? q[r][v] : 0.0f);
+        } else {
+          acc = centre_term<HOT && !ADJ>(a.cf.c0, c, (HOT && !ADJ) ? q[r][v] : 0.0f);
+          acc = (v > 0) ? __builtin_fmaf(wxm, xm, acc) : fma_from_lower(wxm, Cl[r][V - 1], acc);
+          acc = (v < V - 1) ? __builtin_fmaf(wxp, xp, acc) : fma_from_upper(wxp, Cl[r][0], acc);
+          acc = __builtin_fmaf(cyp, yp, acc);
+          acc = __builtin_fmaf(cym, ym, acc);
+        }
         acc = __builtin_fmaf(czm, zm, acc);
         o[r][v] = acc;
       }
