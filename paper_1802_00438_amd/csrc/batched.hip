@@ -234,17 +234,11 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
     b->scratch.push_back(s);
     g.buf[0] = it.grid;
     g.buf[1] = s;
-    // temporal degree per grid from the cost model (tile shape fixed by the kernel)
+    // The persistent kernels fuse up to kBatchK2 (2D) / kBatchK3 (3D) steps per pass, and a
+    // pass costs the same for any number of fused steps up to that (levels past keff forward
+    // their input), so each grid takes the fewest passes (even, so the result lands in its own
+    // buffer), with the steps spread evenly over them.
     if (it.ndim == 2) {
-      double best = 1e300;
-      int bestk = kBatchK2;
-      for (int k : {4, 8, 12, 16}) {
-        const int seg = std::min(g.ny, 512);
-        Geom2D gg = geom2d(kBatchK2, g.nx, g.ny, seg);
-        gg.K = k;  // price k fused steps on the fixed window
-        const double t = model_time_2d(gg, g.nx, g.ny, it.T, false, false);
-        if (t < best) { best = t; bestk = k; }
-      }
       // items of a batch share the device, so each item is a long y-segment (at least 512
       // rows or the whole grid): few, large items keep the per-item flag traffic negligible
       const int seg = std::min(g.ny, std::max(512, kBatchK2));
@@ -252,7 +246,7 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
       g.cs = gg.cs; g.kr = gg.kr; g.ntx = gg.ntx; g.seg = gg.seg; g.nseg = gg.nseg;
       g.aligned = ((g.nx & 3) == 0) && ((reinterpret_cast<uintptr_t>(g.buf[0]) | reinterpret_cast<uintptr_t>(s)) & 15) == 0;
       ntiles[i] = gg.ntx * gg.nseg;
-      steps[i] = even_split(it.T, bestk);
+      steps[i] = even_split(it.T, kBatchK2);
     } else {
       // z-segments of 64 planes (at least the halo) give the 3D list enough items per pass
       const Geom3D gg = geom3d(kBatchK3, false, g.nx, g.ny, g.nz, std::min(g.nz, 64));

@@ -33,9 +33,12 @@ hipError_t launch_tb3d_diff(int K, bool full, const Tb3dArgs& a, hipStream_t s);
 hipError_t launch_tb3d_hot(int K, bool full, const Tb3dArgs& a, hipStream_t s);
 hipError_t launch_tb3d_adj(int K, bool acc, bool full, const Tb3dArgs& a, hipStream_t s);
 
+// Input planes in flight per workgroup: two where the registers allow it (forward diffusion up
+// to K = 5, forward hotspot up to K = 3), else one.
+#define TB3D_PD(K, HOT, ADJ) ((!(ADJ) && ((!(HOT) && (K) <= 5) || ((HOT) && (K) <= 3))) ? 2 : 1)
 #define TB_LAUNCH3D(K, R, NW, HOT, ADJ, ACC, FULL, a, s)                                               \
   do {                                                                                                  \
-    hipLaunchKernelGGL((tb3d_kernel<K, kTb3dV, R, NW, HOT, ADJ, ACC, FULL, 1>),                        \
+    hipLaunchKernelGGL((tb3d_kernel<K, kTb3dV, R, NW, HOT, ADJ, ACC, FULL, TB3D_PD(K, HOT, ADJ)>),     \
                        dim3((a).nwork > 0 ? (a).nwork : (a).ntx * (a).nty * (a).nsegz), dim3(64 * NW), 0, s, a); \
     return hipGetLastError();                                                                           \
   } while (0)

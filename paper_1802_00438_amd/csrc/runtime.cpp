@@ -122,6 +122,34 @@ double model_time_3d(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, 
   return passes * (std::max(tm, ta) + 4e-6);
 }
 
+double model_time_3d_bal(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj, int nwork) {
+  const DeviceInfo& d = device_info();
+  const int WX = 64 * kTb3dV;
+  const int WY = adj ? kTb3dAdjR * kTb3dAdjNW : kTb3dR * kTb3dNW;
+  const long passes = (T + g.K - 1) / g.K;
+  const double units = (double)g.ntx * g.nty * nz;
+  const double share = units / nwork;
+  // a share is one column segment, or two when it crosses a column boundary
+  const double segs = 1.0 + std::min(1.0, share / nz);
+  const double planes = nwork * (share + segs * 2.0 * g.K);
+  const int nread = (hot && !adj) ? 2 : 1;
+  const double bytes = planes * WX * WY * 4.0 * nread + (double)nx * ny * nz * 4.0 * (adj && hot ? 3 : 1);
+  const double ops = planes * WX * WY * g.K * (7.5 + (hot && !adj ? 2.0 : 0.0));
+  const double rounds = std::ceil((double)nwork / d.cus);
+  const double quant = (double)nwork / (rounds * d.cus);
+  const double tm = bytes / (d.hbm_gbs * 1e9 * d.achievable_frac);
+  const double ta = ops / (d.valu_lane_ops * 0.6) / quant;
+  return passes * (std::max(tm, ta) + 4e-6);
+}
+
+int balanced_nwork3d(int K, bool adj, int nx, int ny, int nz, int mult) {
+  const DeviceInfo& d = device_info();
+  const Geom3D g = geom3d(K, adj, nx, ny, nz, nz);
+  const long units = (long)g.ntx * g.nty * nz;
+  const long most = std::max(1L, units / (4L * K + 4));  // shares of at least ~4 pipeline depths
+  return (int)std::max(1L, std::min((long)d.cus * mult, most));
+}
+
 int pick_seg2d(int K, int nx, int ny, int waves_per_cu) {
   const DeviceInfo& d = device_info();
   const Geom2D g0 = geom2d(K, nx, ny, ny);
@@ -235,7 +263,7 @@ hipError_t run_pass(const stencil_plan_s* p, KMode m, int K, int keff, const flo
   a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.keff = keff;
   a.csx = g.csx; a.csy = g.csy; a.krx = g.krx; a.kry = g.kry; a.ntx = g.ntx; a.nty = g.nty;
   a.segz = g.segz; a.nsegz = g.nsegz;
-  a.nwork = 0;
+  a.nwork = p->nwork3d;
   a.aligned = ((p->nx & 1) == 0) && ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 7) == 0 ? 1 : 0;
   a.cf = cf;
   return launch_tb3d(K, m, full, a, p->stream);
@@ -322,16 +350,21 @@ struct TuneKey {
   }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, stencil_tuning_t> g_tune_cache;
+struct TuneResult {
+  stencil_tuning_t t;
+  int nwork;
+};
+std::map<TuneKey, TuneResult> g_tune_cache;
 
 // Model-ranked candidates, the best few timed on scratch memory.
-stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out) {
+stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out, int* nwork_out) {
   const TuneKey key{p->form, p->ndim, p->nx, p->ny, p->nz};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      *out = it->second;
+      *out = it->second.t;
+      *nwork_out = it->second.nwork;
       return STENCIL_OK;
     }
   }
@@ -341,6 +374,7 @@ stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out) {
   struct Cand {
     int K, seg;
     double model;
+    int nwork;  // 3D balanced launch (seg unused), 0 = tile launch
   };
   std::vector<Cand> cands;
   const int* ks;
@@ -353,23 +387,29 @@ stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out) {
       for (int seg : {96, 128, 160, 192, 224, 288, 352, 480, 608}) {
         if (seg < 2 * K && seg < p->ny) continue;
         const Geom2D g = geom2d(K, p->nx, p->ny, seg);
-        cands.push_back({K, g.seg, model_time_2d(g, p->nx, p->ny, Tref, hot, false)});
+        cands.push_back({K, g.seg, model_time_2d(g, p->nx, p->ny, Tref, hot, false), 0});
       }
       for (int wpc : {8, 12}) {
         const int seg = pick_seg2d(K, p->nx, p->ny, wpc);
         const Geom2D g = geom2d(K, p->nx, p->ny, seg);
-        cands.push_back({K, seg, model_time_2d(g, p->nx, p->ny, Tref, hot, false)});
+        cands.push_back({K, seg, model_time_2d(g, p->nx, p->ny, Tref, hot, false), 0});
       }
     } else {
-      for (int wpc : {1, 2, 4}) {
+      for (int mult : {1, 2}) {
+        const int nw = balanced_nwork3d(K, false, p->nx, p->ny, p->nz, mult);
+        const Geom3D g = geom3d(K, false, p->nx, p->ny, p->nz, p->nz);
+        const int share = (int)ceil_div((long)g.ntx * g.nty * p->nz, nw);
+        cands.push_back({K, share, model_time_3d_bal(g, p->nx, p->ny, p->nz, Tref, hot, false, nw), nw});
+      }
+      for (int wpc : {1, 2}) {
         const int segz = pick_segz3d(K, false, p->nx, p->ny, p->nz, wpc);
         const Geom3D g = geom3d(K, false, p->nx, p->ny, p->nz, segz);
-        cands.push_back({K, segz, model_time_3d(g, p->nx, p->ny, p->nz, Tref, hot, false)});
+        cands.push_back({K, segz, model_time_3d(g, p->nx, p->ny, p->nz, Tref, hot, false), 0});
       }
-      for (int segz : {32, 48, 64, 96, 128, 192, 256}) {
+      for (int segz : {32, 48, 64, 96, 128}) {
         if (segz > p->nz) continue;
         const Geom3D g = geom3d(K, false, p->nx, p->ny, p->nz, segz);
-        cands.push_back({K, g.segz, model_time_3d(g, p->nx, p->ny, p->nz, Tref, hot, false)});
+        cands.push_back({K, g.segz, model_time_3d(g, p->nx, p->ny, p->nz, Tref, hot, false), 0});
       }
     }
   }
@@ -378,13 +418,14 @@ stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out) {
   std::vector<Cand> uniq;
   for (const Cand& c : cands) {
     bool dup = false;
-    for (const Cand& u : uniq) dup |= (u.K == c.K && u.seg == c.seg);
+    for (const Cand& u : uniq) dup |= (u.K == c.K && u.seg == c.seg && u.nwork == c.nwork);
     if (!dup) uniq.push_back(c);
   }
   stencil_tuning_t best = p->tuning;
   best.variant = 2;
   best.k = uniq[0].K;
   best.seg_len = uniq[0].seg;
+  int best_nwork = uniq[0].nwork;
   const bool timed = !env_flag("STENCIL_MODEL_ONLY") && p->cells >= (size_t)1 << 16;
   if (timed) {
     // Time the top candidates on scratch memory.
@@ -412,6 +453,7 @@ stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out) {
         stencil_plan_s q = *p;
         q.tuning.k = cd.K;
         q.tuning.seg_len = cd.seg;
+        q.nwork3d = cd.nwork;
         const double per_pass = (double)cd.K * (double)p->cells;
         const int reps = std::max(2, std::min(64, (int)std::ceil(1.4e10 / per_pass)));
         run_pass(&q, m, cd.K, cd.K, tmp, p->scratch, pw, nullptr, cf);
@@ -435,12 +477,13 @@ stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out) {
       double best_rate = 0;
       for (int i = 0; i < ntop; ++i) {
         if (log_enabled())
-          std::fprintf(stderr, "[stencil] tune K=%d seg=%d model=%.3g ms measured=%.1f GCell/s\n", uniq[i].K,
-                       uniq[i].seg, uniq[i].model * 1e3, rate[i] * 1e-9);
+          std::fprintf(stderr, "[stencil] tune K=%d seg=%d nwork=%d model=%.3g ms measured=%.1f GCell/s\n",
+                       uniq[i].K, uniq[i].seg, uniq[i].nwork, uniq[i].model * 1e3, rate[i] * 1e-9);
         if (rate[i] > best_rate) {
           best_rate = rate[i];
           best.k = uniq[i].K;
           best.seg_len = uniq[i].seg;
+          best_nwork = uniq[i].nwork;
         }
       }
       hipEventDestroy(e0);
@@ -452,13 +495,14 @@ stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out) {
     hipGetLastError();
   }
   if (log_enabled())
-    std::fprintf(stderr, "[stencil] plan form=%d ndim=%d %dx%dx%d -> k=%d seg=%d\n", p->form, p->ndim, p->nx, p->ny,
-                 p->nz, best.k, best.seg_len);
+    std::fprintf(stderr, "[stencil] plan form=%d ndim=%d %dx%dx%d -> k=%d seg=%d nwork=%d\n", p->form, p->ndim, p->nx,
+                 p->ny, p->nz, best.k, best.seg_len, best_nwork);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = best;
+    g_tune_cache[key] = TuneResult{best, best_nwork};
   }
   *out = best;
+  *nwork_out = best_nwork;
   return STENCIL_OK;
 }
 
@@ -604,15 +648,28 @@ stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int nd
       const int K = inst_k_for(ndim, m, std::min(t.k, tb_max_k(ndim, m)));
       tuned = t;
       tuned.k = std::min(t.k, tb_max_k(ndim, m));
-      tuned.seg_len = ndim == 2 ? pick_seg2d(K, nx, ny, 8) : pick_segz3d(K, false, nx, ny, nz, 1);
+      if (ndim == 2) {
+        tuned.seg_len = pick_seg2d(K, nx, ny, 8);
+      } else {
+        // balanced launch, one workgroup per CU; seg_len reports the planes of one share
+        p->nwork3d = balanced_nwork3d(K, false, nx, ny, nz, 1);
+        const Geom3D g = geom3d(K, false, nx, ny, nz, nz);
+        tuned.seg_len = (int)ceil_div((long)g.ntx * g.nty * nz, p->nwork3d);
+      }
     } else {
-      stencil_status_t st = autotune(p, &tuned);
+      int nwork = 0;
+      stencil_status_t st = autotune(p, &tuned, &nwork);
       if (st != STENCIL_OK) {
         hipFree(p->scratch);
         delete p;
         return st;
       }
-      if (t.seg_len != 0) tuned.seg_len = t.seg_len;
+      p->nwork3d = nwork;
+      if (t.seg_len != 0) {
+        // an explicit segment length selects the tile launch with that length
+        tuned.seg_len = t.seg_len;
+        p->nwork3d = 0;
+      }
     }
     p->tuning = tuned;
     p->tuning.variant = 2;

@@ -36,6 +36,11 @@ Geom3D geom3d(int K, bool adj, int nx, int ny, int nz, int segz);
 // Model time (seconds) of T steps with the given geometry.
 double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj);
 double model_time_3d(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj);
+// The same for the balanced 3D launch of nwork workgroups (equal shares of column planes).
+double model_time_3d_bal(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj, int nwork);
+// Workgroups of a balanced 3D launch: `mult` per CU, fewer when the grid has too few column
+// planes to give each at least a few times the pipeline depth.
+int balanced_nwork3d(int K, bool adj, int nx, int ny, int nz, int mult);
 // Choose segment lengths that balance the tile count against the device's concurrency.
 int pick_seg2d(int K, int nx, int ny, int waves_per_cu);
 int pick_segz3d(int K, bool adj, int nx, int ny, int nz, int wgs_per_cu);
@@ -52,6 +57,7 @@ struct stencil_plan_s {
   hipStream_t stream;
   int device;
   stencil_tuning_t tuning;  // resolved
+  int nwork3d = 0;          // 3D: > 0 selects the balanced launch with this many workgroups
   float* scratch = nullptr;
   // checkpoints of the last stencil_run_ckpt
   std::vector<float*> ckpts;

@@ -27,3 +27,16 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+# Per-workload error of the FP32 GPU result against the FP64 oracle, filled by
+# test_gpu_fp64_report.py and printed at the end of the session.
+FP64_REPORT = []
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    if not FP64_REPORT:
+        return
+    terminalreporter.write_sep("-", "FP32 GPU result vs FP64 oracle, per workload")
+    for name, what, err, note in FP64_REPORT:
+        terminalreporter.write_line("%-24s %-34s max-rel %.3e  %s" % (name, what, err, note))

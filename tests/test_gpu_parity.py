@@ -125,6 +125,37 @@ def test_forward_3d_hotspot_all_k(shape, k):
         check_forward(x0, "AH3", T, power=p, tuning={"variant": 2, "k": k, "seg_len": 6})
 
 
+# With k given and no segment length, a 3D plan uses the balanced launch: every workgroup
+# streams an equal share of (x-y column, plane) units, crossing column boundaries mid-share.
+
+@pytest.mark.parametrize("shape", [(6, 6, 6), (9, 70, 130), (33, 50, 129), (3, 2, 300), (70, 40, 37)])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_forward_3d_diffusion_balanced_launch(shape, k):
+    x0 = uniform(shape, 0.0, 1.0, 3100 + k)
+    for T in sorted({1, k, 2 * k + 1}):
+        check_forward(x0, "A3", T, tuning={"variant": 2, "k": k})
+
+
+@pytest.mark.parametrize("shape", [(17, 45, 131), (40, 97, 5)])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_forward_3d_hotspot_balanced_launch(shape, k):
+    x0 = uniform(shape, 300.0, 350.0, 4100 + k)
+    p = uniform(shape, 0.0, 1e-3, 4101 + k)
+    for T in sorted({1, k, 2 * k + 1}):
+        check_forward(x0, "AH3", T, power=p, tuning={"variant": 2, "k": k})
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_adjoint_3d_balanced_launch(k):
+    cf = SETS["AH3"]
+    g = uniform((21, 45, 131), -1.0, 1.0, 5100 + k)
+    for T in (1, k + 1, 3 * k):
+        gx, gp = gpu_adjoint(g, cf, T, HOTSPOT, tuning={"variant": 2, "k": k})
+        rx, rp = oracle.adjoint(g, cf, T, form=HOTSPOT)
+        assert normrel(gx, rx) <= TOL, (k, T)
+        assert normrel(gp, rp) <= TOL, (k, T)
+
+
 def test_forward_3d_plain_variant():
     x0 = uniform((11, 23, 45), 0.0, 1.0, 79)
     check_forward(x0, "A3", 9, tuning={"variant": 1})
