@@ -92,6 +92,7 @@ __global__ __launch_bounds__(64) void batched2d_kernel(const BGrid* __restrict__
     a.nx = g.nx; a.ny = g.ny; a.keff = w.keff;
     a.cs = g.cs; a.kr = g.kr; a.ntx = g.ntx; a.seg = g.seg; a.nseg = g.nseg;
     a.aligned = g.aligned;
+    a.part = 0; a.ix0 = a.ix1 = a.iy0 = a.iy1 = 0;
     a.cf = g.cf;
     {
       Tb2dTile<kBatchK2, kTb2dV, false, false, false, false> t(a, threadIdx.x, nullptr);

@@ -33,9 +33,9 @@ hipError_t launch_tb3d_diff(int K, bool full, const Tb3dArgs& a, hipStream_t s);
 hipError_t launch_tb3d_hot(int K, bool full, const Tb3dArgs& a, hipStream_t s);
 hipError_t launch_tb3d_adj(int K, bool acc, bool full, const Tb3dArgs& a, hipStream_t s);
 
-// Input planes in flight per workgroup: two where the registers allow it (forward diffusion up
-// to K = 5, forward hotspot up to K = 3), else one.
-#define TB3D_PD(K, HOT, ADJ) ((!(ADJ) && ((!(HOT) && (K) <= 5) || ((HOT) && (K) <= 3))) ? 2 : 1)
+// One input plane in flight per workgroup: a second one (PD = 2) measured no faster for
+// diffusion and 27% slower for the K = 2 hotspot pass.
+#define TB3D_PD(K, HOT, ADJ) 1
 #define TB_LAUNCH3D(K, R, NW, HOT, ADJ, ACC, FULL, a, s)                                               \
   do {                                                                                                  \
     hipLaunchKernelGGL((tb3d_kernel<K, kTb3dV, R, NW, HOT, ADJ, ACC, FULL, TB3D_PD(K, HOT, ADJ)>),     \

@@ -242,6 +242,23 @@ int inst_k_for(int ndim, KMode m, int k) {
   return ks[n - 1];
 }
 
+// Interior rectangle of a 2D pass: tiles whose window lies inside the grid in x and whose
+// rows (with the keff-row halo) stay clear of the first and last grid row, i.e. the tiles for
+// which the kernel takes its edge-free body.  Both conditions are per axis, so those tiles form
+// a rectangle [*x0, *x1) x [*y0, *y1) of tile indices (empty if x0 >= x1 or y0 >= y1).
+void interior_rect2d(const Geom2D& g, int nx, int ny, int keff, int* x0, int* x1, int* y0, int* y1) {
+  const int W = 64 * kTb2dV;
+  *x0 = g.ntx; *x1 = 0; *y0 = g.nseg; *y1 = 0;
+  for (int tx = 0; tx < g.ntx; ++tx) {
+    const int ws = tx * g.cs - g.kr;
+    if (ws >= 0 && ws + W <= nx) { *x0 = std::min(*x0, tx); *x1 = std::max(*x1, tx + 1); }
+  }
+  for (int sg = 0; sg < g.nseg; ++sg) {
+    const int r0 = sg * g.seg, r1 = std::min(r0 + g.seg, ny);
+    if (r0 - keff > 0 && r1 + keff < ny) { *y0 = std::min(*y0, sg); *y1 = std::max(*y1, sg + 1); }
+  }
+}
+
 // One pass of keff fused steps from src to dst.
 hipError_t run_pass(const stencil_plan_s* p, KMode m, int K, int keff, const float* src, float* dst,
                     const float* power, float* gp, const DevCoef& cf) {
@@ -254,7 +271,29 @@ hipError_t run_pass(const stencil_plan_s* p, KMode m, int K, int keff, const flo
     a.cs = g.cs; a.kr = g.kr; a.ntx = g.ntx; a.seg = g.seg; a.nseg = g.nseg;
     a.aligned = ((p->nx & 3) == 0) && aligned16(src) && aligned16(dst) && (!power || aligned16(power)) ? 1 : 0;
     a.cf = cf;
-    return launch_tb2d(K, m, full, a, p->stream);
+    a.part = 0;
+    interior_rect2d(g, p->nx, p->ny, keff, &a.ix0, &a.ix1, &a.iy0, &a.iy1);
+    const long interior = (a.ix1 > a.ix0 && a.iy1 > a.iy0) ? (long)(a.ix1 - a.ix0) * (a.iy1 - a.iy0) : 0;
+    const long total = (long)g.ntx * g.nseg;
+    // Split when the interior kernel has enough tiles to fill the device and some tiles are
+    // edge tiles: the interior kernel, free of edge code, needs fewer registers; the frame
+    // kernel runs beside it on the side stream (fork/join through events).
+    if (!a.aligned || !p->side || interior < 1024 || interior == total) {
+      a.ix0 = a.ix1 = a.iy0 = a.iy1 = 0;
+      return launch_tb2d(K, m, full, a, p->stream);
+    }
+    hipError_t e = hipEventRecord(p->ev_fork, p->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_fork, 0);
+    if (e != hipSuccess) return e;
+    Tb2dArgs fr = a;
+    fr.part = 2;
+    e = launch_tb2d(K, m, full, fr, p->side);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_join, p->side);
+    if (e != hipSuccess) return e;
+    a.part = 1;
+    e = launch_tb2d(K, m, full, a, p->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamWaitEvent(p->stream, p->ev_join, 0);
   }
   const bool adj = (m == KM_ADJ || m == KM_ADJ_ACC);
   const Geom3D g = geom3d(K, adj, p->nx, p->ny, p->nz, p->tuning.seg_len);
@@ -263,7 +302,9 @@ hipError_t run_pass(const stencil_plan_s* p, KMode m, int K, int keff, const flo
   a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.keff = keff;
   a.csx = g.csx; a.csy = g.csy; a.krx = g.krx; a.kry = g.kry; a.ntx = g.ntx; a.nty = g.nty;
   a.segz = g.segz; a.nsegz = g.nsegz;
-  a.nwork = p->nwork3d;
+  // the balanced launch is tuned on the forward kernel; the transposed kernel (other tile
+  // height, grad_p traffic) keeps the tile launch, which measured faster for it
+  a.nwork = adj ? 0 : p->nwork3d;
   a.aligned = ((p->nx & 1) == 0) && ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 7) == 0 ? 1 : 0;
   a.cf = cf;
   return launch_tb3d(K, m, full, a, p->stream);
@@ -517,6 +558,17 @@ stencil_status_t set_device(const stencil_plan_s* p) {
   return STENCIL_OK;
 }
 
+void destroy_side(stencil_plan_s* p) {
+  if (p->side) {
+    hipStreamSynchronize(p->side);
+    hipStreamDestroy(p->side);
+  }
+  if (p->ev_fork) hipEventDestroy(p->ev_fork);
+  if (p->ev_join) hipEventDestroy(p->ev_join);
+  p->side = nullptr;
+  p->ev_fork = p->ev_join = nullptr;
+}
+
 void free_ckpts(stencil_plan_s* p) {
   for (float* c : p->ckpts) hipFree(c);
   p->ckpts.clear();
@@ -635,6 +687,16 @@ stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int nd
     hipGetLastError();
     return fail(STENCIL_ERR_OUT_OF_MEMORY, "scratch allocation failed");
   }
+  if (ndim == 2) {
+    // side stream (default priority) for the edge tiles of a 2D pass; without it every pass
+    // runs as one launch
+    if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess) {
+      destroy_side(p);
+      hipGetLastError();
+    }
+  }
   stencil_tuning_t t{};
   if (tuning) t = *tuning;
   p->tuning = t;
@@ -660,6 +722,7 @@ stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int nd
       int nwork = 0;
       stencil_status_t st = autotune(p, &tuned, &nwork);
       if (st != STENCIL_OK) {
+        destroy_side(p);
         hipFree(p->scratch);
         delete p;
         return st;
@@ -694,6 +757,7 @@ void stencil_destroy(stencil_plan_t plan) {
   if (!plan) return;
   hipSetDevice(plan->device);
   hipStreamSynchronize(plan->stream);
+  destroy_side(plan);
   free_ckpts(plan);
   hipFree(plan->scratch);
   hipFree(plan->verify_buf);

@@ -58,6 +58,9 @@ struct stencil_plan_s {
   int device;
   stencil_tuning_t tuning;  // resolved
   int nwork3d = 0;          // 3D: > 0 selects the balanced launch with this many workgroups
+  // 2D: edge tiles run on a second stream, concurrently with the interior tiles of a pass
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   float* scratch = nullptr;
   // checkpoints of the last stencil_run_ckpt
   std::vector<float*> ckpts;

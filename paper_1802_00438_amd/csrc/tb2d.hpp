@@ -50,8 +50,27 @@ struct Tb2dArgs {
   int seg;             // output rows per tile
   int nseg;            // tiles along y
   int aligned;         // 1: nx % 4 == 0 and 16-byte aligned buffers (vector access in interior tiles)
+  // Tiles of this launch: part 0 = every tile; part 1 = the interior rectangle
+  // [ix0, ix1) x [iy0, iy1) of tiles that touch no grid edge; part 2 = the frame of all others.
+  int part, ix0, ix1, iy0, iy1;
   DevCoef cf;
 };
+
+// Tile id of the i-th tile of the launch's part.
+__device__ __forceinline__ int tb2d_part_tile(const Tb2dArgs& a, int i) {
+  const int w = a.ix1 - a.ix0;
+  if (a.part == 1) return (a.iy0 + i / w) * a.ntx + a.ix0 + i % w;
+  if (a.part == 2) {
+    const int ntop = a.iy0 * a.ntx, nmid = (a.iy1 - a.iy0) * (a.ntx - w);
+    if (i < ntop) return i;
+    if (i < ntop + nmid) {
+      const int j = i - ntop, c = j % (a.ntx - w);
+      return (a.iy0 + j / (a.ntx - w)) * a.ntx + (c < a.ix0 ? c : c + w);
+    }
+    return a.iy1 * a.ntx + (i - ntop - nmid);
+  }
+  return i;
+}
 
 template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL, int D = 2>
 struct Tb2dTile {
@@ -323,6 +342,9 @@ struct Tb2dTile {
     }
   }
 
+  // INTERIOR: the tile is known to touch no grid edge and the buffers to be aligned, so only
+  // the edge-free body is compiled in (fewer registers than the kernel with every variant).
+  template <bool INTERIOR = false>
   __device__ __forceinline__ void process(int tile) {
     const int tx = tile % a.ntx;
     const int sg = tile / a.ntx;
@@ -346,24 +368,37 @@ struct Tb2dTile {
         if (isR[v]) cxp[v] = a.cf.wx_m;
       }
     }
-    if (xe) {
-      if (ye) run<true, true, false>(); else run<true, false, false>();
-    } else if (a.aligned) {
-      if (ye) run<false, true, true>(); else run<false, false, true>();
+    if constexpr (INTERIOR) {
+      run<false, false, true>();
     } else {
-      if (ye) run<false, true, false>(); else run<false, false, false>();
+      if (xe) {
+        if (ye) run<true, true, false>(); else run<true, false, false>();
+      } else if (a.aligned) {
+        if (ye) run<false, true, true>(); else run<false, false, true>();
+      } else {
+        if (ye) run<false, true, false>(); else run<false, false, false>();
+      }
     }
   }
 };
 
-template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL, int D = 2>
+// One workgroup (one wave) per tile of the launch's part (gridDim.x tiles).  INTERIOR = true
+// is the kernel for part 1; part 0 and part 2 use INTERIOR = false.
+template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL, int D, bool INTERIOR>
 __global__ __launch_bounds__(64) void tb2d_kernel(Tb2dArgs a) {
   constexpr int RING = (HOT && !ADJ) ? (K + 1) : 1;
   __shared__ __align__(16) float ring[RING * 64 * V];
-  const int ntiles = a.ntx * a.nseg;
-  const int tile = xcd_remap(blockIdx.x, ntiles);
+  const int tile = tb2d_part_tile(a, xcd_remap(blockIdx.x, gridDim.x));
   Tb2dTile<K, V, HOT, ADJ, ACC, FULL, D> t(a, threadIdx.x, ring);
-  t.process(tile);
+  t.template process<INTERIOR>(tile);
+}
+
+// Tiles in the launch of part a.part.
+inline int tb2d_part_tiles(const Tb2dArgs& a) {
+  const int interior = (a.ix1 - a.ix0) * (a.iy1 - a.iy0);
+  if (a.part == 1) return interior;
+  if (a.part == 2) return a.ntx * a.nseg - interior;
+  return a.ntx * a.nseg;
 }
 
 // Launch shape of the 2D kernels: 256-column windows (one wave, 4 cells per lane), one
@@ -374,7 +409,11 @@ constexpr int kTb2dV = 4;
 #define TB2D_DEPTH(HOT, ADJ) (((HOT) || (ADJ)) ? 2 : 4)
 #define TB_LAUNCH2D(K, HOT, ADJ, ACC, FULL, a, s)                                                       \
   do {                                                                                                  \
-    hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL, TB2D_DEPTH(HOT, ADJ)>),             \
-                       dim3((a).ntx * (a).nseg), dim3(64), 0, s, a);                                    \
+    if ((a).part == 1)                                                                                  \
+      hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL, TB2D_DEPTH(HOT, ADJ), true>),     \
+                         dim3(tb2d_part_tiles(a)), dim3(64), 0, s, a);                                  \
+    else                                                                                                \
+      hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL, TB2D_DEPTH(HOT, ADJ), false>),    \
+                         dim3(tb2d_part_tiles(a)), dim3(64), 0, s, a);                                  \
     return hipGetLastError();                                                                           \
   } while (0)

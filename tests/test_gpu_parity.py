@@ -102,6 +102,30 @@ def test_forward_2d_unaligned_width():
     check_forward(x0, "A2", 19, tuning={"variant": 2, "k": 8, "seg_len": 30})
 
 
+# Passes with at least 1024 interior tiles run as two launches on two streams: the interior
+# rectangle of tiles (edge-free kernel) and the frame of edge tiles.  These grids are wide
+# and cut into short segments so the split is taken.
+
+@pytest.mark.parametrize("k", [4, 12])
+def test_forward_2d_split_launch(k):
+    x0 = uniform((1500, 2060), 300.0, 350.0, 81 + k)
+    p = uniform((1500, 2060), 0.0, 1e-3, 82 + k)
+    for T in sorted({k, 2 * k + 3}):
+        check_forward(x0, "AH2", T, power=p, tuning={"variant": 2, "k": k, "seg_len": 8})
+        check_forward(x0, "A2", T, tuning={"variant": 2, "k": k, "seg_len": 8})
+
+
+@pytest.mark.parametrize("k", [4, 8])
+def test_adjoint_2d_split_launch(k):
+    cf = SETS["AH2"]
+    g = uniform((1500, 2060), -1.0, 1.0, 83 + k)
+    for T in (k, 2 * k + 1):
+        gx, gp = gpu_adjoint(g, cf, T, HOTSPOT, tuning={"variant": 2, "k": k, "seg_len": 8})
+        rx, rp = oracle.adjoint(g, cf, T, form=HOTSPOT)
+        assert normrel(gx, rx) <= TOL, (k, T)
+        assert normrel(gp, rp) <= TOL, (k, T)
+
+
 # ------------------------------------------------------------------ forward 3D
 
 SHAPES_3D = [(6, 6, 6), (1, 40, 37), (20, 1, 33), (9, 70, 130), (33, 50, 129), (3, 2, 300), (40, 97, 5)]
