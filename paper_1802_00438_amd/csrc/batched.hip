@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 #include "runtime.hpp"
 
@@ -209,6 +210,48 @@ std::vector<int> even_split(int T, int kcap) {
   return v;
 }
 
+// Work model of one work item: cell-levels it executes (its window times the streamed rows or
+// planes, pipeline fill included, times the kernel's K levels).  Only ratios matter: it
+// compares items of the same persistent kernel.
+double item_work2d(const Geom2D& g) { return 64.0 * kTb2dV * (g.seg + 3.0 * kBatchK2) * kBatchK2; }
+double item_work3d(const Geom3D& g) {
+  return 64.0 * kTb3dV * kTb3dR * kTb3dNW * (g.segz + 2.0 * kBatchK3 + 2.0) * kBatchK3;
+}
+
+// Segment length of every grid of one dimensionality.  A grid's passes form a chain of
+// dependent steps: pass p of a tile waits for pass p-1 of its neighbours.  With `slots`
+// resident workgroups the batch cannot finish before max(total work / slots, longest chain),
+// so grids whose chain (passes x item time) exceeds the balanced share get shorter segments
+// (shorter items, more halo work) until the chain fits, largest segment first.  Two
+// refinement rounds, since shortening a chain adds work.
+template <class GeomFn, class WorkFn>
+std::vector<int> choose_segments(const std::vector<int>& idx, const std::vector<int>& passes,
+                                 const std::vector<int>& len, const std::vector<int>& cands, double slots,
+                                 GeomFn geom, WorkFn work) {
+  std::vector<int> seg(passes.size(), 0);
+  for (int i : idx) seg[i] = std::min(len[i], cands.front());
+  for (int round = 0; round < 3; ++round) {
+    double total = 0.0;
+    for (int i : idx) {
+      const auto g = geom(i, seg[i]);
+      total += passes[i] * (double)g.first * work(g.second);
+    }
+    const double share = total / slots;
+    for (int i : idx) {
+      int pick = std::min(len[i], cands.back());
+      for (int c : cands) {
+        const int sgl = std::min(len[i], c);
+        if (passes[i] * work(geom(i, sgl).second) <= share) {
+          pick = sgl;
+          break;
+        }
+      }
+      seg[i] = pick;
+    }
+  }
+  return seg;
+}
+
 stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t stream, stencil_batch_s** out) {
   stencil_batch_s* b = new stencil_batch_s();
   b->stream = stream;
@@ -216,9 +259,9 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
   b->items.assign(items, items + n);
   std::vector<BGrid> grids(n);
   std::vector<std::vector<int>> steps(n);
-  std::vector<int> ntiles(n);
+  std::vector<int> ntiles(n), passes(n), len(n);
+  std::vector<int> idx2, idx3;
   int nflags = 0;
-  int maxP = 0;
   for (int i = 0; i < n; ++i) {
     const stencil_batch_item_t& it = items[i];
     BGrid& g = grids[i];
@@ -239,35 +282,80 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
     // pass costs the same for any number of fused steps up to that (levels past keff forward
     // their input), so each grid takes the fewest passes (even, so the result lands in its own
     // buffer), with the steps spread evenly over them.
-    if (it.ndim == 2) {
-      // items of a batch share the device, so each item is a long y-segment (at least 512
-      // rows or the whole grid): few, large items keep the per-item flag traffic negligible
-      const int seg = std::min(g.ny, std::max(512, kBatchK2));
-      const Geom2D gg = geom2d(kBatchK2, g.nx, g.ny, seg);
+    steps[i] = even_split(it.T, it.ndim == 2 ? kBatchK2 : kBatchK3);
+    passes[i] = (int)steps[i].size();
+    len[i] = it.ndim == 2 ? g.ny : g.nz;
+    (it.ndim == 2 ? idx2 : idx3).push_back(i);
+  }
+  // resident workgroups of the two persistent kernels
+  const DeviceInfo& d = device_info();
+  int occ2 = 1, occ3 = 1;
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, batched2d_kernel, 64, 0);
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ3, batched3d_kernel, 64 * kTb3dNW, 0);
+  const int slots2 = d.cus * std::max(1, occ2), slots3 = d.cus * std::max(1, occ3);
+  auto geom2 = [&](int i, int sg) {
+    const Geom2D gg = geom2d(kBatchK2, grids[i].nx, grids[i].ny, sg);
+    return std::make_pair(gg.ntx * gg.nseg, gg);
+  };
+  auto geom3 = [&](int i, int sz) {
+    const Geom3D gg = geom3d(kBatchK3, false, grids[i].nx, grids[i].ny, grids[i].nz, sz);
+    return std::make_pair(gg.ntx * gg.nty * gg.nsegz, gg);
+  };
+  const std::vector<int> seg2 = choose_segments(idx2, passes, len, {512, 384, 256, 192, 128, 96, 64, 48}, slots2,
+                                                geom2, item_work2d);
+  const std::vector<int> seg3 = choose_segments(idx3, passes, len, {64, 48, 32, 24, 16, 12, 8}, slots3, geom3,
+                                                item_work3d);
+  std::vector<double> t_item(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    BGrid& g = grids[i];
+    if (items[i].ndim == 2) {
+      const Geom2D gg = geom2d(kBatchK2, g.nx, g.ny, seg2[i]);
       g.cs = gg.cs; g.kr = gg.kr; g.ntx = gg.ntx; g.seg = gg.seg; g.nseg = gg.nseg;
-      g.aligned = ((g.nx & 3) == 0) && ((reinterpret_cast<uintptr_t>(g.buf[0]) | reinterpret_cast<uintptr_t>(s)) & 15) == 0;
+      g.aligned = ((g.nx & 3) == 0) && ((reinterpret_cast<uintptr_t>(g.buf[0]) | reinterpret_cast<uintptr_t>(g.buf[1])) & 15) == 0;
       ntiles[i] = gg.ntx * gg.nseg;
-      steps[i] = even_split(it.T, kBatchK2);
+      t_item[i] = item_work2d(gg);
     } else {
-      // z-segments of 64 planes (at least the halo) give the 3D list enough items per pass
-      const Geom3D gg = geom3d(kBatchK3, false, g.nx, g.ny, g.nz, std::min(g.nz, 64));
+      const Geom3D gg = geom3d(kBatchK3, false, g.nx, g.ny, g.nz, seg3[i]);
       g.csx = gg.csx; g.csy = gg.csy; g.krx = gg.krx; g.kry = gg.kry; g.ntx = gg.ntx; g.nty = gg.nty;
       g.segz = gg.segz; g.nsegz = gg.nsegz;
-      g.aligned = ((g.nx & 1) == 0) && ((reinterpret_cast<uintptr_t>(g.buf[0]) | reinterpret_cast<uintptr_t>(s)) & 7) == 0;
+      g.aligned = ((g.nx & 1) == 0) && ((reinterpret_cast<uintptr_t>(g.buf[0]) | reinterpret_cast<uintptr_t>(g.buf[1])) & 7) == 0;
       ntiles[i] = gg.ntx * gg.nty * gg.nsegz;
-      steps[i] = even_split(it.T, kBatchK3);
+      t_item[i] = item_work3d(gg);
     }
     g.flag_off = nflags;
     nflags += ntiles[i];
-    maxP = std::max(maxP, (int)steps[i].size());
   }
-  std::vector<BItem> it2, it3;
-  for (int p = 0; p < maxP; ++p)
-    for (int i = 0; i < n; ++i) {
-      if (p >= (int)steps[i].size()) continue;
-      std::vector<BItem>& dst = items[i].ndim == 2 ? it2 : it3;
-      for (int t = 0; t < ntiles[i]; ++t) dst.push_back({i, p, t, steps[i][p]});
+  // Claim order: latest start time first (critical path priority).  Scheduled as late as
+  // possible against the longest chain, pass p of grid g may start no later than
+  // chain_max - (P_g - p) * t_g; sorting items by that bound starts the long chains first and
+  // lets short grids fill in.  Pass p of a grid always sorts before its pass p+1, so the list
+  // stays a topological order of the dependencies.
+  struct Keyed {
+    double lst;
+    BItem it;
+  };
+  std::vector<Keyed> k2, k3;
+  double chain2 = 0.0, chain3 = 0.0;
+  for (int i = 0; i < n; ++i) (items[i].ndim == 2 ? chain2 : chain3) = std::max(
+      items[i].ndim == 2 ? chain2 : chain3, passes[i] * t_item[i]);
+  for (int i = 0; i < n; ++i) {
+    const double chain = items[i].ndim == 2 ? chain2 : chain3;
+    for (int p = 0; p < passes[i]; ++p) {
+      const double lst = chain - (passes[i] - p) * t_item[i];
+      for (int t = 0; t < ntiles[i]; ++t) (items[i].ndim == 2 ? k2 : k3).push_back({lst, {i, p, t, steps[i][p]}});
     }
+  }
+  auto order = [](const Keyed& x, const Keyed& y) {
+    if (x.lst != y.lst) return x.lst < y.lst;
+    if (x.it.g != y.it.g) return x.it.g < y.it.g;
+    if (x.it.p != y.it.p) return x.it.p < y.it.p;
+    return x.it.tile < y.it.tile;
+  };
+  std::stable_sort(k2.begin(), k2.end(), order);
+  std::stable_sort(k3.begin(), k3.end(), order);
+  std::vector<BItem> it2, it3;
+  for (const Keyed& x : k2) it2.push_back(x.it);
+  for (const Keyed& x : k3) it3.push_back(x.it);
   b->n2 = (int)it2.size();
   b->n3 = (int)it3.size();
   b->nflags = nflags;
@@ -286,12 +374,8 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
     return st;
   }
   // persistent grid sizes: resident capacity of the device
-  const DeviceInfo& d = device_info();
-  int occ2 = 1, occ3 = 1;
-  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, batched2d_kernel, 64, 0);
-  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ3, batched3d_kernel, 64 * kTb3dNW, 0);
-  const int g2 = std::max(1, std::min(b->n2, d.cus * std::max(1, occ2)));
-  const int g3 = std::max(1, std::min(b->n3, d.cus * std::max(1, occ3)));
+  const int g2 = std::max(1, std::min(b->n2, slots2));
+  const int g3 = std::max(1, std::min(b->n3, slots3));
   // capture: reset flags/counters, then the two persistent kernels
   hipStream_t cs = nullptr;
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -314,9 +398,14 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
     release(b);
     return st;
   }
-  if (log_enabled())
+  if (log_enabled()) {
     std::fprintf(stderr, "[stencil] batch: %d grids, %d 2D items (%d WGs), %d 3D items (%d WGs)\n", n, b->n2, g2,
                  b->n3, g3);
+    for (int i = 0; i < n; ++i)
+      std::fprintf(stderr, "[stencil]   grid %d: %dD %dx%dx%d T=%d passes=%d tiles=%d seg=%d\n", i, items[i].ndim,
+                   items[i].nx, items[i].ny, items[i].nz, items[i].T, passes[i], ntiles[i],
+                   items[i].ndim == 2 ? grids[i].seg : grids[i].segz);
+  }
   *out = b;
   return STENCIL_OK;
 }
