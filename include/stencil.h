@@ -124,10 +124,11 @@ typedef struct stencil_batch_s* stencil_batch_t;
  * dimensionality, captured once in a HIP graph.  Work items (grid, pass, tile) are claimed
  * in a global dependency order by resident workgroups; an item waits only for the tiles of
  * the previous pass of its own grid that overlap its halo.  The persistent kernels fuse up to
- * 16 (2D) or 4 (3D) steps per pass on fixed tile shapes (256-column windows by 512-row
- * segments; 128 x 48 windows by 64-plane segments); each grid's T steps are spread evenly over
- * the fewest even number of passes, since a pass costs the same for any number of fused steps
- * up to the kernel's capacity.
+ * 16 (2D) or 4 (3D) steps per pass (256-column windows; 128 x 48 windows); each grid's T steps
+ * are spread evenly over the fewest even number of passes, since a pass costs the same for any
+ * number of fused steps up to the kernel's capacity.  Segment lengths (rows, planes) are chosen
+ * per grid from a work model so that no grid's chain of dependent passes outlasts the
+ * balanced share of the batch, and work items are claimed longest-chain first.
  *   graph_cache: NULL -> build, run and free everything in this call.
  *                non-NULL -> if *graph_cache is NULL, build and store the captured batch
  *                there; otherwise replay *graph_cache, which must have been built from
