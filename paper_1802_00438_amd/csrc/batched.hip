@@ -135,6 +135,7 @@ __global__ __launch_bounds__(64 * kTb3dNW) void batched3d_kernel(const BGrid* __
     a.csx = g.csx; a.csy = g.csy; a.krx = g.krx; a.kry = g.kry; a.ntx = g.ntx; a.nty = g.nty;
     a.segz = g.segz; a.nsegz = g.nsegz;
     a.nwork = 0;
+    a.ax = a.ay = a.fx = a.fy = 0;
     a.aligned = g.aligned;
     a.cf = g.cf;
     {
@@ -208,6 +209,15 @@ std::vector<int> even_split(int T, int kcap) {
   const int base = T / P, rem = T % P;
   for (int i = 0; i < P; ++i) v.push_back(base + (i < rem ? 1 : 0));
   return v;
+}
+
+// The persistent 3D kernel keeps the uniform tiling (its tile decoding has no edge-flush case).
+Geom3D batch_geom3d(const BGrid& g, int segz) {
+  Geom3D gg = geom3d(kBatchK3, false, g.nx, g.ny, g.nz, segz);
+  gg.ax = gg.ay = gg.fx = gg.fy = 0;
+  gg.ntx = (g.nx + gg.csx - 1) / gg.csx;
+  gg.nty = (g.ny + gg.csy - 1) / gg.csy;
+  return gg;
 }
 
 // Work model of one work item: cell-levels it executes (its window times the streamed rows or
@@ -298,7 +308,7 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
     return std::make_pair(gg.ntx * gg.nseg, gg);
   };
   auto geom3 = [&](int i, int sz) {
-    const Geom3D gg = geom3d(kBatchK3, false, grids[i].nx, grids[i].ny, grids[i].nz, sz);
+    const Geom3D gg = batch_geom3d(grids[i], sz);
     return std::make_pair(gg.ntx * gg.nty * gg.nsegz, gg);
   };
   const std::vector<int> seg2 = choose_segments(idx2, passes, len, {512, 384, 256, 192, 128, 96, 64, 48}, slots2,
@@ -315,7 +325,7 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
       ntiles[i] = gg.ntx * gg.nseg;
       t_item[i] = item_work2d(gg);
     } else {
-      const Geom3D gg = geom3d(kBatchK3, false, g.nx, g.ny, g.nz, seg3[i]);
+      const Geom3D gg = batch_geom3d(g, seg3[i]);
       g.csx = gg.csx; g.csy = gg.csy; g.krx = gg.krx; g.kry = gg.kry; g.ntx = gg.ntx; g.nty = gg.nty;
       g.segz = gg.segz; g.nsegz = gg.nsegz;
       g.aligned = ((g.nx & 1) == 0) && ((reinterpret_cast<uintptr_t>(g.buf[0]) | reinterpret_cast<uintptr_t>(g.buf[1])) & 7) == 0;

@@ -44,6 +44,18 @@ __device__ __forceinline__ float from_upper(float x) {
                                                                0x130 /* wave_shl:1 */, 0xf, 0xf, true));
 }
 
+// The same moves where the end lane keeps `own` (bound_ctrl off: an invalid source lane leaves
+// the destination at its old value).  In a window flush with the grid edge, lane 0 holds x = 0
+// and lane 63 holds x = nx-1, so they receive their own value: the clamp-to-edge neighbour.
+__device__ __forceinline__ float from_lower_or(float x, float own) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, own), __builtin_bit_cast(int, x),
+                                                               0x138 /* wave_shr:1 */, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_upper_or(float x, float own) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, own), __builtin_bit_cast(int, x),
+                                                               0x130 /* wave_shl:1 */, 0xf, 0xf, false));
+}
+
 // The x-1 and x+1 terms of interior cells fused with their cross-lane move: acc + w * x of
 // lane i-1 (resp. i+1) as one v_fmac_f32 whose first source is read through DPP, the same
 // single-rounding FMA as fma(w, from_lower(x), acc).  The compiler does not form it by itself

@@ -76,8 +76,24 @@ Geom3D geom3d(int K, bool adj, int nx, int ny, int nz, int segz) {
   g.csx = floor_to(WX - K - g.krx, 2);
   g.kry = K;
   g.csy = WY - 2 * K;
-  g.ntx = ceil_div(nx, g.csx);
-  g.nty = ceil_div(ny, g.csy);
+  // Grids at least one window wide (high) place the first and last window of the axis flush
+  // with the grid edge, where the clamp costs next to nothing; the tiles between are ordinary
+  // overlapped tiles.  x also needs an even width, so every window starts on an 8-byte
+  // boundary.
+  g.ax = (nx >= WX && (nx % 2) == 0) ? 1 : 0;
+  g.ay = (ny >= WY) ? 1 : 0;
+  if (g.ax) {
+    g.fx = floor_to(WX - K, 2);
+    g.ntx = nx == WX ? 1 : (nx <= 2 * g.fx ? 2 : 2 + ceil_div(nx - 2 * g.fx, g.csx));
+  } else {
+    g.ntx = ceil_div(nx, g.csx);
+  }
+  if (g.ay) {
+    g.fy = WY - K;
+    g.nty = ny == WY ? 1 : (ny <= 2 * g.fy ? 2 : 2 + ceil_div(ny - 2 * g.fy, g.csy));
+  } else {
+    g.nty = ceil_div(ny, g.csy);
+  }
   g.segz = std::max(1, std::min(segz, nz));
   g.nsegz = ceil_div(nz, g.segz);
   return g;
@@ -302,9 +318,8 @@ hipError_t run_pass(const stencil_plan_s* p, KMode m, int K, int keff, const flo
   a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.keff = keff;
   a.csx = g.csx; a.csy = g.csy; a.krx = g.krx; a.kry = g.kry; a.ntx = g.ntx; a.nty = g.nty;
   a.segz = g.segz; a.nsegz = g.nsegz;
-  // the balanced launch is tuned on the forward kernel; the transposed kernel (other tile
-  // height, grad_p traffic) keeps the tile launch, which measured faster for it
-  a.nwork = adj ? 0 : p->nwork3d;
+  a.ax = g.ax; a.ay = g.ay; a.fx = g.fx; a.fy = g.fy;
+  a.nwork = p->nwork3d;
   a.aligned = ((p->nx & 1) == 0) && ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 7) == 0 ? 1 : 0;
   a.cf = cf;
   return launch_tb3d(K, m, full, a, p->stream);
@@ -394,18 +409,18 @@ std::mutex g_tune_mu;
 struct TuneResult {
   stencil_tuning_t t;
   int nwork;
+  int adj_k, adj_seg, adj_nwork;  // the transposed pass's own blocking
 };
 std::map<TuneKey, TuneResult> g_tune_cache;
 
 // Model-ranked candidates, the best few timed on scratch memory.
-stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out, int* nwork_out) {
+stencil_status_t autotune(stencil_plan_s* p, TuneResult* out) {
   const TuneKey key{p->form, p->ndim, p->nx, p->ny, p->nz};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      *out = it->second.t;
-      *nwork_out = it->second.nwork;
+      *out = it->second;
       return STENCIL_OK;
     }
   }
@@ -467,6 +482,25 @@ stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out, int* nwork_o
   best.k = uniq[0].K;
   best.seg_len = uniq[0].seg;
   int best_nwork = uniq[0].nwork;
+  // adjoint default (untimed): the instantiated adjoint K with the least modelled time, on
+  // the forward's segment length and the tile launch
+  const KMode am = hot ? KM_ADJ_ACC : KM_ADJ;
+  int adj_k = 1, adj_seg = best.seg_len, adj_nwork = 0;
+  {
+    const int* aks;
+    const int nak = tb_instantiated(p->ndim, am, &aks);
+    double bm = 1e300;
+    for (int i = 0; i < nak; ++i) {
+      const double tm =
+          p->ndim == 2 ? model_time_2d(geom2d(aks[i], p->nx, p->ny, best.seg_len), p->nx, p->ny, Tref, hot, true)
+                       : model_time_3d(geom3d(aks[i], true, p->nx, p->ny, p->nz, best.seg_len), p->nx, p->ny, p->nz,
+                                       Tref, hot, true);
+      if (tm < bm) {
+        bm = tm;
+        adj_k = aks[i];
+      }
+    }
+  }
   const bool timed = !env_flag("STENCIL_MODEL_ONLY") && p->cells >= (size_t)1 << 16;
   if (timed) {
     // Time the top candidates on scratch memory.
@@ -527,6 +561,60 @@ stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out, int* nwork_o
           best_nwork = uniq[i].nwork;
         }
       }
+      // The transposed pass (it also reads and writes grad_p) is timed on candidates of its
+      // own: every instantiated K with a few segment lengths and, in 3D, the balanced launch;
+      // one round after a warm-up.
+      {
+        const DevCoef acf = dev_coef(c, true);
+        const int* aks;
+        const int nak = tb_instantiated(p->ndim, am, &aks);
+        struct ACand {
+          int K, seg, nwork;
+        };
+        std::vector<ACand> ac;
+        for (int i = 0; i < nak; ++i) {
+          if (p->ndim == 2) {
+            for (int sg : {best.seg_len, 96, 192, 384})
+              if (sg <= p->ny || sg == best.seg_len) ac.push_back({aks[i], sg, 0});
+          } else {
+            for (int sz : {8, 16, 32, 64})
+              if (sz <= p->nz) ac.push_back({aks[i], sz, 0});
+            ac.push_back({aks[i], p->nz, balanced_nwork3d(aks[i], true, p->nx, p->ny, p->nz, 1)});
+          }
+        }
+        auto time_adj = [&](const ACand& cd) -> double {
+          stencil_plan_s q = *p;
+          q.tuning.k = cd.K;
+          q.tuning.seg_len = cd.seg;
+          q.nwork3d = cd.nwork;
+          const double per_pass = (double)cd.K * (double)p->cells;
+          const int reps = std::max(2, std::min(64, (int)std::ceil(7e9 / per_pass)));
+          run_pass(&q, am, cd.K, cd.K, tmp, p->scratch, nullptr, pw, acf);
+          hipEventRecord(e0, p->stream);
+          for (int r = 0; r < reps; ++r) {
+            const bool even = (r % 2) == 0;
+            run_pass(&q, am, cd.K, cd.K, even ? p->scratch : tmp, even ? tmp : p->scratch, nullptr, pw, acf);
+          }
+          hipEventRecord(e1, p->stream);
+          hipEventSynchronize(e1);
+          float ms = 0;
+          hipEventElapsedTime(&ms, e0, e1);
+          return ms > 0 ? reps * per_pass / (ms * 1e-3) : 0.0;
+        };
+        double best_arate = 0;
+        for (const ACand& cd : ac) {
+          const double r = time_adj(cd);
+          if (log_enabled())
+            std::fprintf(stderr, "[stencil] tune adjoint K=%d seg=%d nwork=%d measured=%.1f GCell/s\n", cd.K, cd.seg,
+                         cd.nwork, r * 1e-9);
+          if (r > best_arate) {
+            best_arate = r;
+            adj_k = cd.K;
+            adj_seg = cd.seg;
+            adj_nwork = cd.nwork;
+          }
+        }
+      }
       hipEventDestroy(e0);
       hipEventDestroy(e1);
     }
@@ -540,10 +628,9 @@ stencil_status_t autotune(stencil_plan_s* p, stencil_tuning_t* out, int* nwork_o
                  p->ny, p->nz, best.k, best.seg_len, best_nwork);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = TuneResult{best, best_nwork};
+    g_tune_cache[key] = TuneResult{best, best_nwork, adj_k, adj_seg, adj_nwork};
   }
-  *out = best;
-  *nwork_out = best_nwork;
+  *out = TuneResult{best, best_nwork, adj_k, adj_seg, adj_nwork};
   return STENCIL_OK;
 }
 
@@ -719,19 +806,25 @@ stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int nd
         tuned.seg_len = (int)ceil_div((long)g.ntx * g.nty * nz, p->nwork3d);
       }
     } else {
-      int nwork = 0;
-      stencil_status_t st = autotune(p, &tuned, &nwork);
+      TuneResult tr;
+      stencil_status_t st = autotune(p, &tr);
       if (st != STENCIL_OK) {
         destroy_side(p);
         hipFree(p->scratch);
         delete p;
         return st;
       }
-      p->nwork3d = nwork;
+      tuned = tr.t;
+      p->nwork3d = tr.nwork;
+      p->adj_k = tr.adj_k;
+      p->adj_seg = tr.adj_seg;
+      p->adj_nwork = tr.adj_nwork;
       if (t.seg_len != 0) {
         // an explicit segment length selects the tile launch with that length
         tuned.seg_len = t.seg_len;
         p->nwork3d = 0;
+        p->adj_seg = t.seg_len;
+        p->adj_nwork = 0;
       }
     }
     p->tuning = tuned;
@@ -740,6 +833,16 @@ stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int nd
     p->tuning.variant = 2;
     p->tuning.k = std::min(t.k, tb_max_k(ndim, m));
   }
+  // A caller-fixed k (or the plain variant) also fixes the adjoint's blocking: same k and
+  // segment length, tile launch.
+  if (p->adj_k == 0) {
+    p->adj_k = p->tuning.k;
+    p->adj_seg = p->tuning.seg_len;
+    p->adj_nwork = 0;
+  }
+  if (log_enabled())
+    std::fprintf(stderr, "[stencil] plan %dx%dx%d: forward k=%d seg=%d nwork=%d, adjoint k=%d seg=%d nwork=%d\n", nx,
+                 ny, nz, p->tuning.k, p->tuning.seg_len, p->nwork3d, p->adj_k, p->adj_seg, p->adj_nwork);
   p->tuning.vec = ndim == 2 ? kTb2dV : kTb3dV;
   p->tuning.bsize_x = 64 * p->tuning.vec;
   p->tuning.bsize_y = ndim == 2 ? 0 : kTb3dR * kTb3dNW;
@@ -811,11 +914,16 @@ stencil_status_t stencil_adjoint(stencil_plan_t p, const float* cot, const float
     if (e != hipSuccess) return hip_fail(e, "fill");
   }
   const bool plain = (p->tuning.variant == 1);
-  int K = inst_k_for(p->ndim, m, std::min(std::max(1, p->tuning.k), tb_max_k(p->ndim, m)));
+  const int kreq = p->adj_k > 0 ? p->adj_k : std::max(1, p->tuning.k);
+  int K = inst_k_for(p->ndim, m, std::min(kreq, tb_max_k(p->ndim, m)));
+  // the transposed passes run on the adjoint's own blocking
+  stencil_plan_s qa = *p;
+  qa.tuning.seg_len = p->adj_seg > 0 ? p->adj_seg : p->tuning.seg_len;
+  qa.nwork3d = p->adj_nwork;
   const int kpass = plain ? 1 : K;
   int counter = 0;
   if (!recompute) {
-    return run_sequence(p, m, plain, K, split_steps(T, kpass), cot, grad_x0, p->scratch, nullptr, gp, cf, &counter);
+    return run_sequence(&qa, m, plain, K, split_steps(T, kpass), cot, grad_x0, p->scratch, nullptr, gp, cf, &counter);
   }
   // Segment-wise reverse sweep: for segment j (last to first) recompute x from checkpoint j,
   // check it reproduces checkpoint j+1 bit for bit, then run the adjoint over the segment.
@@ -847,7 +955,7 @@ stencil_status_t stencil_adjoint(stencil_plan_t p, const float* cot, const float
       if (e != hipSuccess) return hip_fail(e, "mismatch kernel");
     }
     // adjoint over this segment: lam_src -> grad_x0 (ping-pong partner scratch)
-    st = run_sequence(p, m, plain, K, split_steps(seg_T, kpass), lam_src, grad_x0, p->scratch, nullptr, gp, cf,
+    st = run_sequence(&qa, m, plain, K, split_steps(seg_T, kpass), lam_src, grad_x0, p->scratch, nullptr, gp, cf,
                       &counter);
     if (st != STENCIL_OK) return st;
     lam_src = grad_x0;

@@ -30,6 +30,7 @@ struct Geom2D {
 };
 struct Geom3D {
   int K = 0, csx = 0, csy = 0, krx = 0, kry = 0, ntx = 0, nty = 0, segz = 0, nsegz = 0;
+  int ax = 0, ay = 0, fx = 0, fy = 0;  // edge-flush tiling per axis (see Tb3dArgs)
 };
 Geom2D geom2d(int K, int nx, int ny, int seg);
 Geom3D geom3d(int K, bool adj, int nx, int ny, int nz, int segz);
@@ -58,6 +59,9 @@ struct stencil_plan_s {
   int device;
   stencil_tuning_t tuning;  // resolved
   int nwork3d = 0;          // 3D: > 0 selects the balanced launch with this many workgroups
+  // blocking of the transposed (adjoint) passes: fused steps, segment length, balanced 3D
+  // launch workgroups (0: tile launch)
+  int adj_k = 0, adj_seg = 0, adj_nwork = 0;
   // 2D: edge tiles run on a second stream, concurrently with the interior tiles of a pass
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;

@@ -44,6 +44,10 @@ struct Tb3dArgs {
   int ntx, nty;        // tiles in x, y
   int segz, nsegz;     // output planes per tile, tiles along z
   int nwork;           // > 0: balanced launch of nwork workgroups (see tb3d_kernel)
+  // Edge-flush tiling (forward kernels, grids at least one window wide/high): the first and
+  // last tile of an axis place their window flush with the grid edge and output fx (fy)
+  // cells from it; the tiles between output csx (csy) cells each.  0: uniform tiling.
+  int ax, ay, fx, fy;
   int aligned;         // 1: nx even and 8-byte aligned buffers (vector access in interior tiles)
   DevCoef cf;
 };
@@ -61,6 +65,7 @@ struct Tb3dTile {
   float cxm[V], cxp[V];
   bool isL[V], isR[V];
   bool rowTop[R], rowBot[R];  // wave-uniform: strip row is grid row 0 / ny-1
+  bool topA, botA;            // window flush with grid row 0 / ny-1 (edge-flush tiling)
   float* hal;                 // LDS: [2][K][NW][2][WX]
 
   __device__ __forceinline__ Tb3dTile(const Tb3dArgs& args, int ln, int wv, float* lds)
@@ -101,7 +106,11 @@ struct Tb3dTile {
 
   // Phase 1: source, in-plane terms of centre plane Cl (cross-wave rows from LDS buffer rbuf)
   // and the z-1 term of the oldest plane Pl, for output plane j.
-  template <bool XE, bool YE, bool ZE>
+  // XE/YE: generic clamping of every cell (windows that cross a grid edge).  EA: window flush
+  // with a grid edge (edge-flush tiling): an end lane that holds x = 0 or x = nx-1 keeps its
+  // own value in the cross-lane move, and the outermost wave of a window flush with row 0 or
+  // ny-1 takes its own edge row as the halo row, which is exactly the clamp.
+  template <bool XE, bool YE, bool ZE, bool EA>
   __device__ __forceinline__ void partial(const float (&Pl)[R][V], const float (&Cl)[R][V], float (&o)[R][V],
                                           int lev_in, int rbuf, int j) const {
     float q[R][V];
@@ -137,6 +146,14 @@ struct Tb3dTile {
         hn[v] = pn[v];
         hs[v] = ps[v];
       }
+      if constexpr (EA) {
+        const bool top = topA && wave == 0, bot = botA && wave == NW - 1;  // wave-uniform
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          hn[v] = top ? Cl[0][v] : hn[v];
+          hs[v] = bot ? Cl[R - 1][v] : hs[v];
+        }
+      }
     }
     const bool zlo = ZE && (j == 0);
     float czm = a.cf.wz_m;
@@ -149,11 +166,19 @@ struct Tb3dTile {
       if constexpr (XE) {
         wl = from_lower(Cl[r][V - 1]);
         eu = from_upper(Cl[r][0]);
+      } else if constexpr (EA) {
+        wl = from_lower_or(Cl[r][V - 1], Cl[r][0]);
+        eu = from_upper_or(Cl[r][0], Cl[r][V - 1]);
       }
       float cym = a.cf.wy_m, cyp = a.cf.wy_p;
       if constexpr (ADJ && YE) {
         if (rowTop[r]) cym = a.cf.wy_p;
         if (rowBot[r]) cyp = a.cf.wy_m;
+      }
+      if constexpr (ADJ && EA && !YE) {
+        // transposed step at a flush edge row: the leaving direction's weight on the own value
+        if (r == 0 && topA && wave == 0) cym = a.cf.wy_p;
+        if (r == R - 1 && botA && wave == NW - 1) cyp = a.cf.wy_m;
       }
 #pragma unroll
       for (int v = 0; v < V; ++v) {
@@ -169,6 +194,9 @@ struct Tb3dTile {
           xp = isR[v] ? c : xp;
           wxm = cxm[v];
           wxp = cxp[v];
+        } else if constexpr (EA && ADJ) {
+          wxm = cxm[v];  // per-lane weights: the leaving direction's weight at x = 0 / nx-1
+          wxp = cxp[v];
         }
         if constexpr (YE) {
           ym = rowTop[r] ? c : ym;
@@ -176,7 +204,7 @@ struct Tb3dTile {
         }
         if constexpr (ZE) zm = zlo ? c : zm;
         float acc;
-        if constexpr (XE) {
+        if constexpr (XE || EA) {
           acc = upd2<HOT && !ADJ>(a.cf.c0, c, wxm, xm, wxp, xp, cyp, yp, cym, ym, (HOT && !ADJ) ? q[r][v] : 0.0f);
         } else {
           acc = centre_term<HOT && !ADJ>(a.cf.c0, c, (HOT && !ADJ) ? q[r][v] : 0.0f);
@@ -251,7 +279,7 @@ struct Tb3dTile {
   // Iteration with input plane r: level s computes plane r - s.  Planes made in this
   // iteration publish their edge rows in LDS buffer ROT; phase 1 reads the centre planes'
   // edge rows published in the previous iteration (buffer ROT ^ 1).
-  template <int ROT, bool XE, bool YE, bool ZE>
+  template <int ROT, bool XE, bool YE, bool ZE, bool EA>
   __device__ __forceinline__ void step(int r) {
     float (&X)[K][R][V] = S[ROT];      // oldest planes on entry, partial sums, newest on exit
     float (&C)[K][R][V] = S[ROT ^ 1];  // centre planes
@@ -262,7 +290,7 @@ struct Tb3dTile {
       const int j = r - s;
       float o[R][V];
       if (FULL || s <= keff) {
-        partial<XE, YE, ZE>(X[s - 1], C[s - 1], o, s - 1, ROT ^ 1, j);
+        partial<XE, YE, ZE, EA>(X[s - 1], C[s - 1], o, s - 1, ROT ^ 1, j);
       } else {
 #pragma unroll
         for (int rr = 0; rr < R; ++rr)
@@ -343,7 +371,7 @@ struct Tb3dTile {
     __syncthreads();
   }
 
-  template <bool XE, bool YE>
+  template <bool XE, bool YE, bool EA>
   __device__ __forceinline__ void run() {
 #pragma unroll
     for (int b = 0; b < 2; ++b)
@@ -377,16 +405,16 @@ struct Tb3dTile {
       return (r - K <= 0 && r >= 0) || (r - K <= a.nz - 1 && r >= a.nz - 1);
     };
     for (; it < nit && edge(it); it += 2) {
-      step<0, XE, YE, true>(r0 + it);
-      step<1, XE, YE, true>(r0 + it + 1);
+      step<0, XE, YE, true, EA>(r0 + it);
+      step<1, XE, YE, true, EA>(r0 + it + 1);
     }
     for (; it < nit && !edge(it); it += 2) {
-      step<0, XE, YE, false>(r0 + it);
-      step<1, XE, YE, false>(r0 + it + 1);
+      step<0, XE, YE, false, EA>(r0 + it);
+      step<1, XE, YE, false, EA>(r0 + it + 1);
     }
     for (; it < nit; it += 2) {
-      step<0, XE, YE, true>(r0 + it);
-      step<1, XE, YE, true>(r0 + it + 1);
+      step<0, XE, YE, true, EA>(r0 + it);
+      step<1, XE, YE, true, EA>(r0 + it + 1);
     }
   }
 
@@ -401,12 +429,29 @@ struct Tb3dTile {
 
   // Output planes [zs, ze) of the x-y column (tx, ty).
   __device__ __forceinline__ void process_column(int tx, int ty, int zs, int ze) {
-    ox0 = tx * a.csx;
-    ox1 = min(ox0 + a.csx, a.nx);
-    oy0 = ty * a.csy;
-    oy1 = min(oy0 + a.csy, a.ny);
-    xw = ox0 - a.krx;
-    yw = oy0 - a.kry;
+    if (a.ax) {
+      if (a.ntx == 1) { ox0 = 0; ox1 = a.nx; xw = 0; }
+      else if (tx == 0) { ox0 = 0; ox1 = a.fx; xw = 0; }
+      else if (tx == a.ntx - 1) { ox0 = max(a.fx, a.nx - a.fx); ox1 = a.nx; xw = a.nx - WX; }
+      else { ox0 = a.fx + (tx - 1) * a.csx; ox1 = min(ox0 + a.csx, a.nx - a.fx); xw = ox0 - a.krx; }
+    } else {
+      ox0 = tx * a.csx;
+      ox1 = min(ox0 + a.csx, a.nx);
+      xw = ox0 - a.krx;
+    }
+    if (a.ay) {
+      if (a.nty == 1) { oy0 = 0; oy1 = a.ny; yw = 0; }
+      else if (ty == 0) { oy0 = 0; oy1 = a.fy; yw = 0; }
+      else if (ty == a.nty - 1) { oy0 = max(a.fy, a.ny - a.fy); oy1 = a.ny; yw = a.ny - WY; }
+      else { oy0 = a.fy + (ty - 1) * a.csy; oy1 = min(oy0 + a.csy, a.ny - a.fy); yw = oy0 - a.kry; }
+    } else {
+      oy0 = ty * a.csy;
+      oy1 = min(oy0 + a.csy, a.ny);
+      yw = oy0 - a.kry;
+    }
+    const bool xa = a.ax && (tx == 0 || tx == a.ntx - 1);
+    topA = a.ay && ty == 0;
+    botA = a.ay && ty == a.nty - 1;
     z0 = zs;
     z1 = ze;
     const bool xe = !a.aligned || (xw < 0) || (xw + WX > a.nx);
@@ -429,10 +474,18 @@ struct Tb3dTile {
       rowTop[r] = (y == 0);
       rowBot[r] = (y == a.ny - 1);
     }
-    if (xe) {
-      if (ye) run<true, true>(); else run<true, false>();
+    // A window that needs generic clamping on one axis takes the generic body on the other
+    // axis too when that axis has a flush window (the generic bodies clamp any placement).
+    const bool gx = xe || (ye && xa);
+    const bool gy = ye || (xe && (topA || botA));
+    if (gx) {
+      if (gy) run<true, true, false>(); else run<true, false, false>();
+    } else if (gy) {
+      run<false, true, false>();
+    } else if (xa || topA || botA) {
+      run<false, false, true>();
     } else {
-      if (ye) run<false, true>(); else run<false, false>();
+      run<false, false, false>();
     }
   }
 };

@@ -128,7 +128,11 @@ def test_adjoint_2d_split_launch(k):
 
 # ------------------------------------------------------------------ forward 3D
 
-SHAPES_3D = [(6, 6, 6), (1, 40, 37), (20, 1, 33), (9, 70, 130), (33, 50, 129), (3, 2, 300), (40, 97, 5)]
+# The last three shapes take the edge-flush tiling of forward passes (first and last window
+# of an axis flush with the grid edge): one window exactly the grid's size, two flush
+# windows, and flush windows with ordinary tiles between them.
+SHAPES_3D = [(6, 6, 6), (1, 40, 37), (20, 1, 33), (9, 70, 130), (33, 50, 129), (3, 2, 300), (40, 97, 5),
+             (7, 48, 128), (11, 96, 256), (20, 150, 400)]
 
 
 @pytest.mark.parametrize("shape", SHAPES_3D)
@@ -139,7 +143,7 @@ def test_forward_3d_diffusion_all_k(shape, k):
         check_forward(x0, "A3", T, tuning={"variant": 2, "k": k, "seg_len": 7})
 
 
-@pytest.mark.parametrize("shape", [(6, 6, 6), (17, 45, 131), (1, 60, 61)])
+@pytest.mark.parametrize("shape", [(6, 6, 6), (17, 45, 131), (1, 60, 61), (5, 96, 256)])
 @pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_forward_3d_hotspot_all_k(shape, k):
     x0 = uniform(shape, 300.0, 350.0, 4000 + k)
@@ -152,7 +156,8 @@ def test_forward_3d_hotspot_all_k(shape, k):
 # With k given and no segment length, a 3D plan uses the balanced launch: every workgroup
 # streams an equal share of (x-y column, plane) units, crossing column boundaries mid-share.
 
-@pytest.mark.parametrize("shape", [(6, 6, 6), (9, 70, 130), (33, 50, 129), (3, 2, 300), (70, 40, 37)])
+@pytest.mark.parametrize("shape", [(6, 6, 6), (9, 70, 130), (33, 50, 129), (3, 2, 300), (70, 40, 37),
+                                   (20, 150, 400)])
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
 def test_forward_3d_diffusion_balanced_launch(shape, k):
     x0 = uniform(shape, 0.0, 1.0, 3100 + k)
@@ -160,7 +165,7 @@ def test_forward_3d_diffusion_balanced_launch(shape, k):
         check_forward(x0, "A3", T, tuning={"variant": 2, "k": k})
 
 
-@pytest.mark.parametrize("shape", [(17, 45, 131), (40, 97, 5)])
+@pytest.mark.parametrize("shape", [(17, 45, 131), (40, 97, 5), (9, 150, 400)])
 @pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_forward_3d_hotspot_balanced_launch(shape, k):
     x0 = uniform(shape, 300.0, 350.0, 4100 + k)
@@ -178,6 +183,21 @@ def test_adjoint_3d_balanced_launch(k):
         rx, rp = oracle.adjoint(g, cf, T, form=HOTSPOT)
         assert normrel(gx, rx) <= TOL, (k, T)
         assert normrel(gp, rp) <= TOL, (k, T)
+
+
+@pytest.mark.parametrize("shape,cset,form", [((24, 100, 260), "AH3", HOTSPOT), ((30, 64, 130), "A3", DIFFUSION),
+                                             ((700, 1200), "AH2", HOTSPOT)])
+def test_adjoint_autotuned_plan(shape, cset, form):
+    """Auto-tuned plans time the adjoint's own candidates (k, segment, balanced launch in 3D);
+    whichever wins must match the oracle."""
+    cf = SETS[cset]
+    g = uniform(shape, -1.0, 1.0, 5200)
+    for T in (7, 16):
+        gx, gp = gpu_adjoint(g, cf, T, form)
+        rx, rp = oracle.adjoint(g, cf, T, form=form)
+        assert normrel(gx, rx) <= TOL, (shape, T)
+        if form == HOTSPOT:
+            assert normrel(gp, rp) <= TOL, (shape, T)
 
 
 def test_forward_3d_plain_variant():
