@@ -56,22 +56,18 @@ __device__ __forceinline__ float from_upper_or(float x, float own) {
                                                                0x130 /* wave_shl:1 */, 0xf, 0xf, false));
 }
 
-// The x-1 and x+1 terms of interior cells fused with their cross-lane move: acc + w * x of
-// lane i-1 (resp. i+1) as one v_fmac_f32 whose first source is read through DPP, the same
-// single-rounding FMA as fma(w, from_lower(x), acc).  The compiler does not form it by itself
-// because a DPP instruction cannot take its other operand from an SGPR, so the weight is
-// passed in a VGPR.  "s_nop 1" provides the two wait states a DPP read needs after a VALU
-// write of its source register.  End lanes read 0 and leave acc unchanged; they only ever
-// hold halo columns.
-__device__ __forceinline__ float fma_from_lower(float w, float x, float acc) {
-  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
-      : "+v"(acc) : "v"(x), "v"(w));
-  return acc;
-}
-__device__ __forceinline__ float fma_from_upper(float w, float x, float acc) {
-  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
-      : "+v"(acc) : "v"(x), "v"(w));
-  return acc;
+// The x-1 and x+1 terms of an interior row fused with their cross-lane moves: al += wl * xl of
+// lane i-1 and au += wu * xu of lane i+1, each one v_fmac_f32 whose first source is read
+// through DPP -- the same single-rounding FMA as fma(wl, from_lower(xl), al).  The compiler
+// does not form these itself because a DPP instruction cannot take its other operand from an
+// SGPR, so the weights are passed in VGPRs.  One "s_nop 1" before the pair provides the two
+// wait states a DPP read needs after a VALU write of its source register.  End lanes read 0
+// and leave their accumulator unchanged; they only ever hold halo columns.
+__device__ __forceinline__ void fma_pair_dpp(float wl, float xl, float& al, float wu, float xu, float& au) {
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %2, %3 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %1, %4, %5 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "+v"(al), "+v"(au)
+      : "v"(xl), "v"(wl), "v"(xu), "v"(wu));
 }
 
 // gfx950 dispatches consecutive workgroup ids round-robin over its 8 XCDs, each with a

@@ -37,6 +37,15 @@
 #pragma once
 #include "device_common.hpp"
 
+// Rows of the hotspot source ring: at least K+1.  Rounded up to a power of two (the slot
+// index becomes a mask instead of a compare-and-select per level) when that wastes less than
+// a third of the ring, so the LDS footprint does not cost a wave per SIMD.
+constexpr int tb2d_ring_rows(int K) {
+  int p = 1;
+  while (p < K + 1) p *= 2;
+  return 3 * p <= 4 * (K + 1) ? p : K + 1;
+}
+
 struct Tb2dArgs {
   const float* src;
   float* dst;
@@ -77,7 +86,8 @@ struct Tb2dTile {
   static_assert(V == 4 || V == 8, "V");
   static_assert(D == 2 || D == 4 || D == 6, "prefetch depth must be even");
   static constexpr int W = 64 * V;    // window width
-  static constexpr int RING = K + 1;  // hotspot source rows kept in LDS
+  static constexpr int RING = tb2d_ring_rows(K);  // hotspot source rows kept in LDS
+  static constexpr bool RING_POW2 = (RING & (RING - 1)) == 0;
 
   const Tb2dArgs& a;
   const int lane;
@@ -120,7 +130,8 @@ struct Tb2dTile {
   __device__ __forceinline__ void read_q(int s, float (&q)[V]) const {
     if constexpr (HOT && !ADJ) {
       int qs = slot0 - s;
-      if (qs < 0) qs += RING;
+      if constexpr (RING_POW2) qs &= RING - 1;
+      else if (qs < 0) qs += RING;
       const float* qp = ring + qs * W + lane * V;
 #pragma unroll
       for (int h = 0; h < V; h += 4) {
@@ -158,16 +169,27 @@ struct Tb2dTile {
         wxp = cxp[v];
       }
       if constexpr (YE) yp = bot ? c : yp;
-      float acc = centre_term<HOT && !ADJ>(a.cf.c0, c, (HOT && !ADJ) ? q[v] : 0.0f);
       if constexpr (XE) {
+        float acc = centre_term<HOT && !ADJ>(a.cf.c0, c, (HOT && !ADJ) ? q[v] : 0.0f);
         acc = __builtin_fmaf(wxm, xm, acc);
         acc = __builtin_fmaf(wxp, xp, acc);
-      } else {
-        acc = (v > 0) ? __builtin_fmaf(wxm, xm, acc) : fma_from_lower(wxm, Cr[V - 1], acc);
-        acc = (v < V - 1) ? __builtin_fmaf(wxp, xp, acc) : fma_from_upper(wxp, Cr[0], acc);
+        acc = __builtin_fmaf(cyp, yp, acc);
+        o[v] = acc;
       }
-      acc = __builtin_fmaf(cyp, yp, acc);
-      o[v] = acc;
+    }
+    if constexpr (!XE) {
+      // Same term order per cell; the row's two cross-lane terms (x-1 of the first cell, x+1
+      // of the last) are issued together behind one DPP hazard wait.
+      float acc[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[v] = centre_term<HOT && !ADJ>(a.cf.c0, Cr[v], (HOT && !ADJ) ? q[v] : 0.0f);
+#pragma unroll
+      for (int v = 1; v < V; ++v) acc[v] = __builtin_fmaf(a.cf.wx_m, Cr[v - 1], acc[v]);
+      fma_pair_dpp(a.cf.wx_m, Cr[V - 1], acc[0], a.cf.wx_p, Cr[0], acc[V - 1]);
+#pragma unroll
+      for (int v = 0; v < V - 1; ++v) acc[v] = __builtin_fmaf(a.cf.wx_p, Cr[v + 1], acc[v]);
+#pragma unroll
+      for (int v = 0; v < V; ++v) o[v] = __builtin_fmaf(cyp, (YE && bot) ? Cr[v] : Pr[v], acc[v]);
     }
   }
 
@@ -303,7 +325,10 @@ struct Tb2dTile {
 #pragma unroll
         for (int v = 0; v < V; ++v) Pp[s][v] = Pn[s][v];
     }
-    if constexpr (HOT && !ADJ) slot0 = (slot0 + 1 == RING) ? 0 : slot0 + 1;
+    if constexpr (HOT && !ADJ) {
+      if constexpr (RING_POW2) slot0 = (slot0 + 1) & (RING - 1);
+      else slot0 = (slot0 + 1 == RING) ? 0 : slot0 + 1;
+    }
   }
 
   template <bool XE, bool YE, bool VEC>
@@ -386,7 +411,7 @@ struct Tb2dTile {
 // is the kernel for part 1; part 0 and part 2 use INTERIOR = false.
 template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL, int D, bool INTERIOR>
 __global__ __launch_bounds__(64) void tb2d_kernel(Tb2dArgs a) {
-  constexpr int RING = (HOT && !ADJ) ? (K + 1) : 1;
+  constexpr int RING = (HOT && !ADJ) ? tb2d_ring_rows(K) : 1;
   __shared__ __align__(16) float ring[RING * 64 * V];
   const int tile = tb2d_part_tile(a, xcd_remap(blockIdx.x, gridDim.x));
   Tb2dTile<K, V, HOT, ADJ, ACC, FULL, D> t(a, threadIdx.x, ring);

@@ -203,18 +203,39 @@ struct Tb3dTile {
           yp = rowBot[r] ? c : yp;
         }
         if constexpr (ZE) zm = zlo ? c : zm;
-        float acc;
         if constexpr (XE || EA) {
-          acc = upd2<HOT && !ADJ>(a.cf.c0, c, wxm, xm, wxp, xp, cyp, yp, cym, ym, (HOT && !ADJ) ? q[r][v] : 0.0f);
-        } else {
-          acc = centre_term<HOT && !ADJ>(a.cf.c0, c, (HOT && !ADJ) ? q[r][v] : 0.0f);
-          acc = (v > 0) ? __builtin_fmaf(wxm, xm, acc) : fma_from_lower(wxm, Cl[r][V - 1], acc);
-          acc = (v < V - 1) ? __builtin_fmaf(wxp, xp, acc) : fma_from_upper(wxp, Cl[r][0], acc);
-          acc = __builtin_fmaf(cyp, yp, acc);
-          acc = __builtin_fmaf(cym, ym, acc);
+          float acc =
+              upd2<HOT && !ADJ>(a.cf.c0, c, wxm, xm, wxp, xp, cyp, yp, cym, ym, (HOT && !ADJ) ? q[r][v] : 0.0f);
+          o[r][v] = __builtin_fmaf(czm, zm, acc);
         }
-        acc = __builtin_fmaf(czm, zm, acc);
-        o[r][v] = acc;
+      }
+      if constexpr (!XE && !EA) {
+        // Same term order per cell; the row's two cross-lane terms (x-1 of the first cell,
+        // x+1 of the last) are issued together behind one DPP hazard wait.
+        float acc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          acc[v] = centre_term<HOT && !ADJ>(a.cf.c0, Cl[r][v], (HOT && !ADJ) ? q[r][v] : 0.0f);
+#pragma unroll
+        for (int v = 1; v < V; ++v) acc[v] = __builtin_fmaf(a.cf.wx_m, Cl[r][v - 1], acc[v]);
+        fma_pair_dpp(a.cf.wx_m, Cl[r][V - 1], acc[0], a.cf.wx_p, Cl[r][0], acc[V - 1]);
+#pragma unroll
+        for (int v = 0; v < V - 1; ++v) acc[v] = __builtin_fmaf(a.cf.wx_p, Cl[r][v + 1], acc[v]);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const float c = Cl[r][v];
+          float ym = (r > 0) ? Cl[r - 1][v] : hn[v];
+          float yp = (r < R - 1) ? Cl[r + 1][v] : hs[v];
+          float zm = Pl[r][v];
+          if constexpr (YE) {
+            ym = rowTop[r] ? c : ym;
+            yp = rowBot[r] ? c : yp;
+          }
+          if constexpr (ZE) zm = zlo ? c : zm;
+          float t = __builtin_fmaf(cyp, yp, acc[v]);
+          t = __builtin_fmaf(cym, ym, t);
+          o[r][v] = __builtin_fmaf(czm, zm, t);
+        }
       }
     }
   }
