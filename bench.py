@@ -150,7 +150,7 @@ def main():
                          "calibrating memory counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the slab "
+        print("bench.py measures one GPU only: this library has no multi-GPU path (the slab "
               "decomposition over xGMI is design-only).", file=sys.stderr)
         sys.exit(2)
 

@@ -38,7 +38,7 @@ extern "C" {
 typedef enum {
   STENCIL_OK = 0,
   STENCIL_ERR_INVALID_ARG = -1,   /* bad pointer, size, step count, coefficient, form */
-  STENCIL_ERR_UNSUPPORTED = -2,   /* valid request this build does not implement */
+  STENCIL_ERR_UNSUPPORTED = -2,   /* valid request the library does not implement */
   STENCIL_ERR_OUT_OF_MEMORY = -3, /* device allocation of plan-owned memory failed */
   STENCIL_ERR_HIP = -4,           /* a HIP runtime call failed (message in stencil_last_error) */
   STENCIL_ERR_INTERNAL = -5       /* invariant violated inside the library */
@@ -109,7 +109,7 @@ stencil_status_t stencil_adjoint(stencil_plan_t plan, const float* cotangent, co
 
 /* One grid of a batch. */
 typedef struct {
-  stencil_form_t form; /* DIFFUSION only in this build (HOTSPOT returns UNSUPPORTED) */
+  stencil_form_t form; /* DIFFUSION only (HOTSPOT returns UNSUPPORTED) */
   int ndim, nx, ny, nz;
   float* grid;         /* device, in/out */
   const float* power;  /* unused for diffusion */
