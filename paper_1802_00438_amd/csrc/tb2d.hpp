@@ -429,16 +429,18 @@ inline int tb2d_part_tiles(const Tb2dArgs& a) {
 // Launch shape of the 2D kernels: 256-column windows (one wave, 4 cells per lane), one
 // workgroup per (x tile, row segment).
 constexpr int kTb2dV = 4;
-// Rows in flight per wave: four for diffusion, two where the hotspot source ring or the
-// adjoint's running sums already take the registers (three resp. two waves per SIMD).
-#define TB2D_DEPTH(HOT, ADJ) (((HOT) || (ADJ)) ? 2 : 4)
+// Rows in flight per wave: four for diffusion; two where the hotspot source ring or the
+// adjoint's running sums already take the registers, except in the edge-free hotspot kernel
+// for 8 < K <= 12, which has the registers for four at the same two waves per SIMD (+7%).
+#define TB2D_DEPTH(K, HOT, ADJ, INTERIOR) \
+  ((!(HOT) && !(ADJ)) ? 4 : ((HOT) && !(ADJ) && (INTERIOR) && (K) > 8 && (K) <= 12) ? 4 : 2)
 #define TB_LAUNCH2D(K, HOT, ADJ, ACC, FULL, a, s)                                                       \
   do {                                                                                                  \
     if ((a).part == 1)                                                                                  \
-      hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL, TB2D_DEPTH(HOT, ADJ), true>),     \
+      hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL, TB2D_DEPTH(K, HOT, ADJ, true), true>), \
                          dim3(tb2d_part_tiles(a)), dim3(64), 0, s, a);                                  \
     else                                                                                                \
-      hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL, TB2D_DEPTH(HOT, ADJ), false>),    \
+      hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL, TB2D_DEPTH(K, HOT, ADJ, false), false>), \
                          dim3(tb2d_part_tiles(a)), dim3(64), 0, s, a);                                  \
     return hipGetLastError();                                                                           \
   } while (0)
