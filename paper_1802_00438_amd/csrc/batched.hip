@@ -27,6 +27,7 @@ namespace {
 
 constexpr int kBatchK2 = 16;  // fused-step capacity of the 2D persistent kernel
 constexpr int kBatchK3 = 4;   // and of the 3D one
+constexpr int kBatchR3 = tb3d_rows(kBatchK3, false), kBatchNW3 = tb3d_waves(kBatchK3, false);
 
 struct BGrid {
   float* buf[2];  // buf[0] = caller's grid, buf[1] = scratch
@@ -104,10 +105,10 @@ __global__ __launch_bounds__(64) void batched2d_kernel(const BGrid* __restrict__
   }
 }
 
-__global__ __launch_bounds__(64 * kTb3dNW) void batched3d_kernel(const BGrid* __restrict__ grids,
+__global__ __launch_bounds__(64 * kBatchNW3) void batched3d_kernel(const BGrid* __restrict__ grids,
                                                                  const BItem* __restrict__ items, int nitems,
                                                                  int* counter, int* flags) {
-  __shared__ __align__(16) float hal[2 * kBatchK3 * kTb3dNW * 2 * 64 * kTb3dV];
+  __shared__ __align__(16) float hal[2 * kBatchK3 * kBatchNW3 * 2 * 64 * kTb3dV];
   __shared__ int sh;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (;;) {
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(64 * kTb3dNW) void batched3d_kernel(const BGrid* __
     a.aligned = g.aligned;
     a.cf = g.cf;
     {
-      Tb3dTile<kBatchK3, kTb3dV, kTb3dR, kTb3dNW, false, false, false, false> t(a, threadIdx.x & 63, threadIdx.x >> 6,
+      Tb3dTile<kBatchK3, kTb3dV, kBatchR3, kBatchNW3, false, false, false, false> t(a, threadIdx.x & 63, threadIdx.x >> 6,
                                                                                  hal);
       t.process(w.tile);
     }
@@ -225,7 +226,7 @@ Geom3D batch_geom3d(const BGrid& g, int segz) {
 // compares items of the same persistent kernel.
 double item_work2d(const Geom2D& g) { return 64.0 * kTb2dV * (g.seg + 3.0 * kBatchK2) * kBatchK2; }
 double item_work3d(const Geom3D& g) {
-  return 64.0 * kTb3dV * kTb3dR * kTb3dNW * (g.segz + 2.0 * kBatchK3 + 2.0) * kBatchK3;
+  return 64.0 * kTb3dV * kTb3dWY * (g.segz + 2.0 * kBatchK3 + 2.0) * kBatchK3;
 }
 
 // Segment length of every grid of one dimensionality.  A grid's passes form a chain of
@@ -301,7 +302,7 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
   const DeviceInfo& d = device_info();
   int occ2 = 1, occ3 = 1;
   hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, batched2d_kernel, 64, 0);
-  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ3, batched3d_kernel, 64 * kTb3dNW, 0);
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ3, batched3d_kernel, 64 * kBatchNW3, 0);
   const int slots2 = d.cus * std::max(1, occ2), slots3 = d.cus * std::max(1, occ3);
   auto geom2 = [&](int i, int sg) {
     const Geom2D gg = geom2d(kBatchK2, grids[i].nx, grids[i].ny, sg);
@@ -397,7 +398,7 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
       hipLaunchKernelGGL(batched2d_kernel, dim3(g2), dim3(64), 0, cs, b->d_grids, b->d_items2, b->n2, b->d_counters,
                          b->d_flags);
     if (b->n3)
-      hipLaunchKernelGGL(batched3d_kernel, dim3(g3), dim3(64 * kTb3dNW), 0, cs, b->d_grids, b->d_items3, b->n3,
+      hipLaunchKernelGGL(batched3d_kernel, dim3(g3), dim3(64 * kBatchNW3), 0, cs, b->d_grids, b->d_items3, b->n3,
                          b->d_counters + 1, b->d_flags);
     e = hipStreamEndCapture(cs, &b->graph);
   }

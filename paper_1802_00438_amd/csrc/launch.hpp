@@ -10,8 +10,14 @@
 enum KMode { KM_DIFF = 0, KM_HOT = 1, KM_ADJ = 2, KM_ADJ_ACC = 3 };
 
 // Tile shapes of the temporal-blocked kernels.
-constexpr int kTb3dV = 2, kTb3dR = 6, kTb3dNW = 8;       // forward: 128 x 48 x-y window, 512 threads
-constexpr int kTb3dAdjR = 4, kTb3dAdjNW = 8;            // adjoint: 128 x 32 window
+// 3D windows: 128 x 48 cells forward, 128 x 32 for the transposed (adjoint) step.  The
+// forward window is split over the workgroup's waves as 16 waves of 3 rows (1024 threads, four
+// waves per SIMD) where the K-level state fits in 128 VGPRs and the halo rows in LDS, else as
+// 8 waves of 6 rows (two waves per SIMD).  Both splits give the same tiles.
+constexpr int kTb3dV = 2, kTb3dWY = 48, kTb3dAdjWY = 32;
+constexpr int kTb3dAdjR = 4, kTb3dAdjNW = 8;
+constexpr int tb3d_rows(int K, bool hot) { return (hot ? K <= 3 : K <= 4) ? 3 : 6; }
+constexpr int tb3d_waves(int K, bool hot) { return kTb3dWY / tb3d_rows(K, hot); }
 
 // Largest fused-step count instantiated per (dimensionality, mode); every k in
 // [1, max] is served by the smallest instantiated K >= k (levels past k forward their input).

@@ -71,7 +71,7 @@ Geom3D geom3d(int K, bool adj, int nx, int ny, int nz, int segz) {
   Geom3D g;
   g.K = K;
   const int WX = 64 * kTb3dV;
-  const int WY = (adj ? kTb3dAdjR * kTb3dAdjNW : kTb3dR * kTb3dNW);
+  const int WY = adj ? kTb3dAdjWY : kTb3dWY;
   g.krx = round_up(K, 2);
   g.csx = floor_to(WX - K - g.krx, 2);
   g.kry = K;
@@ -126,7 +126,7 @@ double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj
 double model_time_3d(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj) {
   const DeviceInfo& d = device_info();
   const int WX = 64 * kTb3dV;
-  const int WY = adj ? kTb3dAdjR * kTb3dAdjNW : kTb3dR * kTb3dNW;
+  const int WY = adj ? kTb3dAdjWY : kTb3dWY;
   const long passes = (T + g.K - 1) / g.K;
   const double tiles = (double)g.ntx * g.nty * g.nsegz;
   const double planes = (double)g.segz + 2.0 * g.K;
@@ -144,7 +144,7 @@ double model_time_3d(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, 
 double model_time_3d_bal(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj, int nwork) {
   const DeviceInfo& d = device_info();
   const int WX = 64 * kTb3dV;
-  const int WY = adj ? kTb3dAdjR * kTb3dAdjNW : kTb3dR * kTb3dNW;
+  const int WY = adj ? kTb3dAdjWY : kTb3dWY;
   const long passes = (T + g.K - 1) / g.K;
   const double units = (double)g.ntx * g.nty * nz;
   const double share = units / nwork;
@@ -856,7 +856,7 @@ stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int nd
                  ny, nz, p->tuning.k, p->tuning.seg_len, p->nwork3d, p->adj_k, p->adj_seg, p->adj_nwork);
   p->tuning.vec = ndim == 2 ? kTb2dV : kTb3dV;
   p->tuning.bsize_x = 64 * p->tuning.vec;
-  p->tuning.bsize_y = ndim == 2 ? 0 : kTb3dR * kTb3dNW;
+  p->tuning.bsize_y = ndim == 2 ? 0 : kTb3dWY;
   *out = p;
   return STENCIL_OK;
 }
