@@ -15,7 +15,7 @@ enum KMode { KM_DIFF = 0, KM_HOT = 1, KM_ADJ = 2, KM_ADJ_ACC = 3 };
 // waves per SIMD) where the K-level state fits in 128 VGPRs and the halo rows in LDS, else as
 // 8 waves of 6 rows (two waves per SIMD).  Both splits give the same tiles.
 constexpr int kTb3dV = 2, kTb3dWY = 48, kTb3dAdjWY = 32;
-constexpr int kTb3dAdjR = 4, kTb3dAdjNW = 8;
+constexpr int kTb3dAdjR = 2, kTb3dAdjNW = 16;
 constexpr int tb3d_rows(int K, bool hot) { return (hot ? K <= 3 : K <= 4) ? 3 : 6; }
 constexpr int tb3d_waves(int K, bool hot) { return kTb3dWY / tb3d_rows(K, hot); }
 
