@@ -357,3 +357,42 @@ def test_t0_is_identity_and_nan_free_small_grids():
         x0 = uniform(shape, 0.0, 1.0, 9)
         check_forward(x0, "A2" if len(shape) == 2 else "A3", 0)
         check_forward(x0, "A2" if len(shape) == 2 else "A3", 7)
+
+
+# ------------------------------------------------------------------ graph capture
+
+@pytest.mark.parametrize("shape,cset,hot,tuning,T", [
+    ((1500, 2060), "AH2", True, {"variant": 2, "k": 8, "seg_len": 8}, 27),   # split 2D pass (two streams)
+    ((40, 70, 130), "A3", False, {"variant": 2, "k": 3}, 10),                # balanced 3D launch
+])
+def test_stencil_run_captured_in_a_graph(shape, cset, hot, tuning, T):
+    """stencil_run enqueued on a capturing stream records into a HIP graph (kernels, the
+    parity copy, the fork/join of the 2D edge-tile stream); every replay must equal the same
+    steps run eagerly, with eager work and synchronisation between the replays."""
+    cf = SETS[cset]
+    x0 = uniform(shape, 300.0 if hot else 0.0, 350.0 if hot else 1.0, 90)
+    p = dev(uniform(shape, 0.0, 1e-3, 91)) if hot else None
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan = S.Plan(HOTSPOT if hot else DIFFUSION, shape, tuning)
+        ref_plan = S.Plan(HOTSPOT if hot else DIFFUSION, shape, tuning)
+    try:
+        x = dev(x0)
+        y = dev(x0)
+        with torch.cuda.stream(s):
+            plan.run(x, cf, T, p)  # warm-up outside the capture
+            ref_plan.run(y, cf, T, p)
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            plan.run(x, cf, T, p)
+        for _ in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                ref_plan.run(y, cf, T, p)
+            s.synchronize()
+            assert torch.equal(x, y)
+    finally:
+        plan.close()
+        ref_plan.close()
