@@ -209,30 +209,45 @@ struct Tb2dTile {
     }
   }
 
-  template <bool XE>
+  // VEC tiles (nx % 4 == 0, aligned buffers) have window starts, halos, output widths and nx
+  // all multiples of 4, so a lane's cells are all inside the output range or all outside it:
+  // one predicate and one 16-byte access per lane.
+  template <bool XE, bool VEC>
   __device__ __forceinline__ void store_row(int j, const float (&o)[V], float* base) const {
     float* rowp = base + (size_t)j * a.nx;
     const int x0 = ws + lane * V;
-    if constexpr (!XE) {
-      if (a.aligned && x0 >= ox0 && x0 + V <= ox1) {
+    if constexpr (!XE && VEC) {
+      if (x0 >= ox0 && x0 < ox1) {
 #pragma unroll
         for (int h = 0; h < V; h += 4)
           *reinterpret_cast<float4*>(rowp + x0 + h) = make_float4(o[h], o[h + 1], o[h + 2], o[h + 3]);
-        return;
       }
-    }
+    } else {
 #pragma unroll
-    for (int v = 0; v < V; ++v)
-      if (x0 + v >= ox0 && x0 + v < ox1) rowp[x0 + v] = o[v];
+      for (int v = 0; v < V; ++v)
+        if (x0 + v >= ox0 && x0 + v < ox1) rowp[x0 + v] = o[v];
+    }
   }
 
-  template <bool XE>
+  template <bool XE, bool VEC>
   __device__ __forceinline__ void accum_gp(int j, const float (&e)[V]) const {
     float* rowp = a.gp + (size_t)j * a.nx;
     const int x0 = ws + lane * V;
+    if constexpr (!XE && VEC) {
+      if (x0 >= ox0 && x0 < ox1) {
 #pragma unroll
-    for (int v = 0; v < V; ++v)
-      if (x0 + v >= ox0 && x0 + v < ox1) rowp[x0 + v] = __builtin_fmaf(a.cf.cp, e[v], rowp[x0 + v]);
+        for (int h = 0; h < V; h += 4) {
+          float4* q = reinterpret_cast<float4*>(rowp + x0 + h);
+          const float4 g = *q;
+          *q = make_float4(__builtin_fmaf(a.cf.cp, e[h], g.x), __builtin_fmaf(a.cf.cp, e[h + 1], g.y),
+                           __builtin_fmaf(a.cf.cp, e[h + 2], g.z), __builtin_fmaf(a.cf.cp, e[h + 3], g.w));
+        }
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (x0 + v >= ox0 && x0 + v < ox1) rowp[x0 + v] = __builtin_fmaf(a.cf.cp, e[v], rowp[x0 + v]);
+    }
   }
 
   // One iteration: input row r arrives (rows stream downwards in index), level s makes row r+s.
@@ -310,12 +325,12 @@ struct Tb2dTile {
 #pragma unroll
         for (int v = 0; v < V; ++v) X[s][v] = o[v];
       } else if (j >= y0 && j < y1) {
-        store_row<XE>(j, o, a.dst);
+        store_row<XE, VEC>(j, o, a.dst);
         if constexpr (ACC) {
           float e[V];
 #pragma unroll
           for (int v = 0; v < V; ++v) e[v] = (K == 1) ? C[0][v] : Pp[K - 1][v];
-          accum_gp<XE>(j, e);
+          accum_gp<XE, VEC>(j, e);
         }
       }
     }

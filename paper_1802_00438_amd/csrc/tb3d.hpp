@@ -268,13 +268,10 @@ struct Tb3dTile {
       const int y = yw + wave * R + r;
       if (y < oy0 || y >= oy1) continue;
       float* rowp = pl + (size_t)y * a.nx;
-      if (!XE && x0 >= ox0 && x0 + V <= ox1) {
-        if constexpr (V == 2) {
-          *reinterpret_cast<float2*>(rowp + x0) = make_float2(o[r][0], o[r][V - 1]);
-        } else {
-#pragma unroll
-          for (int v = 0; v < V; ++v) rowp[x0 + v] = o[r][v];
-        }
+      if constexpr (!XE && V == 2) {
+        // edge-free tiles: window starts and output bounds are all even (nx even), so a lane's
+        // two cells are both inside the output range or both outside it
+        if (x0 >= ox0 && x0 < ox1) *reinterpret_cast<float2*>(rowp + x0) = make_float2(o[r][0], o[r][1]);
       } else {
 #pragma unroll
         for (int v = 0; v < V; ++v)
@@ -283,6 +280,7 @@ struct Tb3dTile {
     }
   }
 
+  template <bool XE>
   __device__ __forceinline__ void accum_gp(int j, const float (&e)[R][V]) const {
     float* pl = a.gp + (size_t)j * a.ny * a.nx;
     const int x0 = xw + lane * V;
@@ -291,9 +289,17 @@ struct Tb3dTile {
       const int y = yw + wave * R + r;
       if (y < oy0 || y >= oy1) continue;
       float* rowp = pl + (size_t)y * a.nx;
+      if constexpr (!XE && V == 2) {
+        if (x0 >= ox0 && x0 < ox1) {
+          float2* q = reinterpret_cast<float2*>(rowp + x0);
+          const float2 g = *q;
+          *q = make_float2(__builtin_fmaf(a.cf.cp, e[r][0], g.x), __builtin_fmaf(a.cf.cp, e[r][1], g.y));
+        }
+      } else {
 #pragma unroll
-      for (int v = 0; v < V; ++v)
-        if (x0 + v >= ox0 && x0 + v < ox1) rowp[x0 + v] = __builtin_fmaf(a.cf.cp, e[r][v], rowp[x0 + v]);
+        for (int v = 0; v < V; ++v)
+          if (x0 + v >= ox0 && x0 + v < ox1) rowp[x0 + v] = __builtin_fmaf(a.cf.cp, e[r][v], rowp[x0 + v]);
+      }
     }
   }
 
@@ -377,7 +383,7 @@ struct Tb3dTile {
           for (int rr = 0; rr < R; ++rr)
 #pragma unroll
             for (int v = 0; v < V; ++v) e[rr][v] = (K == 1) ? C[0][rr][v] : Pp[K - 1][rr][v];
-          accum_gp(j, e);
+          accum_gp<XE>(j, e);
         }
       }
     }
