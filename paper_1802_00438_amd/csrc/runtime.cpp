@@ -250,6 +250,13 @@ int fault_pass() {
   return v && *v ? std::atoi(v) : -1;
 }
 
+// Debug aid for tests: STENCIL_DEBUG_POISON=1 fills the plan's ping-pong scratch with NaN
+// before every run, so a read of scratch cells that no pass has written turns the result NaN.
+hipError_t poison_scratch(const stencil_plan_s* p) {
+  if (!env_flag("STENCIL_DEBUG_POISON")) return hipSuccess;
+  return launch_fill(p->scratch, p->cells, __builtin_nanf(""), p->stream);
+}
+
 KMode fwd_mode(const stencil_plan_s* p) { return p->form == STENCIL_HOTSPOT ? KM_HOT : KM_DIFF; }
 
 // Smallest instantiated K >= k.
@@ -687,6 +694,7 @@ stencil_status_t forward(stencil_plan_s* p, float* grid, const float* power, con
   if (power == grid) return fail(STENCIL_ERR_INVALID_ARG, "power must not alias grid");
   stencil_status_t st = set_device(p);
   if (st != STENCIL_OK) return st;
+  if (hipError_t e = poison_scratch(p); e != hipSuccess) return hip_fail(e, "poison fill");
   const KMode m = fwd_mode(p);
   const DevCoef cf = dev_coef(*coeffs, false);
   const float* pw = (p->form == STENCIL_HOTSPOT) ? power : nullptr;
@@ -913,6 +921,7 @@ stencil_status_t stencil_adjoint(stencil_plan_t p, const float* cot, const float
   }
   st = set_device(p);
   if (st != STENCIL_OK) return st;
+  if (hipError_t e = poison_scratch(p); e != hipSuccess) return hip_fail(e, "poison fill");
   const bool hot = p->form == STENCIL_HOTSPOT;
   float* gp = hot ? grad_power : nullptr;
   const KMode m = gp ? KM_ADJ_ACC : KM_ADJ;

@@ -396,3 +396,106 @@ def test_stencil_run_captured_in_a_graph(shape, cset, hot, tuning, T):
     finally:
         plan.close()
         ref_plan.close()
+
+
+# ------------------------------------------------------------------ invariants and failure paths
+
+INVARIANT_CASES = [
+    ((1500, 2060), "AH2", True, {"variant": 2, "k": 8, "seg_len": 8}),    # split 2D pass
+    ((131, 257), "A2", False, {"variant": 2, "k": 12, "seg_len": 40}),    # one 2D launch
+    ((40, 70, 130), "AH3", True, {"variant": 2, "k": 3}),                 # balanced 3D launch
+    ((33, 50, 129), "A3", False, {"variant": 2, "k": 4, "seg_len": 9}),   # 3D tile launch, odd nx
+]
+
+
+def _inputs(shape, cset, hot, seed):
+    x0 = uniform(shape, 300.0 if hot else 0.0, 350.0 if hot else 1.0, seed)
+    p = uniform(shape, 0.0, 1e-3, seed + 1) if hot else None
+    return SETS[cset], x0, p
+
+
+@pytest.mark.parametrize("shape,cset,hot,tuning", INVARIANT_CASES)
+def test_semigroup_resume_bitwise(shape, cset, hot, tuning):
+    """run(T) equals run(t) followed by run(T - t), bit for bit (pass boundaries move)."""
+    cf, x0, p = _inputs(shape, cset, hot, 95)
+    pw = dev(p) if hot else None
+    plan = S.Plan(HOTSPOT if hot else DIFFUSION, shape, tuning)
+    try:
+        for T, t in ((23, 9), (17, 1), (30, 13)):
+            x = dev(x0)
+            y = dev(x0)
+            plan.run(x, cf, T, pw)
+            plan.run(y, cf, t, pw)
+            plan.run(y, cf, T - t, pw)
+            torch.cuda.synchronize()
+            assert torch.equal(x, y), (T, t)
+    finally:
+        plan.close()
+
+
+def _guarded(a, guard, fill):
+    """A device copy of `a` inside a larger buffer whose guard regions hold `fill`."""
+    n = a.size
+    buf = torch.full((n + 2 * guard,), fill, dtype=torch.float32, device="cuda")
+    view = buf[guard:guard + n].view(a.shape)
+    view.copy_(dev(a))
+    return buf, view
+
+
+@pytest.mark.parametrize("shape,cset,hot,tuning", INVARIANT_CASES)
+def test_poisoned_scratch_and_guard_canaries(shape, cset, hot, tuning, monkeypatch):
+    """With STENCIL_DEBUG_POISON=1 the plan's scratch is NaN before every run, so any read of
+    scratch that no pass wrote would poison the result; guard regions around the caller's
+    buffers must come back untouched (no stores outside the grid)."""
+    monkeypatch.setenv("STENCIL_DEBUG_POISON", "1")
+    cf, x0, p = _inputs(shape, cset, hot, 96)
+    guard, canary = 4096, 12345.0
+    plan = S.Plan(HOTSPOT if hot else DIFFUSION, shape, tuning)
+    try:
+        for T in (1, 10, 21):
+            xb, x = _guarded(x0, guard, canary)
+            pb, pw = _guarded(p, guard, canary) if hot else (None, None)
+            plan.run(x, cf, T, pw)
+            torch.cuda.synchronize()
+            ref = oracle.forward(x0, cf, T, power=p, dtype=np.float32)
+            assert np.array_equal(x.cpu().numpy(), ref), T
+            for b in (xb, pb):
+                if b is not None:
+                    assert bool(torch.all(b[:guard] == canary)) and bool(torch.all(b[-guard:] == canary)), T
+        # the adjoint through guarded outputs
+        gb, g = _guarded(uniform(shape, -1.0, 1.0, 97), guard, canary)
+        gxb, gx = _guarded(np.zeros(shape, np.float32), guard, canary)
+        gpb, gp = _guarded(np.zeros(shape, np.float32), guard, canary) if hot else (None, None)
+        plan.adjoint(g, cf, 11, gx, gp)
+        torch.cuda.synchronize()
+        rx, rp = oracle.adjoint(g.cpu().numpy(), cf, 11, form=HOTSPOT if hot else DIFFUSION)
+        assert normrel(gx.cpu().numpy(), rx) <= TOL
+        if hot:
+            assert normrel(gp.cpu().numpy(), rp) <= TOL
+        for b in (gb, gxb, gpb):
+            if b is not None:
+                assert bool(torch.all(b[:guard] == canary)) and bool(torch.all(b[-guard:] == canary))
+    finally:
+        plan.close()
+
+
+def test_injected_fault_is_reported_and_plan_recovers(monkeypatch):
+    """A HIP error forced at the second pass (STENCIL_FAULT_INJECT) is returned as
+    STENCIL_ERR_HIP through the binding; the same plan then runs correctly."""
+    shape, cset = (300, 520), "AH2"
+    cf, x0, p = _inputs(shape, cset, True, 98)
+    pw = dev(p)
+    plan = S.Plan(HOTSPOT, shape, {"variant": 2, "k": 4, "seg_len": 32})
+    try:
+        x = dev(x0)
+        monkeypatch.setenv("STENCIL_FAULT_INJECT", "1")
+        with pytest.raises(S.StencilError):
+            plan.run(x, cf, 12, pw)
+        monkeypatch.delenv("STENCIL_FAULT_INJECT")
+        torch.cuda.synchronize()
+        x = dev(x0)
+        plan.run(x, cf, 12, pw)
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), oracle.forward(x0, cf, 12, power=p, dtype=np.float32))
+    finally:
+        plan.close()
