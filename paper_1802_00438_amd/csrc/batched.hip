@@ -34,6 +34,7 @@ struct BGrid {
   int nx, ny, nz;
   int cs, kr, ntx, seg, nseg;           // 2D geometry
   int csx, csy, krx, kry, nty, segz, nsegz;  // 3D geometry (ntx shared)
+  int ax, ay, fx, fy;                         // 3D edge-flush tiling per axis
   int flag_off;
   int aligned;
   DevCoef cf;
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(64 * kBatchNW3) void batched3d_kernel(const BGrid* 
     a.csx = g.csx; a.csy = g.csy; a.krx = g.krx; a.kry = g.kry; a.ntx = g.ntx; a.nty = g.nty;
     a.segz = g.segz; a.nsegz = g.nsegz;
     a.nwork = 0;
-    a.ax = a.ay = a.fx = a.fy = 0;
+    a.ax = g.ax; a.ay = g.ay; a.fx = g.fx; a.fy = g.fy;
     a.aligned = g.aligned;
     a.cf = g.cf;
     {
@@ -213,11 +214,50 @@ std::vector<int> even_split(int T, int kcap) {
 }
 
 // The persistent 3D kernel keeps the uniform tiling (its tile decoding has no edge-flush case).
+// Whether, along one axis, every tile's window reads only cells that its own tile and its two
+// neighbours output: an item waits only for those neighbours of the previous pass.  Tile
+// ranges follow the kernel's edge-flush tiling (flush = 1) or uniform tiling (flush = 0).
+bool windows_within_neighbours(int n, int W, int nt, int f, int cs, int kr, bool flush) {
+  auto range = [&](int t, int* o0, int* o1, int* w0) {
+    if (!flush) {
+      *o0 = t * cs; *o1 = std::min(*o0 + cs, n); *w0 = *o0 - kr;
+    } else if (nt == 1) {
+      *o0 = 0; *o1 = n; *w0 = 0;
+    } else if (t == 0) {
+      *o0 = 0; *o1 = f; *w0 = 0;
+    } else if (t == nt - 1) {
+      *o0 = std::max(f, n - f); *o1 = n; *w0 = n - W;
+    } else {
+      *o0 = f + (t - 1) * cs; *o1 = std::min(*o0 + cs, n - f); *w0 = *o0 - kr;
+    }
+  };
+  for (int t = 0; t < nt; ++t) {
+    int o0, o1, w0, lo0, lo1, lw, hi0, hi1, hw;
+    range(t, &o0, &o1, &w0);
+    range(std::max(t - 1, 0), &lo0, &lo1, &lw);
+    range(std::min(t + 1, nt - 1), &hi0, &hi1, &hw);
+    const int r0 = std::max(w0, 0), r1 = std::min(w0 + W, n);
+    if (r0 < lo0 || r1 > hi1) return false;
+  }
+  return true;
+}
+
+// Geometry of a batched 3D grid: the kernel's edge-flush tiling where every window stays
+// within its neighbours' outputs (the dependency rule of the work list), else uniform tiling
+// on that axis.
 Geom3D batch_geom3d(const BGrid& g, int segz) {
   Geom3D gg = geom3d(kBatchK3, false, g.nx, g.ny, g.nz, segz);
-  gg.ax = gg.ay = gg.fx = gg.fy = 0;
-  gg.ntx = (g.nx + gg.csx - 1) / gg.csx;
-  gg.nty = (g.ny + gg.csy - 1) / gg.csy;
+  const int WX = 64 * kTb3dV, WY = kTb3dWY;
+  if (gg.ax && !windows_within_neighbours(g.nx, WX, gg.ntx, gg.fx, gg.csx, gg.krx, true)) {
+    gg.ax = 0;
+    gg.fx = 0;
+    gg.ntx = (g.nx + gg.csx - 1) / gg.csx;
+  }
+  if (gg.ay && !windows_within_neighbours(g.ny, WY, gg.nty, gg.fy, gg.csy, gg.kry, true)) {
+    gg.ay = 0;
+    gg.fy = 0;
+    gg.nty = (g.ny + gg.csy - 1) / gg.csy;
+  }
   return gg;
 }
 
@@ -329,6 +369,7 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
       const Geom3D gg = batch_geom3d(g, seg3[i]);
       g.csx = gg.csx; g.csy = gg.csy; g.krx = gg.krx; g.kry = gg.kry; g.ntx = gg.ntx; g.nty = gg.nty;
       g.segz = gg.segz; g.nsegz = gg.nsegz;
+      g.ax = gg.ax; g.ay = gg.ay; g.fx = gg.fx; g.fy = gg.fy;
       g.aligned = ((g.nx & 1) == 0) && ((reinterpret_cast<uintptr_t>(g.buf[0]) | reinterpret_cast<uintptr_t>(g.buf[1])) & 7) == 0;
       ntiles[i] = gg.ntx * gg.nty * gg.nsegz;
       t_item[i] = item_work3d(gg);

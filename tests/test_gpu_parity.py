@@ -352,6 +352,30 @@ def test_batched_bitwise_equals_oracle_and_replays():
     S.stencil_batch_destroy(cache)
 
 
+def test_batched_edge_flush_3d_grids():
+    """3D grids of the batch at least one window wide and high take the edge-flush tiling in
+    the persistent kernel (when every window stays within its neighbours' outputs): results
+    must equal the oracle bit for bit, on the first launch and on graph replays."""
+    shapes = [(12, 100, 256), (9, 150, 144), (7, 49, 130), (5, 90, 250)]
+    xs = [uniform(sh, 0.0, 1.0, 8100 + i) for i, sh in enumerate(shapes)]
+    cfs = [SETS["A3"]] * len(shapes)
+    ts = [9, 13, 6, 17]
+    dts = [dev(x) for x in xs]
+    cache = S.run_batched(dts, cfs, ts)
+    torch.cuda.synchronize()
+    for x, c, T, d in zip(xs, cfs, ts, dts):
+        assert np.array_equal(d.cpu().numpy(), oracle.forward(x, c, T, dtype=np.float32)), x.shape
+    for rep in range(2):
+        for d, x in zip(dts, xs):
+            d.copy_(dev(x))
+        torch.cuda.synchronize()
+        S.run_batched(dts, cfs, ts, cache=cache)
+        torch.cuda.synchronize()
+        for x, c, T, d in zip(xs, cfs, ts, dts):
+            assert np.array_equal(d.cpu().numpy(), oracle.forward(x, c, T, dtype=np.float32)), (rep, x.shape)
+    S.stencil_batch_destroy(cache)
+
+
 def test_t0_is_identity_and_nan_free_small_grids():
     for shape in [(1, 1), (2, 2), (1, 1, 1), (2, 3, 1)]:
         x0 = uniform(shape, 0.0, 1.0, 9)
