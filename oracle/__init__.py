@@ -31,6 +31,7 @@ _lib = None
 
 DIFFUSION = 0
 HOTSPOT = 1
+HOTSPOT_PHYS = 2   # Table 2's Hotspot 2D as printed (2D only)
 
 
 def build(force: bool = False) -> str:
@@ -89,7 +90,9 @@ def forward(x0, coeffs, T, power=None, form=None, dtype=np.float64):
 
     ``x0`` has shape (ny, nx) or (nz, ny, nx); ``coeffs`` is the 10-vector
     [cc, cw, ce, cn, cs, cb, ca, cp, c_amb, t_amb] (FP32 values; the FP64 run promotes
-    them exactly).  Returns a new array of ``dtype`` (float64 or float32).
+    them exactly).  For ``form=HOTSPOT_PHYS`` (2D) the vector carries sdc in cp, Rx_1 in
+    ce, Ry_1 in cs, Rz_1 in c_amb and TEMP_AMB in t_amb.  Returns a new array of
+    ``dtype`` (float64 or float32).
     """
     lib = _load()
     dtype = np.dtype(dtype)
@@ -101,7 +104,7 @@ def forward(x0, coeffs, T, power=None, form=None, dtype=np.float64):
     ndim, nx, ny, nz = _dims(g.shape)
     cf = np.ascontiguousarray(coeffs, dtype=np.float32)
     p = None
-    if form == HOTSPOT:
+    if form in (HOTSPOT, HOTSPOT_PHYS):
         if power is None:
             raise ValueError("hotspot needs a power map")
         p = _prep(power, dtype)
@@ -128,7 +131,7 @@ def adjoint(cot, coeffs, T, form=DIFFUSION, dtype=np.float64, want_grad_p=None):
     cf = np.ascontiguousarray(coeffs, dtype=np.float32)
     gx = np.empty_like(c)
     if want_grad_p is None:
-        want_grad_p = form == HOTSPOT
+        want_grad_p = form != DIFFUSION
     gp = np.empty_like(c) if want_grad_p else None
     rc = fn(form, ndim, nx, ny, nz, _ptr(cf, ctypes.c_float), _ptr(c, ct), int(T), _ptr(gx, ct),
             _ptr(gp, ct) if gp is not None else None)

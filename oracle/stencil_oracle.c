@@ -17,6 +17,11 @@
  *     neighbour weights, plus cp*power + c_amb*t_amb); the physical Table-2 form of
  *     Hotspot 2D maps onto it with cc = 1 - sdc*(2Rx+2Ry+Rz), cw = ce = sdc*Rx,
  *     cn = cs = sdc*Ry, cp = sdc, c_amb = sdc*Rz.
+ *   * Table 2, Hotspot 2D as printed (form ORACLE_HOTSPOT_PHYS, 2D only): the new value is
+ *     the centre plus sdc times the sum of the power, the y-difference (n + s - 2c) times
+ *     Ry_1, the x-difference (e + w - 2c) times Rx_1 and the ambient difference
+ *     (TEMP_AMB - c) times Rz_1.  The coefficient vector carries sdc in cp, Rx_1 in ce,
+ *     Ry_1 in cs, Rz_1 in c_amb and TEMP_AMB in t_amb; the other weights are unused.
  *   * Section 5.1: an out-of-range neighbour of a boundary cell takes the value of the
  *     boundary cell itself (clamp-to-edge), in every direction and at every step.
  *
@@ -26,6 +31,10 @@
  *              (k_amb = c_amb*t_amb rounded once in the working precision) starts the sum;
  *   then acc = fma(cw,w,acc); acc = fma(ce,e,acc); acc = fma(cs,s,acc); acc = fma(cn,n,acc);
  *   [3D: acc = fma(cb,b,acc); acc = fma(ca,a,acc)].
+ *   physical Hotspot 2D, term by term in the order the formula is written:
+ *              dy = (n + s) - 2c;  dx = (e + w) - 2c;  dz = TEMP_AMB - c   (each rounded);
+ *              acc = fma(dy, Ry_1, p); acc = fma(dx, Rx_1, acc); acc = fma(dz, Rz_1, acc);
+ *              out = fma(sdc, acc, c).
  * Two instantiations are built from the same text: FP64 (coefficients promoted from their
  * FP32 values) and FP32.  Compile with -ffp-contract=off so no other fusion happens.
  *
@@ -33,6 +42,9 @@
  * c_d * lambda[i] onto the cell its direction-d neighbour clamps to.  With
  * x_{t+1} = A x_t + cp*p + k_amb, lambda_T = dJ/dx_T:
  *   grad_x0 = (A^T)^T lambda_T,  grad_p = cp * sum_{t=1..T} lambda_t.
+ * For the physical Hotspot 2D form every occurrence of a cell in the printed formula
+ * scatters its own partial derivative (1 for the leading centre, sdc*Ry_1 for n and s,
+ * -2*sdc*Ry_1 for the centre inside the y-difference, and so on), and grad_p uses sdc.
  *
  * Parallelism: the forward sweep parallelises over rows with OpenMP; every output cell has
  * exactly one writer, so results do not depend on the thread count.  The adjoint scatter
@@ -45,7 +57,7 @@
 #include <omp.h>
 #endif
 
-enum { ORACLE_DIFFUSION = 0, ORACLE_HOTSPOT = 1 };
+enum { ORACLE_DIFFUSION = 0, ORACLE_HOTSPOT = 1, ORACLE_HOTSPOT_PHYS = 2 };
 enum { C_CC = 0, C_CW, C_CE, C_CN, C_CS, C_CB, C_CA, C_CP, C_AMB, C_TAMB };
 
 static inline long clampl(long v, long lo, long hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -66,12 +78,16 @@ int oracle_num_threads(void) {
                            REAL* grid, const REAL* power, int T) {                            \
     if (nx < 1 || ny < 1 || nz < 1 || T < 0 || (ndim != 2 && ndim != 3)) return -1;           \
     if (ndim == 2) nz = 1;                                                                    \
-    if (form == ORACLE_HOTSPOT && !power) return -1;                                          \
+    if ((form == ORACLE_HOTSPOT || form == ORACLE_HOTSPOT_PHYS) && !power) return -1;         \
+    if (form == ORACLE_HOTSPOT_PHYS && ndim != 2) return -1;                                  \
+    if (form < ORACLE_DIFFUSION || form > ORACLE_HOTSPOT_PHYS) return -1;                     \
     const long n = (long)nx * ny * nz;                                                        \
     const REAL cc = (REAL)cf[C_CC], cw = (REAL)cf[C_CW], ce = (REAL)cf[C_CE];                 \
     const REAL cn = (REAL)cf[C_CN], cs = (REAL)cf[C_CS], cb = (REAL)cf[C_CB];                 \
     const REAL ca = (REAL)cf[C_CA], cp = (REAL)cf[C_CP];                                      \
     const REAL kamb = (REAL)cf[C_AMB] * (REAL)cf[C_TAMB];                                     \
+    /* physical Hotspot 2D: sdc, Rx_1, Ry_1, Rz_1, TEMP_AMB */                                \
+    const REAL sdc = cp, rx = ce, ry = cs, rz = (REAL)cf[C_AMB], tamb = (REAL)cf[C_TAMB];     \
     REAL* buf = (REAL*)malloc(sizeof(REAL) * (size_t)n);                                      \
     REAL* q = NULL;                                                                           \
     if (!buf) return -1;                                                                      \
@@ -95,6 +111,21 @@ int oracle_num_threads(void) {
           const REAL* ra = v + (zp * ny + y) * nx;                                            \
           REAL* out = o + (z * ny + y) * nx;                                                  \
           const REAL* qr = q ? q + (z * ny + y) * nx : NULL;                                  \
+          if (form == ORACLE_HOTSPOT_PHYS) {                                                  \
+            const REAL* pr = power + y * nx;                                                  \
+            for (long x = 0; x < nx; ++x) {                                                   \
+              const long xm = clampl(x - 1, 0, nx - 1), xp = clampl(x + 1, 0, nx - 1);        \
+              const REAL c = row[x];                                                          \
+              const REAL dy = (rn[x] + rs[x]) - (REAL)2 * c;                                  \
+              const REAL dx = (row[xp] + row[xm]) - (REAL)2 * c;                              \
+              const REAL dz = tamb - c;                                                       \
+              REAL acc = FMA(dy, ry, pr[x]);                                                  \
+              acc = FMA(dx, rx, acc);                                                         \
+              acc = FMA(dz, rz, acc);                                                         \
+              out[x] = FMA(sdc, acc, c);                                                      \
+            }                                                                                 \
+            continue;                                                                         \
+          }                                                                                   \
           for (long x = 0; x < nx; ++x) {                                                     \
             const long xm = clampl(x - 1, 0, nx - 1), xp = clampl(x + 1, 0, nx - 1);          \
             REAL acc = qr ? FMA(cc, row[x], qr[x]) : cc * row[x];                             \
@@ -125,23 +156,39 @@ int oracle_num_threads(void) {
                            const REAL* cot, int T, REAL* grad_x0, REAL* grad_p) {             \
     if (nx < 1 || ny < 1 || nz < 1 || T < 0 || (ndim != 2 && ndim != 3)) return -1;           \
     if (ndim == 2) nz = 1;                                                                    \
+    if (form < ORACLE_DIFFUSION || form > ORACLE_HOTSPOT_PHYS) return -1;                     \
+    if (form == ORACLE_HOTSPOT_PHYS && ndim != 2) return -1;                                  \
     const long n = (long)nx * ny * nz;                                                        \
     const REAL cc = (REAL)cf[C_CC], cw = (REAL)cf[C_CW], ce = (REAL)cf[C_CE];                 \
     const REAL cn = (REAL)cf[C_CN], cs = (REAL)cf[C_CS], cb = (REAL)cf[C_CB];                 \
     const REAL ca = (REAL)cf[C_CA], cp = (REAL)cf[C_CP];                                      \
+    const REAL sdc = cp, rx = ce, ry = cs, rz = (REAL)cf[C_AMB];                              \
     REAL* lam = grad_x0;                                                                      \
     REAL* nl = (REAL*)malloc(sizeof(REAL) * (size_t)n);                                       \
     if (!nl) return -1;                                                                       \
     memcpy(lam, cot, sizeof(REAL) * (size_t)n);                                               \
     if (grad_p) memset(grad_p, 0, sizeof(REAL) * (size_t)n);                                  \
     for (int t = T; t >= 1; --t) {                                                            \
-      if (grad_p && form == ORACLE_HOTSPOT)                                                   \
+      if (grad_p && form != ORACLE_DIFFUSION)                                                 \
         for (long i = 0; i < n; ++i) grad_p[i] = grad_p[i] + cp * lam[i];                     \
       memset(nl, 0, sizeof(REAL) * (size_t)n);                                                \
       for (long z = 0; z < nz; ++z)                                                           \
         for (long y = 0; y < ny; ++y)                                                         \
           for (long x = 0; x < nx; ++x) {                                                     \
             const REAL l = lam[(z * ny + y) * nx + x];                                        \
+            if (form == ORACLE_HOTSPOT_PHYS) {                                                \
+              const long i = y * nx + x;                                                      \
+              const REAL g = sdc * l;                                                         \
+              nl[i] += l;                                                                     \
+              nl[clampl(y - 1, 0, ny - 1) * nx + x] += ry * g;                                \
+              nl[clampl(y + 1, 0, ny - 1) * nx + x] += ry * g;                                \
+              nl[i] += -2 * ry * g;                                                           \
+              nl[y * nx + clampl(x + 1, 0, nx - 1)] += rx * g;                                \
+              nl[y * nx + clampl(x - 1, 0, nx - 1)] += rx * g;                                \
+              nl[i] += -2 * rx * g;                                                           \
+              nl[i] += -rz * g;                                                               \
+              continue;                                                                       \
+            }                                                                                 \
             nl[(z * ny + y) * nx + x] += cc * l;                                              \
             nl[(z * ny + y) * nx + clampl(x - 1, 0, nx - 1)] += cw * l;                       \
             nl[(z * ny + y) * nx + clampl(x + 1, 0, nx - 1)] += ce * l;                       \

@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import SETS, DIFFUSION, HOTSPOT, uniform
+from workloads import SETS, DIFFUSION, HOTSPOT, HOTSPOT_PHYS, phys_coeffs, uniform
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -391,3 +391,134 @@ def test_fp32_vs_fp64_error_budget():
     a = oracle.forward(x0, cf, 1000, power=p)
     b = oracle.forward(x0, cf, 1000, power=p, dtype=np.float32)
     assert relerr(b, a) < 1e-5
+
+
+# ---------------------------------------------------------------- physical Hotspot 2D (Table 2 as printed)
+
+def _phys_as_weights(cf):
+    """The weights the physical formula expands to, in FP64 from the FP32 parameters:
+    cc = 1 - sdc(2Rx_1 + 2Ry_1 + Rz_1), cw = ce = sdc Rx_1, cn = cs = sdc Ry_1, cp = sdc,
+    c_amb = sdc Rz_1."""
+    sdc, rx, ry, rz, ta = (float(cf[i]) for i in (7, 2, 4, 8, 9))
+    return np.array([1.0 - sdc * (2 * rx + 2 * ry + rz), sdc * rx, sdc * rx, sdc * ry, sdc * ry, 0.0, 0.0,
+                     sdc, sdc * rz, ta], dtype=np.float64)
+
+
+def test_phys_hand_worked_step_matches_golden():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "hand_step_HP_3x2.txt")) if l.strip() and l[0] != "#"]
+    expected = np.array(rows, dtype=np.float64)
+    x0 = np.array([[1, 2, 4], [8, 16, 32]], dtype=np.float32)
+    p = np.array([[0, 1, 0], [2, 0, 4]], dtype=np.float32)
+    cf = phys_coeffs(0.5, 0.25, 0.125, 0.0625, 16.0)
+    for dt in (np.float64, np.float32):
+        out = oracle.forward(x0, cf, 1, power=p, form=HOTSPOT_PHYS, dtype=dt)
+        assert np.array_equal(out.astype(np.float64), expected), dt
+
+
+@pytest.mark.parametrize("shape", SMALL_2D)
+@pytest.mark.parametrize("cset", ["HP2", "HPr"])
+def test_phys_equals_dense_affine_power(shape, cset):
+    """The physical formula is the affine map of its expanded weights: brute-force matrix power."""
+    cf = SETS[cset]
+    x0 = uniform(shape, 300.0, 350.0, 121)
+    p = uniform(shape, 0.0, 1.0, 122)
+    w = _phys_as_weights(cf)
+    for T in TS:
+        ref = dense_forward(x0, w, T, p)
+        out = oracle.forward(x0, cf, T, power=p, form=HOTSPOT_PHYS)
+        assert relerr(out, ref) < 1e-13, (shape, cset, T)
+        out32 = oracle.forward(x0, cf, T, power=p, form=HOTSPOT_PHYS, dtype=np.float32)
+        assert relerr(out32, ref) < 2e-6, (shape, cset, T)
+
+
+def test_phys_hp2_is_the_weighted_h2_set():
+    """HP2 expands exactly to H2, so the two forms agree to FP64 rounding on the same inputs."""
+    assert np.array_equal(_phys_as_weights(SETS["HP2"]), SETS["H2"].astype(np.float64))
+    x0 = uniform((37, 29), 300.0, 350.0, 123)
+    p = uniform((37, 29), 0.0, 1e-3, 124)
+    a = oracle.forward(x0, SETS["HP2"], 50, power=p, form=HOTSPOT_PHYS)
+    b = oracle.forward(x0, SETS["H2"], 50, power=p, form=HOTSPOT)
+    assert relerr(a, b) < 1e-13
+
+
+@pytest.mark.parametrize("cset", ["HP2", "HPr"])
+def test_phys_ambient_is_an_exact_fixed_point(cset):
+    """With zero power a field at TEMP_AMB makes every difference of the formula exactly zero,
+    so it stays bit-exact in FP32 too, also with weights that are not dyadic."""
+    x0 = np.full((11, 13), 80.0, dtype=np.float32)
+    for dt in (np.float64, np.float32):
+        out = oracle.forward(x0, SETS[cset], 60, power=np.zeros_like(x0), form=HOTSPOT_PHYS, dtype=dt)
+        assert np.all(out == 80.0), dt
+
+
+@pytest.mark.parametrize("cset", ["HP2", "HPr"])
+def test_phys_uniform_closed_form(cset):
+    """Uniform X and P: the differences vanish and x_{t+1} = x_t + sdc(P + Rz_1(TEMP_AMB - x_t)),
+    so x_t = x* + (X - x*)(1 - sdc Rz_1)^t with x* = TEMP_AMB + P / Rz_1."""
+    cf = SETS[cset]
+    sdc, rz, ta = float(cf[7]), float(cf[8]), float(cf[9])
+    X, P = 300.0, float(np.float32(1e-3))
+    xs = ta + P / rz
+    for T in (1, 5, 50, 400):
+        out = oracle.forward(np.full((5, 7), X), cf, T, power=np.full((5, 7), np.float32(P)), form=HOTSPOT_PHYS)
+        ref = xs + (X - xs) * (1.0 - sdc * rz) ** T
+        assert np.max(np.abs(out - ref)) / abs(ref) < 1e-12, T
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (5, 3), (1, 6), (7, 1)])
+def test_phys_adjoint_equals_dense_transpose(shape):
+    cf = SETS["HPr"]
+    A = dense_operator(shape, _phys_as_weights(cf))
+    g = uniform(shape, -1.0, 1.0, 125).astype(np.float64).ravel()
+    for T in (0, 1, 2, 5, 13):
+        gx, gp = oracle.adjoint(g.reshape(shape), cf, T, form=HOTSPOT_PHYS)
+        assert relerr(gx.ravel(), np.linalg.matrix_power(A.T, T) @ g) < 1e-13, T
+        acc = np.zeros_like(g)
+        lam = g.copy()
+        for _ in range(T):
+            acc += lam
+            lam = A.T @ lam
+        if T == 0:
+            assert np.all(gp == 0)
+        else:
+            assert relerr(gp.ravel(), float(cf[7]) * acc) < 1e-13, T
+
+
+def test_phys_central_differences():
+    """Central differences of the quadratic loss through the physical forward match the
+    physical adjoint (no truncation error)."""
+    cf = SETS["HPr"]
+    shape, T = (9, 11), 6
+    x0 = uniform(shape, 300.0, 350.0, 126).astype(np.float64)
+    p = uniform(shape, 0.0, 1e-3, 127).astype(np.float64)
+    y = uniform(shape, 300.0, 350.0, 128).astype(np.float64)
+    xT = oracle.forward(x0, cf, T, power=p, form=HOTSPOT_PHYS)
+    gx, gp = oracle.adjoint(xT - y, cf, T, form=HOTSPOT_PHYS)
+    rng = np.random.default_rng(1)
+    h = 0.5
+    for _ in range(6):
+        idx = tuple(int(rng.integers(0, n)) for n in shape)
+        for which, grad in (("x", gx), ("p", gp)):
+            xp, xm, pp, pm = x0.copy(), x0.copy(), p.copy(), p.copy()
+            if which == "x":
+                xp[idx] += h
+                xm[idx] -= h
+            else:
+                pp[idx] += h
+                pm[idx] -= h
+            jp = oracle.loss(oracle.forward(xp, cf, T, power=pp, form=HOTSPOT_PHYS), y)
+            jm = oracle.loss(oracle.forward(xm, cf, T, power=pm, form=HOTSPOT_PHYS), y)
+            assert abs((jp - jm) / (2 * h) - grad[idx]) <= 1e-7 * max(1.0, abs(grad[idx])), (which, idx)
+
+
+def test_phys_fp32_error_budget_and_rejections():
+    cf = SETS["HP2"]
+    x0 = uniform((64, 64), 300.0, 350.0, 129)
+    p = uniform((64, 64), 0.0, 1e-3, 130)
+    a = oracle.forward(x0, cf, 1000, power=p, form=HOTSPOT_PHYS)
+    b = oracle.forward(x0, cf, 1000, power=p, form=HOTSPOT_PHYS, dtype=np.float32)
+    assert relerr(b, a) < 1e-5
+    with pytest.raises(ValueError):
+        oracle.forward(np.zeros((2, 3, 3)), cf, 1, power=np.zeros((2, 3, 3)), form=HOTSPOT_PHYS)
+    with pytest.raises(ValueError):
+        oracle.forward(np.zeros((3, 3)), cf, 1, form=HOTSPOT_PHYS)

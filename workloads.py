@@ -26,6 +26,7 @@ import numpy as np
 
 DIFFUSION = 0
 HOTSPOT = 1
+HOTSPOT_PHYS = 2   # Table 2's Hotspot 2D as printed (sdc, Rx_1, Ry_1, Rz_1, TEMP_AMB)
 
 # Coefficient vector layout used everywhere (oracle and library binding):
 #   [cc, cw, ce, cn, cs, cb, ca, cp, c_amb, t_amb]
@@ -36,6 +37,12 @@ COEF_NAMES = ("cc", "cw", "ce", "cn", "cs", "cb", "ca", "cp", "c_amb", "t_amb")
 def coeffs(cc, cw, ce, cn, cs, cb=0.0, ca=0.0, cp=0.0, c_amb=0.0, t_amb=0.0):
     """Pack a coefficient set as a float32 vector in the canonical layout."""
     return np.array([cc, cw, ce, cn, cs, cb, ca, cp, c_amb, t_amb], dtype=np.float32)
+
+
+def phys_coeffs(sdc, rx, ry, rz, t_amb):
+    """Pack the parameters of the physical Hotspot 2D form (Table 2) in the canonical layout:
+    sdc in cp, Rx_1 in ce, Ry_1 in cs, Rz_1 in c_amb, TEMP_AMB in t_amb."""
+    return np.array([0.0, 0.0, rx, 0.0, ry, 0.0, 0.0, sdc, rz, t_amb], dtype=np.float32)
 
 
 # Coefficient sets.  D2/D3 are the diffusion weights of the workloads; the hotspot sets
@@ -54,6 +61,10 @@ SETS = {
     # asymmetric hotspot sets (for adjoint / orientation tests of the affine form)
     "AH2": coeffs(0.375, 0.0625, 0.1875, 0.125, 0.25, cp=8.0, c_amb=2.0 ** -8, t_amb=80.0),
     "AH3": coeffs(0.25, 0.0625, 0.1875, 0.125, 0.1875, 0.0625, 0.125, cp=8.0, c_amb=2.0 ** -8, t_amb=80.0),
+    # physical Hotspot 2D parameters (Table 2 as printed).  HP2 is the physical reading of
+    # H2: sdc*Rx_1 = sdc*Ry_1 = 1/8, sdc*Rz_1 = 2^-10, sdc = 64.  HPr is non-dyadic.
+    "HP2": phys_coeffs(64.0, 2.0 ** -9, 2.0 ** -9, 2.0 ** -16, 80.0),
+    "HPr": phys_coeffs(0.3, 0.8, 0.6, 0.05, 80.0),
 }
 
 
@@ -109,7 +120,7 @@ class Workload:
         return uniform(self.shape, self.field_lo, self.field_hi, self.seed)
 
     def power(self):
-        if self.form != HOTSPOT:
+        if self.form == DIFFUSION:
             return None
         return uniform(self.shape, 0.0, self.power_hi, self.seed + 1)
 
