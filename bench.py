@@ -294,6 +294,23 @@ def main():
     torch.cuda.empty_cache()
 
     if not args.quick:
+        # the same problem in Table 2's physical Hotspot 2D form (its own workload inputs)
+        w6 = WORKLOADS["hotspot2d_phys_16384"]
+        x6 = torch.from_numpy(w6.field()).to(dev)
+        p6 = torch.from_numpy(w6.power()).to(dev)
+        pl6 = S.Plan(S.HOTSPOT_PHYS, w6.shape)
+        pl6.run(x6, w6.coeffs, 24, p6)
+        ms6 = time_call(lambda: pl6.run(x6, w6.coeffs, w6.T, p6), stream, 2)
+        g6 = w6.cells * w6.T / (ms6 * 1e-3) / 1e9
+        extras["hotspot2d_phys_16384"] = {"gcells": round(g6, 1), "ms_per_run": round(ms6, 2),
+                                          "k": pl6.tuning["k"], "seg_len": pl6.tuning["seg_len"],
+                                          "pct_single_pass_roofline": round(100 * g6 / (HBM_PEAK_GBS / 12), 1)}
+        pl6.close()
+        del x6, p6
+        torch.cuda.empty_cache()
+        log("[bench] physical hotspot 2D: %.1f GCell/s" % g6)
+
+    if not args.quick:
         # 3D diffusion 512^3, 200 steps: temporal-blocked vs plain
         w3 = WORKLOADS["diffusion3d_512"]
         x3 = torch.from_numpy(w3.field()).to(dev)

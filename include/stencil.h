@@ -44,12 +44,20 @@ typedef enum {
   STENCIL_ERR_INTERNAL = -5       /* invariant violated inside the library */
 } stencil_status_t;
 
-typedef enum { STENCIL_DIFFUSION = 0, STENCIL_HOTSPOT = 1 } stencil_form_t;
+/* HOTSPOT is the weighted-sum form above.  HOTSPOT_PHYS (2D only) is Table 2's Hotspot 2D
+ * formula as printed,
+ *     out = c + sdc*(p + ((n + s) - 2c)*Ry_1 + ((e + w) - 2c)*Rx_1 + (TEMP_AMB - c)*Rz_1),
+ * every operation rounded in FP32 in that order, each "x + y*z" as one FMA and the final
+ * c + sdc*(...) as fma(sdc, ..., c).  A field at TEMP_AMB with zero power is then an exact
+ * fixed point.  It has no adjoint and no batched launch (both return UNSUPPORTED). */
+typedef enum { STENCIL_DIFFUSION = 0, STENCIL_HOTSPOT = 1, STENCIL_HOTSPOT_PHYS = 2 } stencil_form_t;
 
 /* Stencil weights (Table 2).  cb, ca are ignored for 2D; cp, c_amb, t_amb for diffusion.
  * All must be finite.  The paper's Hotspot 2D form maps onto these with
  * cc = 1 - sdc*(2Rx_1 + 2Ry_1 + Rz_1), cw = ce = sdc*Rx_1, cn = cs = sdc*Ry_1, cp = sdc,
- * c_amb = sdc*Rz_1; its Hotspot 3D form sets c_amb = ca. */
+ * c_amb = sdc*Rz_1; its Hotspot 3D form sets c_amb = ca.
+ * HOTSPOT_PHYS reads its parameters from the same struct: sdc from cp, Rx_1 from ce, Ry_1
+ * from cs, Rz_1 from c_amb and TEMP_AMB from t_amb; the other fields are ignored. */
 typedef struct {
   float cc, cw, ce, cn, cs, cb, ca;
   float cp;    /* hotspot: weight of the power map (sdc in Table 2) */
@@ -79,7 +87,7 @@ stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int nd
                                 int nz, const stencil_tuning_t* tuning, void* hip_stream);
 
 /* Run exactly T >= 0 time steps in place on grid (device, nx*ny*nz FP32).  power (device,
- * same shape) is required for HOTSPOT and ignored for DIFFUSION.  T == 0 leaves grid
+ * same shape) is required for both hotspot forms and ignored for DIFFUSION.  T == 0 leaves grid
  * unchanged.  Enqueues ceil(T/k) temporal-blocked passes (the last one shorter when k does
  * not divide T, Section 3.2) alternating between grid and plan scratch so that the result
  * lands in grid.  Asynchronous. */
@@ -109,7 +117,7 @@ stencil_status_t stencil_adjoint(stencil_plan_t plan, const float* cotangent, co
 
 /* One grid of a batch. */
 typedef struct {
-  stencil_form_t form; /* DIFFUSION only (HOTSPOT returns UNSUPPORTED) */
+  stencil_form_t form; /* DIFFUSION only (the hotspot forms return UNSUPPORTED) */
   int ndim, nx, ny, nz;
   float* grid;         /* device, in/out */
   const float* power;  /* unused for diffusion */

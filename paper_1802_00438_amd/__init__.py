@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libstencil_mi355.so")
 
 DIFFUSION = 0
 HOTSPOT = 1
+HOTSPOT_PHYS = 2   # Table 2's Hotspot 2D formula as printed (2D, forward only)
 
 STENCIL_OK = 0
 STATUS = {0: "STENCIL_OK", -1: "STENCIL_ERR_INVALID_ARG", -2: "STENCIL_ERR_UNSUPPORTED",
@@ -269,10 +270,12 @@ class Plan:
             pass
 
 
-def run(x, coeffs, T, power=None, tuning=None):
-    """T steps in place on x (float32 device tensor, (ny, nx) or (nz, ny, nx))."""
+def run(x, coeffs, T, power=None, tuning=None, form=None):
+    """T steps in place on x (float32 device tensor, (ny, nx) or (nz, ny, nx)).  form defaults
+    to HOTSPOT when power is given, else DIFFUSION."""
     _check_tensor(x, "x")
-    form = HOTSPOT if power is not None else DIFFUSION
+    if form is None:
+        form = HOTSPOT if power is not None else DIFFUSION
     p = Plan(form, x.shape, tuning)
     try:
         p.run(x, coeffs, T, power)

@@ -472,7 +472,8 @@ stencil_status_t stencil_run_batched(int n, const stencil_batch_item_t* items, v
   for (int i = 0; i < n; ++i) {
     const stencil_batch_item_t& it = items[i];
     if (it.form != STENCIL_DIFFUSION)
-      return fail(it.form == STENCIL_HOTSPOT ? STENCIL_ERR_UNSUPPORTED : STENCIL_ERR_INVALID_ARG,
+      return fail(it.form == STENCIL_HOTSPOT || it.form == STENCIL_HOTSPOT_PHYS ? STENCIL_ERR_UNSUPPORTED
+                                                                                : STENCIL_ERR_INVALID_ARG,
                   "batched launch supports the diffusion form");
     if ((it.ndim != 2 && it.ndim != 3) || it.nx < 1 || it.ny < 1 || it.nz < 1 || (it.ndim == 2 && it.nz != 1))
       return fail(STENCIL_ERR_INVALID_ARG, "item " + std::to_string(i) + ": bad dimensions");

@@ -8,6 +8,8 @@
 //   forward step (Table 2):   wx_m = cw, wx_p = ce, wy_m = cn, wy_p = cs, wz_m = cb, wz_p = ca
 //   transposed step (adjoint): wx_m = ce, wx_p = cw, wy_m = cs, wy_p = cn, wz_m = ca, wz_p = cb
 // kamb = c_amb * t_amb rounded once in FP32; cp multiplies the power map.
+// Physical Hotspot 2D (Table 2 as printed): wx_m = wx_p = Rx_1, wy_m = wy_p = Ry_1,
+// wz_m = Rz_1, cp = sdc, kamb = TEMP_AMB; c0 and wz_p are unused.
 struct DevCoef {
   float c0, wx_m, wx_p, wy_m, wy_p, wz_m, wz_p, cp, kamb;
 };
@@ -68,6 +70,16 @@ __device__ __forceinline__ void fma_pair_dpp(float wl, float xl, float& al, floa
       "v_fmac_f32_dpp %1, %4, %5 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
       : "+v"(al), "+v"(au)
       : "v"(xl), "v"(wl), "v"(xu), "v"(wu));
+}
+
+// The same pairing for sums: sl = (xl of lane i-1) + yl and su = (xu of lane i+1) + yu, each
+// one v_add_f32 whose first source is read through DPP (end lanes read 0; halo columns only).
+// The outputs are early-clobber: the first add must not overwrite an operand of the second.
+__device__ __forceinline__ void add_pair_dpp(float xl, float yl, float& sl, float xu, float yu, float& su) {
+  asm("s_nop 1\n\tv_add_f32_dpp %0, %2, %3 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %1, %4, %5 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "=&v"(sl), "=&v"(su)
+      : "v"(xl), "v"(yl), "v"(xu), "v"(yu));
 }
 
 // gfx950 dispatches consecutive workgroup ids round-robin over its 8 XCDs, each with a

@@ -26,7 +26,7 @@ const int kK3A[] = {1, 2, 3, 4};
 int tb_instantiated(int ndim, KMode m, const int** ks) {
   if (ndim == 2) {
     if (m == KM_DIFF) { *ks = kK2D; return 6; }
-    if (m == KM_HOT) { *ks = kK2H; return 4; }
+    if (m == KM_HOT || m == KM_PHYS) { *ks = kK2H; return 4; }
     *ks = kK2A; return 3;
   }
   if (m == KM_DIFF) { *ks = kK3D; return 6; }
@@ -46,6 +46,7 @@ hipError_t launch_tb2d(int K, KMode m, bool full, const Tb2dArgs& a, hipStream_t
     case KM_HOT: return launch_tb2d_hot(K, full, a, s);
     case KM_ADJ: return launch_tb2d_adj(K, false, full, a, s);
     case KM_ADJ_ACC: return launch_tb2d_adj(K, true, full, a, s);
+    case KM_PHYS: return launch_tb2d_phys(K, full, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -56,6 +57,7 @@ hipError_t launch_tb3d(int K, KMode m, bool full, const Tb3dArgs& a, hipStream_t
     case KM_HOT: return launch_tb3d_hot(K, full, a, s);
     case KM_ADJ: return launch_tb3d_adj(K, false, full, a, s);
     case KM_ADJ_ACC: return launch_tb3d_adj(K, true, full, a, s);
+    case KM_PHYS: break;  // 2D only
   }
   return hipErrorInvalidValue;
 }
@@ -67,6 +69,10 @@ hipError_t launch_plain(KMode m, const PlainArgs& a, hipStream_t s) {
     case KM_HOT: hipLaunchKernelGGL((plain_kernel<true, false, false>), dim3(nb), dim3(256), 0, s, a); break;
     case KM_ADJ: hipLaunchKernelGGL((plain_kernel<false, true, false>), dim3(nb), dim3(256), 0, s, a); break;
     case KM_ADJ_ACC: hipLaunchKernelGGL((plain_kernel<false, true, true>), dim3(nb), dim3(256), 0, s, a); break;
+    case KM_PHYS:
+      if (a.ndim != 2) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((plain_kernel<true, false, false, true>), dim3(nb), dim3(256), 0, s, a);
+      break;
   }
   return hipGetLastError();
 }

@@ -102,7 +102,7 @@ Geom3D geom3d(int K, bool adj, int nx, int ny, int nz, int segz) {
 // The paper's model (Eq. 6-8) counts external-memory cells including the overlapped halos;
 // on the GPU a pass also costs VALU time for the redundantly computed halo cells, so a pass is
 // priced as max(memory, arithmetic) after wave quantisation, plus a launch overhead.
-double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj) {
+double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj, bool phys) {
   const DeviceInfo& d = device_info();
   const int W = 64 * kTb2dV;
   const long passes = (T + g.K - 1) / g.K;
@@ -110,7 +110,9 @@ double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj
   const double rows = (double)g.seg + 2.0 * g.K;  // streamed rows per tile
   const int nread = (hot && !adj) ? 2 : 1;
   const double bytes = tiles * rows * W * 4.0 * nread + (double)nx * ny * 4.0 * (adj && hot ? 3 : 1);
-  const double ops_per_cell = (adj ? 5.5 : 5.5) + (hot && !adj ? 1.25 : 0.0);
+  // VALU instructions per cell and level (the physical hotspot formula takes 9 rounded
+  // operations where the weighted sum takes 5)
+  const double ops_per_cell = phys ? 9.5 : (adj ? 5.5 : 5.5) + (hot && !adj ? 1.25 : 0.0);
   const double ops = tiles * rows * W * g.K * ops_per_cell;
   const double slots = (double)d.cus * 4 * 2;  // two 64-lane waves per SIMD
   const double rounds = std::ceil(tiles / slots);
@@ -214,8 +216,20 @@ int pick_segz3d(int K, bool adj, int nx, int ny, int nz, int wgs_per_cu) {
   return best;
 }
 
-DevCoef dev_coef(const stencil_coeffs_t& c, bool adjoint) {
+DevCoef dev_coef(const stencil_coeffs_t& c, bool adjoint, bool phys) {
   DevCoef d;
+  if (phys) {
+    // Table 2's physical Hotspot 2D parameters (see DevCoef): sdc in cp, Rx_1 in ce, Ry_1 in
+    // cs, Rz_1 in c_amb, TEMP_AMB in t_amb
+    d.c0 = 0.0f;
+    d.wx_m = d.wx_p = c.ce;
+    d.wy_m = d.wy_p = c.cs;
+    d.wz_m = c.c_amb;
+    d.wz_p = 0.0f;
+    d.cp = c.cp;
+    d.kamb = c.t_amb;
+    return d;
+  }
   d.c0 = c.cc;
   if (!adjoint) {
     d.wx_m = c.cw; d.wx_p = c.ce; d.wy_m = c.cn; d.wy_p = c.cs; d.wz_m = c.cb; d.wz_p = c.ca;
@@ -257,7 +271,10 @@ hipError_t poison_scratch(const stencil_plan_s* p) {
   return launch_fill(p->scratch, p->cells, __builtin_nanf(""), p->stream);
 }
 
-KMode fwd_mode(const stencil_plan_s* p) { return p->form == STENCIL_HOTSPOT ? KM_HOT : KM_DIFF; }
+KMode form_mode(stencil_form_t f) {
+  return f == STENCIL_HOTSPOT ? KM_HOT : (f == STENCIL_HOTSPOT_PHYS ? KM_PHYS : KM_DIFF);
+}
+KMode fwd_mode(const stencil_plan_s* p) { return form_mode(p->form); }
 
 // Smallest instantiated K >= k.
 int inst_k_for(int ndim, KMode m, int k) {
@@ -434,8 +451,9 @@ stencil_status_t autotune(stencil_plan_s* p, TuneResult* out) {
       return STENCIL_OK;
     }
   }
-  const bool hot = p->form == STENCIL_HOTSPOT;
-  const KMode m = hot ? KM_HOT : KM_DIFF;
+  const bool hot = p->form != STENCIL_DIFFUSION;  // reads a power map
+  const bool phys = p->form == STENCIL_HOTSPOT_PHYS;
+  const KMode m = fwd_mode(p);
   const long Tref = 240;  // a step count divisible by every instantiated k
   struct Cand {
     int K, seg;
@@ -453,12 +471,12 @@ stencil_status_t autotune(stencil_plan_s* p, TuneResult* out) {
       for (int seg : {96, 128, 160, 192, 224, 288, 352, 480, 608}) {
         if (seg < 2 * K && seg < p->ny) continue;
         const Geom2D g = geom2d(K, p->nx, p->ny, seg);
-        cands.push_back({K, g.seg, model_time_2d(g, p->nx, p->ny, Tref, hot, false), 0});
+        cands.push_back({K, g.seg, model_time_2d(g, p->nx, p->ny, Tref, hot, false, phys), 0});
       }
       for (int wpc : {8, 12}) {
         const int seg = pick_seg2d(K, p->nx, p->ny, wpc);
         const Geom2D g = geom2d(K, p->nx, p->ny, seg);
-        cands.push_back({K, seg, model_time_2d(g, p->nx, p->ny, Tref, hot, false), 0});
+        cands.push_back({K, seg, model_time_2d(g, p->nx, p->ny, Tref, hot, false, phys), 0});
       }
     } else {
       for (int mult : {1, 2}) {
@@ -534,7 +552,7 @@ stencil_status_t autotune(stencil_plan_s* p, TuneResult* out) {
       if (pw) launch_fill(pw, p->cells, 0.0f, p->stream);
       stencil_coeffs_t c{};
       c.cc = 0.5f; c.cw = c.ce = c.cn = c.cs = 0.125f; c.cb = c.ca = 0.0f;
-      const DevCoef cf = dev_coef(c, false);
+      const DevCoef cf = dev_coef(c, false, phys);
       hipEvent_t e0, e1;
       hipEventCreate(&e0);
       hipEventCreate(&e1);
@@ -581,8 +599,8 @@ stencil_status_t autotune(stencil_plan_s* p, TuneResult* out) {
       }
       // The transposed pass (it also reads and writes grad_p) is timed on candidates of its
       // own: every instantiated K with a few segment lengths and, in 3D, the balanced launch;
-      // one round after a warm-up.
-      {
+      // one round after a warm-up.  (The physical Hotspot 2D form has no transposed pass.)
+      if (!phys) {
         const DevCoef acf = dev_coef(c, true);
         const int* aks;
         const int nak = tb_instantiated(p->ndim, am, &aks);
@@ -688,7 +706,7 @@ stencil_status_t forward(stencil_plan_s* p, float* grid, const float* power, con
   if (!coeffs) return fail(STENCIL_ERR_INVALID_ARG, "coeffs is NULL");
   if (T < 0) return fail(STENCIL_ERR_INVALID_ARG, "T must be >= 0");
   if (!coeffs_finite(*coeffs)) return fail(STENCIL_ERR_INVALID_ARG, "coefficients must be finite");
-  if (p->form == STENCIL_HOTSPOT && !power) return fail(STENCIL_ERR_INVALID_ARG, "hotspot needs a power map");
+  if (p->form != STENCIL_DIFFUSION && !power) return fail(STENCIL_ERR_INVALID_ARG, "hotspot needs a power map");
   if ((reinterpret_cast<uintptr_t>(grid) & 3) || (power && (reinterpret_cast<uintptr_t>(power) & 3)))
     return fail(STENCIL_ERR_INVALID_ARG, "buffers must be 4-byte aligned");
   if (power == grid) return fail(STENCIL_ERR_INVALID_ARG, "power must not alias grid");
@@ -696,8 +714,8 @@ stencil_status_t forward(stencil_plan_s* p, float* grid, const float* power, con
   if (st != STENCIL_OK) return st;
   if (hipError_t e = poison_scratch(p); e != hipSuccess) return hip_fail(e, "poison fill");
   const KMode m = fwd_mode(p);
-  const DevCoef cf = dev_coef(*coeffs, false);
-  const float* pw = (p->form == STENCIL_HOTSPOT) ? power : nullptr;
+  const DevCoef cf = dev_coef(*coeffs, false, p->form == STENCIL_HOTSPOT_PHYS);
+  const float* pw = (p->form != STENCIL_DIFFUSION) ? power : nullptr;
   int K;
   bool plain;
   resolve_k(p, m, &K, &plain);
@@ -759,8 +777,11 @@ stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int nd
                                 const stencil_tuning_t* tuning, void* hip_stream) {
   if (!out) return fail(STENCIL_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  if (form != STENCIL_DIFFUSION && form != STENCIL_HOTSPOT) return fail(STENCIL_ERR_INVALID_ARG, "unknown form");
+  if (form != STENCIL_DIFFUSION && form != STENCIL_HOTSPOT && form != STENCIL_HOTSPOT_PHYS)
+    return fail(STENCIL_ERR_INVALID_ARG, "unknown form");
   if (ndim != 2 && ndim != 3) return fail(STENCIL_ERR_INVALID_ARG, "ndim must be 2 or 3");
+  if (form == STENCIL_HOTSPOT_PHYS && ndim != 2)
+    return fail(STENCIL_ERR_UNSUPPORTED, "the physical hotspot form is defined for 2D grids");
   if (nx < 1 || ny < 1 || nz < 1) return fail(STENCIL_ERR_INVALID_ARG, "grid dimensions must be >= 1");
   if (ndim == 2 && nz != 1) return fail(STENCIL_ERR_INVALID_ARG, "2D grids need nz == 1");
   const double cells = (double)nx * ny * nz;
@@ -806,7 +827,7 @@ stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int nd
   stencil_tuning_t t{};
   if (tuning) t = *tuning;
   p->tuning = t;
-  const KMode m = form == STENCIL_HOTSPOT ? KM_HOT : KM_DIFF;
+  const KMode m = form_mode(form);
   if (t.variant == 1) {
     p->tuning.k = 1;
   } else if (t.k == 0 || t.seg_len == 0) {
@@ -907,6 +928,8 @@ stencil_status_t stencil_adjoint(stencil_plan_t p, const float* cot, const float
                                  int recompute) {
   stencil_status_t st = check_plan(p);
   if (st != STENCIL_OK) return st;
+  if (p->form == STENCIL_HOTSPOT_PHYS)
+    return fail(STENCIL_ERR_UNSUPPORTED, "no adjoint for the physical hotspot form (use the weighted form)");
   if (!cot || !grad_x0) return fail(STENCIL_ERR_INVALID_ARG, "cotangent and grad_x0 are required");
   if (!coeffs) return fail(STENCIL_ERR_INVALID_ARG, "coeffs is NULL");
   if (T < 0) return fail(STENCIL_ERR_INVALID_ARG, "T must be >= 0");

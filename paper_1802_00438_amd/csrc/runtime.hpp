@@ -35,7 +35,7 @@ struct Geom3D {
 Geom2D geom2d(int K, int nx, int ny, int seg);
 Geom3D geom3d(int K, bool adj, int nx, int ny, int nz, int segz);
 // Model time (seconds) of T steps with the given geometry.
-double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj);
+double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj, bool phys = false);
 double model_time_3d(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj);
 // The same for the balanced 3D launch of nwork workgroups (equal shares of column planes).
 double model_time_3d_bal(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj, int nwork);
@@ -46,7 +46,7 @@ int balanced_nwork3d(int K, bool adj, int nx, int ny, int nz, int mult);
 int pick_seg2d(int K, int nx, int ny, int waves_per_cu);
 int pick_segz3d(int K, bool adj, int nx, int ny, int nz, int wgs_per_cu);
 
-DevCoef dev_coef(const stencil_coeffs_t& c, bool adjoint);
+DevCoef dev_coef(const stencil_coeffs_t& c, bool adjoint, bool phys = false);
 bool coeffs_finite(const stencil_coeffs_t& c);
 
 }  // namespace stn

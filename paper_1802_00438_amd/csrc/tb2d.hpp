@@ -34,6 +34,11 @@
 //     per pass.
 //   * Passes with fewer than K steps (the tail of T, Section 3.2) run the same kernel with
 //     the levels past keff simply forwarding their input row.
+//   * PHYS: Table 2's Hotspot 2D as printed, c + sdc*(p + ((n+s)-2c)*Ry_1 + ((e+w)-2c)*Rx_1
+//     + (TEMP_AMB-c)*Rz_1), each operation rounded in that order.  Its first operation needs
+//     the oldest and the newest row together, so phase 1 keeps the oldest row in place of a
+//     partial sum (same registers) and phase 2 evaluates the whole formula; the ring holds the
+//     raw power rows.
 #pragma once
 #include "device_common.hpp"
 
@@ -81,9 +86,10 @@ __device__ __forceinline__ int tb2d_part_tile(const Tb2dArgs& a, int i) {
   return i;
 }
 
-template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL, int D = 2>
+template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL, int D = 2, bool PHYS = false>
 struct Tb2dTile {
   static_assert(V == 4 || V == 8, "V");
+  static_assert(!PHYS || (HOT && !ADJ && !ACC), "the physical form is a forward hotspot step");
   static_assert(D == 2 || D == 4 || D == 6, "prefetch depth must be even");
   static constexpr int W = 64 * V;    // window width
   static constexpr int RING = tb2d_ring_rows(K);  // hotspot source rows kept in LDS
@@ -145,6 +151,13 @@ struct Tb2dTile {
   template <bool XE, bool YE>
   __device__ __forceinline__ void partial(const float (&Pr)[V], const float (&Cr)[V], float (&o)[V], int j,
                                           const float (&q)[V]) const {
+    if constexpr (PHYS) {
+      // keep the y+1 row (clamped at the last grid row) for phase 2
+      const bool botp = YE && (j == a.ny - 1);
+#pragma unroll
+      for (int v = 0; v < V; ++v) o[v] = botp ? Cr[v] : Pr[v];
+      return;
+    }
     float wl = 0.0f, eu = 0.0f;
     if constexpr (XE) {
       wl = from_lower(Cr[V - 1]);
@@ -193,10 +206,47 @@ struct Tb2dTile {
     }
   }
 
-  // Phase 2 of a level: add the y-1 term (newest row Nr of the level below).
-  template <bool YE>
-  __device__ __forceinline__ void finish(const float (&Nr)[V], const float (&Cr)[V], float (&o)[V], int j) const {
+  // Phase 2 of a level: add the y-1 term (newest row Nr of the level below).  PHYS: o holds
+  // the y+1 row and the whole physical formula is evaluated here, with q the power row.
+  template <bool XE, bool YE>
+  __device__ __forceinline__ void finish(const float (&Nr)[V], const float (&Cr)[V], float (&o)[V], int j,
+                                         const float (&q)[V]) const {
     const bool top = YE && (j == 0);  // y-1 leaves the grid
+    if constexpr (PHYS) {
+      float sx[V];  // e + w
+      if constexpr (XE) {
+        const float wl = from_lower(Cr[V - 1]);
+        const float eu = from_upper(Cr[0]);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const float c = Cr[v];
+          float xm = (v > 0) ? Cr[v - 1] : wl;
+          float xp = (v < V - 1) ? Cr[v + 1] : eu;
+          xm = isL[v] ? c : xm;
+          xp = isR[v] ? c : xp;
+          sx[v] = xp + xm;
+        }
+      } else {
+#pragma unroll
+        for (int v = 1; v < V - 1; ++v) sx[v] = Cr[v + 1] + Cr[v - 1];
+        add_pair_dpp(Cr[V - 1], Cr[1], sx[0], Cr[0], Cr[V - 2], sx[V - 1]);
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const float c = Cr[v];
+        const float yn = (YE && top) ? c : Nr[v];
+        // (a + b) - 2c is one rounding of the exact difference: 2c is exact, so it is the
+        // fused -2*c + (a + b)
+        const float dy = __builtin_fmaf(-2.0f, c, yn + o[v]);
+        const float dx = __builtin_fmaf(-2.0f, c, sx[v]);
+        const float dz = a.cf.kamb - c;
+        float acc = __builtin_fmaf(dy, a.cf.wy_m, q[v]);
+        acc = __builtin_fmaf(dx, a.cf.wx_m, acc);
+        acc = __builtin_fmaf(dz, a.cf.wz_m, acc);
+        o[v] = __builtin_fmaf(a.cf.cp, acc, c);
+      }
+      return;
+    }
     float cym = a.cf.wy_m;
     if constexpr (ADJ && YE) {
       if (top) cym = a.cf.wy_p;
@@ -264,11 +314,11 @@ struct Tb2dTile {
     float qc[V], qn[V];
     (void)qc;
     (void)qn;
-    read_q(K, qc);
+    if constexpr (!PHYS) read_q(K, qc);
 #pragma unroll
     for (int s = K; s >= 1; --s) {
       const int j = r + s;
-      if constexpr (HOT && !ADJ) {
+      if constexpr (HOT && !ADJ && !PHYS) {
         if (s > 1) read_q(s - 1, qn);
       }
       float o[V];
@@ -283,7 +333,7 @@ struct Tb2dTile {
         if (s == K) part_top[v] = o[v];
         else X[s][v] = o[v];
       }
-      if constexpr (HOT && !ADJ) {
+      if constexpr (HOT && !ADJ && !PHYS) {
 #pragma unroll
         for (int v = 0; v < V; ++v) qc[v] = qn[v];
       }
@@ -293,8 +343,13 @@ struct Tb2dTile {
     for (int v = 0; v < V; ++v) X[0][v] = Lb[LB][v];
     if constexpr (HOT && !ADJ) {
       float* qp = ring + slot0 * W + lane * V;
+      if constexpr (PHYS) {
 #pragma unroll
-      for (int v = 0; v < V; ++v) qp[v] = __builtin_fmaf(a.cf.cp, Pb[LB][v], a.cf.kamb);
+        for (int v = 0; v < V; ++v) qp[v] = Pb[LB][v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) qp[v] = __builtin_fmaf(a.cf.cp, Pb[LB][v], a.cf.kamb);
+      }
     }
     prefetch<VEC>(r - D, LB);
     float Pn[K][V];
@@ -306,7 +361,9 @@ struct Tb2dTile {
 #pragma unroll
       for (int v = 0; v < V; ++v) o[v] = (s == K) ? part_top[v] : X[s][v];
       if (FULL || s <= keff) {
-        finish<YE>(X[s - 1], C[s - 1], o, j);
+        float qv[V];
+        if constexpr (PHYS) read_q(s, qv);
+        finish<XE, YE>(X[s - 1], C[s - 1], o, j, qv);
       } else {
 #pragma unroll
         for (int v = 0; v < V; ++v) o[v] = C[s - 1][v];  // surplus level: forward its input row
@@ -424,12 +481,12 @@ struct Tb2dTile {
 
 // One workgroup (one wave) per tile of the launch's part (gridDim.x tiles).  INTERIOR = true
 // is the kernel for part 1; part 0 and part 2 use INTERIOR = false.
-template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL, int D, bool INTERIOR>
+template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL, int D, bool INTERIOR, bool PHYS = false>
 __global__ __launch_bounds__(64) void tb2d_kernel(Tb2dArgs a) {
   constexpr int RING = (HOT && !ADJ) ? tb2d_ring_rows(K) : 1;
   __shared__ __align__(16) float ring[RING * 64 * V];
   const int tile = tb2d_part_tile(a, xcd_remap(blockIdx.x, gridDim.x));
-  Tb2dTile<K, V, HOT, ADJ, ACC, FULL, D> t(a, threadIdx.x, ring);
+  Tb2dTile<K, V, HOT, ADJ, ACC, FULL, D, PHYS> t(a, threadIdx.x, ring);
   t.template process<INTERIOR>(tile);
 }
 
@@ -449,13 +506,14 @@ constexpr int kTb2dV = 4;
 // for 8 < K <= 12, which has the registers for four at the same two waves per SIMD (+7%).
 #define TB2D_DEPTH(K, HOT, ADJ, INTERIOR) \
   ((!(HOT) && !(ADJ)) ? 4 : ((HOT) && !(ADJ) && (INTERIOR) && (K) > 8 && (K) <= 12) ? 4 : 2)
-#define TB_LAUNCH2D(K, HOT, ADJ, ACC, FULL, a, s)                                                       \
+#define TB_LAUNCH2D_F(K, HOT, ADJ, ACC, FULL, PHYS, a, s)                                               \
   do {                                                                                                  \
     if ((a).part == 1)                                                                                  \
-      hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL, TB2D_DEPTH(K, HOT, ADJ, true), true>), \
+      hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL, TB2D_DEPTH(K, HOT, ADJ, true), true, PHYS>), \
                          dim3(tb2d_part_tiles(a)), dim3(64), 0, s, a);                                  \
     else                                                                                                \
-      hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL, TB2D_DEPTH(K, HOT, ADJ, false), false>), \
+      hipLaunchKernelGGL((tb2d_kernel<K, kTb2dV, HOT, ADJ, ACC, FULL, TB2D_DEPTH(K, HOT, ADJ, false), false, PHYS>), \
                          dim3(tb2d_part_tiles(a)), dim3(64), 0, s, a);                                  \
     return hipGetLastError();                                                                           \
   } while (0)
+#define TB_LAUNCH2D(K, HOT, ADJ, ACC, FULL, a, s) TB_LAUNCH2D_F(K, HOT, ADJ, ACC, FULL, false, a, s)

@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import paper_1802_00438_amd as S
-from workloads import WORKLOADS, SETS, DIFFUSION, HOTSPOT
+from workloads import WORKLOADS, SETS, DIFFUSION, HOTSPOT, HOTSPOT_PHYS
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -25,12 +25,12 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 
 
-def cone_sample(x0, power, cf, T, idx, dtype=np.float32):
+def cone_sample(x0, power, cf, T, idx, dtype=np.float32, form=None):
     """Oracle value of output cell idx after T steps, from the sub-grid of radius T."""
     sl = tuple(slice(max(0, i - T), min(n, i + T + 1)) for i, n in zip(idx, x0.shape))
     sub = np.ascontiguousarray(x0[sl])
     psub = np.ascontiguousarray(power[sl]) if power is not None else None
-    out = oracle.forward(sub, cf, T, power=psub, dtype=dtype)
+    out = oracle.forward(sub, cf, T, power=psub, dtype=dtype, form=form)
     return out[tuple(i - s.start for i, s in zip(idx, sl))]
 
 
@@ -56,6 +56,30 @@ def test_hotspot2d_16384_full_size_samples():
         assert g == ref, (idx, g, ref)
     # a property that holds at any size: the field stays within the bounds of the fixed point
     # and the initial data (convex weights plus a non-negative source)
+    assert got.min() >= 80.0 and got.max() <= 350.0 + wl.T * 64 * 1e-3 + 1.0
+
+
+def test_hotspot2d_phys_16384_full_size_samples():
+    """The physical-form workload at its full size, auto-tuned as the bench runs it."""
+    wl = WORKLOADS["hotspot2d_phys_16384"]
+    x0 = wl.field()
+    p = wl.power()
+    x = torch.from_numpy(x0).cuda()
+    pw = torch.from_numpy(p).cuda()
+    plan = S.Plan(HOTSPOT_PHYS, wl.shape)
+    try:
+        plan.run(x, wl.coeffs, wl.T, pw)
+        torch.cuda.synchronize()
+        got = x.cpu().numpy()
+    finally:
+        plan.close()
+    assert np.isfinite(got).all()
+    n = wl.nx
+    for idx in [(n // 2 + 3, n // 5 + 11), (0, 0), (n - 1, 4321), (1234, n - 1)]:
+        ref = cone_sample(x0, p, wl.coeffs, wl.T, idx, form=HOTSPOT_PHYS)
+        g = got[idx]
+        assert abs(g - ref) / abs(ref) <= TOL, (idx, g, ref)
+        assert g == ref, (idx, g, ref)
     assert got.min() >= 80.0 and got.max() <= 350.0 + wl.T * 64 * 1e-3 + 1.0
 
 

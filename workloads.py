@@ -128,8 +128,9 @@ class Workload:
         return uniform(self.shape, self.target_lo, self.target_hi, self.seed + 2)
 
 
-# The five workloads, in order: small 2D diffusion, large 2D hotspot, large 3D diffusion,
-# the batch of uneven grids, and the 3D hotspot adjoint problem.
+# The workloads, in order: small 2D diffusion, large 2D hotspot, large 3D diffusion, the
+# batch of uneven grids, the 3D hotspot adjoint problem, and the large 2D hotspot problem in
+# the physical form.
 WORKLOADS = {
     "diffusion2d_256": Workload("diffusion2d_256", DIFFUSION, 2, 256, 256, 1, 16, "D2", 0.0, 1.0, seed=1000),
     "hotspot2d_16384": Workload("hotspot2d_16384", HOTSPOT, 2, 16384, 16384, 1, 1000, "H2", 300.0, 350.0,
@@ -137,6 +138,10 @@ WORKLOADS = {
     "diffusion3d_512": Workload("diffusion3d_512", DIFFUSION, 3, 512, 512, 512, 200, "D3", 0.0, 1.0, seed=3000),
     "hotspot3d_256_adjoint": Workload("hotspot3d_256_adjoint", HOTSPOT, 3, 256, 256, 256, 400, "H3", 300.0, 350.0,
                                       power_hi=1e-3, seed=5000, ckpt_every=20),
+    # the large 2D hotspot problem in Table 2's physical form (parameters HP2, the physical
+    # reading of H2); listed sixth, so its seed is 6000
+    "hotspot2d_phys_16384": Workload("hotspot2d_phys_16384", HOTSPOT_PHYS, 2, 16384, 16384, 1, 1000, "HP2",
+                                     300.0, 350.0, power_hi=1e-3, seed=6000),
 }
 BATCH_SEED = 4000
 
