@@ -243,9 +243,10 @@ def main():
                 "frac": round(frac_hbm, 4)}
     # measured HBM traffic per launch over the same average launch duration, in GB/s
     roof["traffic"] = None if traffic_bytes is None else round(traffic_bytes / (kern_ms * 1e-3) / 1e9, 1)
-    # the kernel symbol: rows in flight are 4 in the edge-free hotspot kernel for 8 < K <= 12
+    # the kernel symbol: four rows in flight in the edge-free hotspot kernel for 8 < K <= 12
     depth = 4 if split and 8 < K <= 12 else 2
-    roof["kernel"] = "tb2d_kernel<%d, 4, true, false, false, true, %d, %s>" % (K, depth, "true" if split else "false")
+    roof["kernel"] = "tb2d_kernel<%d, 4, true, false, false, true, %d, %s, false>" % (
+        K, depth, "true" if split else "false")
     roof["avg_launch_ms"] = round(kern_ms, 4)
     roof["launches_per_run"] = n_full
     roof["algorithmic_bytes_per_launch"] = int(launch_bytes)
