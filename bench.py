@@ -7,6 +7,8 @@ temperature and power maps already resident in HBM.  value = cell updates per se
 (Table 2 bytes per update).  The same JSON line carries, for the dominant kernel, the
 achieved rate against its roofline, the CPU oracle timed on a bounded sample, and (unless
 --quick) the plain one-step-per-launch kernel, the 3D and batched workloads and the adjoint.
+`model_accuracy` sets each measured workload against the library's own time model and the
+paper's Eq. 3-9 model at the same blocking (measured over modelled throughput).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 """
@@ -102,6 +104,27 @@ def measured_traffic(K, seg):
         return None
     return (rec["fetch_kib_per_dispatch"] * 1024.0 / rec["copy_fetch_factor"] +
             rec["write_kib_per_dispatch"] * 1024.0 / rec["copy_write_factor"])
+
+
+def model_row(S, plan, T, ms, ndim, nread, dims, bsize):
+    """Measured against modelled for one workload: the library's own plan model (the tuner's)
+    and the paper's Eq. 3-9 external-memory model at this blocking, with the HBM peak as
+    th_max and one cell per lane per clock as the pipeline rate (so Eq. 3 gives th_max).  Ratios
+    are measured throughput over modelled throughput, the paper's convention (Section 6.2)."""
+    tun = plan.tuning
+    k = 1 if tun["variant"] == 1 else tun["k"]
+    gm = plan.model(T)
+    nx, ny, nz = dims
+    eq = S.stencil_model_estimate(ndim=ndim, rad=1, par_vec=16384, par_time=k, f_max_hz=2.4e9, size_cell=4,
+                                  num_read=nread, num_write=1, bsize_x=bsize[0], bsize_y=bsize[1], dim_x=nx,
+                                  dim_y=ny, dim_z=nz, iter=T, th_max_gbs=HBM_PEAK_GBS)
+    cells = nx * ny * nz
+    meas_gbs = (nread + 1) * 4.0 * cells * T / (ms * 1e-3) / 1e9
+    return {"k": k, "measured_ms": round(ms, 3), "model_ms": round(gm["seconds"] * 1e3, 3),
+            "model_mem_ms": round(gm["mem_seconds"] * 1e3, 3), "model_alu_ms": round(gm["alu_seconds"] * 1e3, 3),
+            "measured_over_model": round(gm["seconds"] * 1e3 / ms, 3),
+            "eq9_gbs": round(eq["throughput_gbs"], 1), "measured_gbs_eq9": round(meas_gbs, 1),
+            "measured_over_eq9": round(meas_gbs / eq["throughput_gbs"], 3)}
 
 
 def time_call(fn, stream, reps):
@@ -278,6 +301,8 @@ def main():
     }
 
     extras = {}
+    study = {}
+    study["hotspot2d_16384"] = model_row(S, plan, wl.T, ms, 2, 2, (wl.nx, wl.ny, 1), (256, 0))
     if not args.quick:
         # plain one-step-per-launch comparator on the same grid (fewer steps, same per-step work)
         pplan = S.Plan(HOTSPOT, wl.shape, {"variant": 1})
@@ -285,6 +310,7 @@ def main():
         pplan.run(x, cf, 4, p)
         pms = time_call(lambda: pplan.run(x, cf, Tp, p), stream, 2)
         pg = cells * Tp / (pms * 1e-3) / 1e9
+        study["plain_hotspot2d_16384"] = model_row(S, pplan, Tp, pms, 2, 2, (wl.nx, wl.ny, 1), (wl.nx + 2, 0))
         extras["plain_hotspot2d_16384"] = {"gcells": round(pg, 1), "ms_per_step_update": round(pms / Tp, 4),
                                            "hbm_gbs_eff": round(pg * 12, 1),
                                            "speedup_tb_vs_plain": round(gcells / pg, 2)}
@@ -303,6 +329,7 @@ def main():
         pl6.run(x6, w6.coeffs, 24, p6)
         ms6 = time_call(lambda: pl6.run(x6, w6.coeffs, w6.T, p6), stream, 2)
         g6 = w6.cells * w6.T / (ms6 * 1e-3) / 1e9
+        study["hotspot2d_phys_16384"] = model_row(S, pl6, w6.T, ms6, 2, 2, (w6.nx, w6.ny, 1), (256, 0))
         extras["hotspot2d_phys_16384"] = {"gcells": round(g6, 1), "ms_per_run": round(ms6, 2),
                                           "k": pl6.tuning["k"], "seg_len": pl6.tuning["seg_len"],
                                           "pct_single_pass_roofline": round(100 * g6 / (HBM_PEAK_GBS / 12), 1)}
@@ -322,6 +349,7 @@ def main():
         pp3 = S.Plan(DIFFUSION, w3.shape, {"variant": 1})
         msp3 = time_call(lambda: pp3.run(x3, w3.coeffs, 40), stream, 1)
         gp3 = w3.cells * 40 / (msp3 * 1e-3) / 1e9
+        study["diffusion3d_512"] = model_row(S, pl3, w3.T, ms3, 3, 1, (w3.nx, w3.ny, w3.nz), (128, 48))
         extras["diffusion3d_512"] = {"gcells_tb": round(g3, 1), "ms_tb": round(ms3, 2), "k": pl3.tuning["k"],
                                      "gcells_plain": round(gp3, 1),
                                      "pct_single_pass_roofline": round(100 * g3 / (HBM_PEAK_GBS / 8), 1)}
@@ -335,6 +363,7 @@ def main():
         pl1 = S.Plan(DIFFUSION, w1.shape)
         pl1.run(x1, w1.coeffs, w1.T)
         ms1 = time_call(lambda: pl1.run(x1, w1.coeffs, w1.T), stream, 20)
+        study["diffusion2d_256"] = model_row(S, pl1, w1.T, ms1, 2, 1, (w1.nx, w1.ny, 1), (256, 0))
         extras["diffusion2d_256"] = {"us_per_run": round(ms1 * 1e3, 1),
                                      "gcells": round(w1.cells * w1.T / (ms1 * 1e-3) / 1e9, 1)}
         pl1.close()
@@ -349,6 +378,7 @@ def main():
         pl5.run(xs, w5.coeffs, 4, p5)
         xs.copy_(x5)
         fwd_ms = time_call(lambda: pl5.run_ckpt(xs, w5.coeffs, w5.T, w5.ckpt_every, p5), stream, 1)
+        study["hotspot3d_256"] = model_row(S, pl5, w5.T, fwd_ms, 3, 2, (w5.nx, w5.ny, w5.nz), (128, 48))
         cot = (xs - y5).contiguous()
         gx = torch.empty_like(x5)
         gp = torch.empty_like(x5)
@@ -382,6 +412,7 @@ def main():
         log("[bench] batched: %.1f GCell/s aggregate" % (upd / (bms * 1e-3) / 1e9))
 
     out["other_workloads"] = extras
+    out["model_accuracy"] = study
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -152,6 +152,22 @@ void stencil_batch_destroy(stencil_batch_t batch);
 /* Report the blocking the plan resolved to (after auto-tuning). */
 stencil_status_t stencil_get_tuning(stencil_plan_t plan, stencil_tuning_t* out);
 
+/* The library's own time model for T steps of the plan's resolved blocking, the model the
+ * tuner ranks candidates with: the paper's external-memory count (Section 4, Eq. 6-8, with
+ * the GPU tile's halo rows added and the HBM rate at an achievable fraction of its peak)
+ * next to an arithmetic term for the redundantly computed halo cells, priced per pass as the
+ * larger of the two plus a launch overhead.  Host arithmetic only; no device work.
+ *   seconds       modelled time of the T steps
+ *   mem_seconds   memory part, summed over the passes
+ *   alu_seconds   arithmetic part, summed over the passes (0 for the plain kernel)
+ *   passes        passes over HBM (T for the plain one-step kernel)
+ * Returns INVALID_ARG for a NULL argument or T < 0. */
+typedef struct {
+  double seconds, mem_seconds, alu_seconds;
+  long passes;
+} stencil_plan_model_t;
+stencil_status_t stencil_plan_model(stencil_plan_t plan, int T, stencil_plan_model_t* out);
+
 /* Free the plan, its scratch and checkpoints (synchronises the plan stream).  NULL ok. */
 void stencil_destroy(stencil_plan_t plan);
 

@@ -27,7 +27,7 @@ STATUS = {0: "STENCIL_OK", -1: "STENCIL_ERR_INVALID_ARG", -2: "STENCIL_ERR_UNSUP
 
 EXPORTED = ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoint", "stencil_run_batched",
             "stencil_batch_destroy", "stencil_get_tuning", "stencil_destroy", "stencil_status_string",
-            "stencil_last_error", "stencil_model_estimate")
+            "stencil_last_error", "stencil_model_estimate", "stencil_plan_model")
 
 
 class StencilError(RuntimeError):
@@ -65,6 +65,11 @@ class ModelResult(ctypes.Structure):
                 ("throughput_gbs", ctypes.c_double)]
 
 
+class PlanModel(ctypes.Structure):
+    _fields_ = [("seconds", ctypes.c_double), ("mem_seconds", ctypes.c_double), ("alu_seconds", ctypes.c_double),
+                ("passes", ctypes.c_long)]
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -98,8 +103,10 @@ def lib():
             L.stencil_last_error.argtypes = []
             L.stencil_last_error.restype = ctypes.c_char_p
             L.stencil_model_estimate.argtypes = [ctypes.POINTER(ModelParams), ctypes.POINTER(ModelResult)]
+            L.stencil_plan_model.argtypes = [vp, i, ctypes.POINTER(PlanModel)]
             for name in ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoint",
-                         "stencil_run_batched", "stencil_get_tuning", "stencil_model_estimate"):
+                         "stencil_run_batched", "stencil_get_tuning", "stencil_model_estimate",
+                         "stencil_plan_model"):
                 getattr(L, name).restype = i
             _lib = L
     return _lib
@@ -188,6 +195,13 @@ def stencil_get_tuning(plan) -> dict:
     return {k: getattr(t, k) for k, _ in Tuning._fields_}
 
 
+def stencil_plan_model(plan, T) -> dict:
+    """The library's time model of T steps on the plan's resolved blocking."""
+    m = PlanModel()
+    _check(lib().stencil_plan_model(plan, int(T), ctypes.byref(m)))
+    return {k: getattr(m, k) for k, _ in PlanModel._fields_}
+
+
 def stencil_destroy(plan):
     lib().stencil_destroy(plan)
 
@@ -257,6 +271,9 @@ class Plan:
     @property
     def tuning(self):
         return stencil_get_tuning(self.handle)
+
+    def model(self, T):
+        return stencil_plan_model(self.handle, T)
 
     def close(self):
         if self.handle is not None and self.handle.value:

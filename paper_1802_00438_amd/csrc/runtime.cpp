@@ -102,7 +102,7 @@ Geom3D geom3d(int K, bool adj, int nx, int ny, int nz, int segz) {
 // The paper's model (Eq. 6-8) counts external-memory cells including the overlapped halos;
 // on the GPU a pass also costs VALU time for the redundantly computed halo cells, so a pass is
 // priced as max(memory, arithmetic) after wave quantisation, plus a launch overhead.
-double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj, bool phys) {
+double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj, bool phys, ModelParts* parts) {
   const DeviceInfo& d = device_info();
   const int W = 64 * kTb2dV;
   const long passes = (T + g.K - 1) / g.K;
@@ -122,10 +122,11 @@ double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj
   const double conc = std::min(1.0, std::sqrt(tiles / (2.0 * slots)));
   const double tm = bytes / (d.hbm_gbs * 1e9 * d.achievable_frac);
   const double ta = ops / (d.valu_lane_ops * 0.8) / (quant * conc);
+  if (parts) *parts = ModelParts{passes * tm, passes * ta};
   return passes * (std::max(tm, ta) + 4e-6);
 }
 
-double model_time_3d(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj) {
+double model_time_3d(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj, ModelParts* parts) {
   const DeviceInfo& d = device_info();
   const int WX = 64 * kTb3dV;
   const int WY = adj ? kTb3dAdjWY : kTb3dWY;
@@ -140,10 +141,12 @@ double model_time_3d(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, 
   const double quant = tiles / (rounds * slots);
   const double tm = bytes / (d.hbm_gbs * 1e9 * d.achievable_frac);
   const double ta = ops / (d.valu_lane_ops * 0.6) / quant;
+  if (parts) *parts = ModelParts{passes * tm, passes * ta};
   return passes * (std::max(tm, ta) + 4e-6);
 }
 
-double model_time_3d_bal(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj, int nwork) {
+double model_time_3d_bal(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj, int nwork,
+                         ModelParts* parts) {
   const DeviceInfo& d = device_info();
   const int WX = 64 * kTb3dV;
   const int WY = adj ? kTb3dAdjWY : kTb3dWY;
@@ -160,6 +163,7 @@ double model_time_3d_bal(const Geom3D& g, int nx, int ny, int nz, long T, bool h
   const double quant = (double)nwork / (rounds * d.cus);
   const double tm = bytes / (d.hbm_gbs * 1e9 * d.achievable_frac);
   const double ta = ops / (d.valu_lane_ops * 0.6) / quant;
+  if (parts) *parts = ModelParts{passes * tm, passes * ta};
   return passes * (std::max(tm, ta) + 4e-6);
 }
 
@@ -899,6 +903,47 @@ stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int nd
 stencil_status_t stencil_get_tuning(stencil_plan_t plan, stencil_tuning_t* out) {
   if (!plan || !out) return fail(STENCIL_ERR_INVALID_ARG, "NULL argument");
   *out = plan->tuning;
+  return STENCIL_OK;
+}
+
+stencil_status_t stencil_plan_model(stencil_plan_t p, int T, stencil_plan_model_t* out) {
+  if (!p || !out) return fail(STENCIL_ERR_INVALID_ARG, "NULL argument");
+  if (T < 0) return fail(STENCIL_ERR_INVALID_ARG, "T must be >= 0");
+  const KMode m = fwd_mode(p);
+  const bool hot = p->form != STENCIL_DIFFUSION;
+  int K;
+  bool plain;
+  resolve_k(p, m, &K, &plain);
+  ModelParts mp;
+  stencil_plan_model_t r{};
+  if (plain) {
+    // one step per launch: every step reads the grid (and power) and writes it once
+    const DeviceInfo& d = device_info();
+    const double bytes = (double)p->cells * 4.0 * ((hot ? 2 : 1) + 1);
+    r.passes = T;
+    r.mem_seconds = T * bytes / (d.hbm_gbs * 1e9 * d.achievable_frac);
+    r.alu_seconds = 0.0;
+    r.seconds = T * (bytes / (d.hbm_gbs * 1e9 * d.achievable_frac) + 4e-6);
+  } else {
+    const int kpass = std::min(K, std::max(1, p->tuning.k));
+    if (p->ndim == 2) {
+      Geom2D g = geom2d(K, p->nx, p->ny, p->tuning.seg_len);
+      g.K = kpass;
+      r.seconds = model_time_2d(g, p->nx, p->ny, T, hot, false, p->form == STENCIL_HOTSPOT_PHYS, &mp);
+    } else if (p->nwork3d > 0) {
+      Geom3D g = geom3d(K, false, p->nx, p->ny, p->nz, p->nz);
+      g.K = kpass;
+      r.seconds = model_time_3d_bal(g, p->nx, p->ny, p->nz, T, hot, false, p->nwork3d, &mp);
+    } else {
+      Geom3D g = geom3d(K, false, p->nx, p->ny, p->nz, p->tuning.seg_len);
+      g.K = kpass;
+      r.seconds = model_time_3d(g, p->nx, p->ny, p->nz, T, hot, false, &mp);
+    }
+    r.passes = (T + kpass - 1) / kpass;
+    r.mem_seconds = mp.mem;
+    r.alu_seconds = mp.alu;
+  }
+  *out = r;
   return STENCIL_OK;
 }
 

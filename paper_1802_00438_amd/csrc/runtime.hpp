@@ -33,12 +33,18 @@ struct Geom3D {
   int ax = 0, ay = 0, fx = 0, fy = 0;  // edge-flush tiling per axis (see Tb3dArgs)
 };
 Geom2D geom2d(int K, int nx, int ny, int seg);
+// Memory and arithmetic parts of a modelled time, summed over the passes (seconds).
+struct ModelParts {
+  double mem = 0.0, alu = 0.0;
+};
 Geom3D geom3d(int K, bool adj, int nx, int ny, int nz, int segz);
 // Model time (seconds) of T steps with the given geometry.
-double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj, bool phys = false);
-double model_time_3d(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj);
+double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj, bool phys = false,
+                     ModelParts* parts = nullptr);
+double model_time_3d(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj, ModelParts* parts = nullptr);
 // The same for the balanced 3D launch of nwork workgroups (equal shares of column planes).
-double model_time_3d_bal(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj, int nwork);
+double model_time_3d_bal(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj, int nwork,
+                         ModelParts* parts = nullptr);
 // Workgroups of a balanced 3D launch: `mult` per CU, fewer when the grid has too few column
 // planes to give each at least a few times the pipeline depth.
 int balanced_nwork3d(int K, bool adj, int nx, int ny, int nz, int mult);

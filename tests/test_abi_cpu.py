@@ -73,6 +73,8 @@ def test_calls_on_null_plan_are_rejected():
     assert L.stencil_run_ckpt(None, None, None, ctypes.byref(c), 1, 0) == -1
     assert L.stencil_adjoint(None, None, None, ctypes.byref(c), 1, None, None, 0) == -1
     assert L.stencil_get_tuning(None, None) == -1
+    m = S.PlanModel()
+    assert L.stencil_plan_model(None, 10, ctypes.byref(m)) == -1
     L.stencil_destroy(None)        # no-op
     L.stencil_batch_destroy(None)  # no-op
 
