@@ -60,6 +60,9 @@ def _load():
                 adj = getattr(lib, "oracle_adjoint_" + suf)
                 adj.restype = ctypes.c_int
                 adj.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_float), p, ctypes.c_int, p, p]
+                st = getattr(lib, "oracle_star2d_" + suf)
+                st.restype = ctypes.c_int
+                st.argtypes = [ctypes.c_int] * 3 + [ctypes.POINTER(ctypes.c_float), p, ctypes.c_int]
             lib.oracle_num_threads.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -138,6 +141,27 @@ def adjoint(cot, coeffs, T, form=DIFFUSION, dtype=np.float64, want_grad_p=None):
     if rc != 0:
         raise ValueError("oracle_adjoint rejected its arguments")
     return gx, gp
+
+
+def star2d(x0, weights, T, dtype=np.float64):
+    """T clamped Jacobi steps of the radius-r 2D star stencil (diffusion form) on ``x0`` of
+    shape (ny, nx).  ``weights`` has 1 + 4r entries: cc, then w_d, e_d for d = 1..r, then
+    s_1..s_r, then n_1..n_r (FP32 values; the FP64 run promotes them exactly)."""
+    lib = _load()
+    dtype = np.dtype(dtype)
+    ct = ctypes.c_double if dtype == np.float64 else ctypes.c_float
+    fn = lib.oracle_star2d_f64 if dtype == np.float64 else lib.oracle_star2d_f32
+    g = _prep(x0, dtype)
+    if g.ndim != 2:
+        raise ValueError("the radius-r stencil is 2D: shape (ny, nx)")
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    if w.size < 5 or (w.size - 1) % 4:
+        raise ValueError("weights must have 1 + 4r entries")
+    rad = (w.size - 1) // 4
+    rc = fn(rad, g.shape[1], g.shape[0], _ptr(w, ctypes.c_float), _ptr(g, ct), int(T))
+    if rc != 0:
+        raise ValueError("oracle_star2d rejected its arguments")
+    return g
 
 
 def loss(xT, target) -> float:

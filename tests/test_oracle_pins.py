@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import SETS, DIFFUSION, HOTSPOT, HOTSPOT_PHYS, phys_coeffs, uniform
+from workloads import SETS, STAR_SETS, DIFFUSION, HOTSPOT, HOTSPOT_PHYS, phys_coeffs, uniform
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -522,3 +522,103 @@ def test_phys_fp32_error_budget_and_rejections():
         oracle.forward(np.zeros((2, 3, 3)), cf, 1, power=np.zeros((2, 3, 3)), form=HOTSPOT_PHYS)
     with pytest.raises(ValueError):
         oracle.forward(np.zeros((3, 3)), cf, 1, form=HOTSPOT_PHYS)
+
+
+# ---------------------------------------------------------------- radius-r star stencils (Eq. 1, Eq. 2)
+
+STAR = STAR_SETS
+
+
+def dense_star(shape, wts):
+    """Dense A of the radius-r star stencil from its definition: row i gets cc at i and each
+    directional weight at the clamped index of that neighbour."""
+    ny, nx = shape
+    r = (len(wts) - 1) // 4
+    A = np.zeros((nx * ny, nx * ny))
+    for y, x in itertools.product(range(ny), range(nx)):
+        i = y * nx + x
+        A[i, i] += float(wts[0])
+        for d in range(1, r + 1):
+            A[i, y * nx + max(x - d, 0)] += float(wts[2 * d - 1])
+            A[i, y * nx + min(x + d, nx - 1)] += float(wts[2 * d])
+            A[i, min(y + d, ny - 1) * nx + x] += float(wts[2 * r + d])
+            A[i, max(y - d, 0) * nx + x] += float(wts[3 * r + d])
+    return A
+
+
+def test_star_radius_one_is_the_diffusion_stencil():
+    cf = SETS["A2"]  # cc, cw, ce, cn, cs
+    w = np.array([cf[0], cf[1], cf[2], cf[4], cf[3]], dtype=np.float32)
+    x0 = uniform((37, 53), 0.0, 1.0, 141)
+    for dt in (np.float64, np.float32):
+        assert np.array_equal(oracle.star2d(x0, w, 19, dtype=dt), oracle.forward(x0, cf, 19, dtype=dt))
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (5, 3), (1, 7), (7, 1), (2, 9), (3, 3), (1, 1)])
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_star_equals_dense_matrix_power(shape, r):
+    w = STAR[r]
+    A = dense_star(shape, w)
+    x0 = uniform(shape, 0.0, 1.0, 142 + r)
+    for T in (0, 1, 2, 3, 7):
+        ref = (np.linalg.matrix_power(A, T) @ x0.astype(np.float64).ravel()).reshape(shape)
+        assert relerr(oracle.star2d(x0, w, T), ref) < 1e-13, (shape, r, T)
+        assert relerr(oracle.star2d(x0, w, T, dtype=np.float32), ref) < 2e-6, (shape, r, T)
+
+
+@pytest.mark.parametrize("r,T", [(2, 6), (3, 5), (4, 4)])
+def test_star_green_function_exact(r, T):
+    """Away from the edges the impulse response is the T-fold convolution of the stencil,
+    computed here in exact integers (weights scaled by 2^6).  Its denominators fit FP64, so the
+    FP64 oracle must reproduce it exactly."""
+    w = STAR[r]
+    scale = 64
+    iw = [int(round(float(v) * scale)) for v in w]
+    assert all(abs(a - float(v) * scale) == 0 for a, v in zip(iw, w))
+    n = 2 * r * T + 5
+    c = n // 2
+    ex = {(c, c): 1}
+    for _ in range(T):
+        nxt = {}
+        for (y, x), v in ex.items():
+            # scatter: the value at (y, x) feeds (y, x) with cc, (y, x+d) with w_d (it is that
+            # cell's x-d neighbour), (y, x-d) with e_d, (y-d, x) with s_d, (y+d, x) with n_d
+            terms = [((y, x), iw[0])]
+            for d in range(1, r + 1):
+                terms += [((y, x + d), iw[2 * d - 1]), ((y, x - d), iw[2 * d]),
+                          ((y - d, x), iw[2 * r + d]), ((y + d, x), iw[3 * r + d])]
+            for k, wv in terms:
+                nxt[k] = nxt.get(k, 0) + wv * v
+        ex = nxt
+    x0 = np.zeros((n, n))
+    x0[c, c] = 1.0
+    out = oracle.star2d(x0, w, T)
+    ref = np.zeros((n, n))
+    for (y, x), v in ex.items():
+        ref[y, x] = Fraction(v, scale ** T)
+    assert np.array_equal(out, ref)
+
+
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_star_constant_field_and_axis_swap(r):
+    w = STAR[r]
+    x0 = np.full((19, 23), 0.75, dtype=np.float32)
+    assert np.all(oracle.star2d(x0, w, 30, dtype=np.float32) == 0.75)
+    # swapping x and y together with (w_d, e_d) <-> (n_d, s_d) transposes the result
+    sw = w.copy()
+    for d in range(1, r + 1):
+        sw[2 * d - 1], sw[2 * d] = w[3 * r + d], w[2 * r + d]
+        sw[3 * r + d], sw[2 * r + d] = w[2 * d - 1], w[2 * d]
+    x1 = uniform((13, 29), 0.0, 1.0, 150 + r)
+    a = oracle.star2d(x1, w, 9)
+    b = oracle.star2d(np.ascontiguousarray(x1.T), sw, 9)
+    assert relerr(b.T, a) < 1e-14
+
+
+def test_star_rejects_bad_arguments():
+    with pytest.raises(ValueError):
+        oracle.star2d(np.zeros((3, 3)), np.zeros(6, np.float32), 1)
+    with pytest.raises(ValueError):
+        oracle.star2d(np.zeros((2, 3, 3)), STAR[2], 1)
+    with pytest.raises(ValueError):
+        oracle.star2d(np.zeros((3, 3)), STAR[2], -1)

@@ -68,6 +68,26 @@ SETS = {
 }
 
 
+def star_weights(cc, xw, xe, ys, yn):
+    """Pack the weights of a radius-r 2D star stencil: cc; w_d, e_d for d = 1..r (x-d, x+d);
+    s_1..s_r (y+d); n_1..n_r (y-d).  The order is also the stencil's evaluation order."""
+    r = len(xw)
+    out = [cc]
+    for d in range(r):
+        out += [xw[d], xe[d]]
+    return np.array(out + list(ys) + list(yn), dtype=np.float32)
+
+
+# Radius-r weights: dyadic (multiples of 1/64), asymmetric, summing to exactly 1.
+STAR_SETS = {
+    2: star_weights(0.28125, [0.0625, 0.03125], [0.125, 0.0625], [0.125, 0.03125], [0.1875, 0.09375]),
+    3: star_weights(0.328125, [0.0625, 0.03125, 0.015625], [0.09375, 0.046875, 0.03125],
+                    [0.125, 0.0625, 0.015625], [0.125, 0.046875, 0.015625]),
+    4: star_weights(0.21875, [0.0625, 0.03125, 0.015625, 0.015625], [0.0625, 0.046875, 0.03125, 0.015625],
+                    [0.125, 0.0625, 0.03125, 0.015625], [0.125, 0.0625, 0.046875, 0.03125]),
+}
+
+
 def rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
