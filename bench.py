@@ -338,6 +338,29 @@ def main():
         torch.cuda.empty_cache()
         log("[bench] physical hotspot 2D: %.1f GCell/s" % g6)
 
+        # radius-2 star stencil (Eq. 1, Eq. 2 with rad = 2), 2D diffusion form, 16384^2, T = 1000
+        from workloads import STAR_WORKLOAD, STAR_SETS, star_field
+        w7 = STAR_WORKLOAD
+        x7 = torch.from_numpy(star_field(w7)).to(dev)
+        pl7 = S.StarPlan(w7["rad"], (w7["ny"], w7["nx"]))
+        wt7 = STAR_SETS[w7["rad"]]
+        pl7.run(x7, wt7, 16)
+        ms7 = time_call(lambda: pl7.run(x7, wt7, w7["T"]), stream, 2)
+        c7 = w7["nx"] * w7["ny"]
+        g7 = c7 * w7["T"] / (ms7 * 1e-3) / 1e9
+        t7 = pl7.tuning
+        pp7 = S.StarPlan(w7["rad"], (w7["ny"], w7["nx"]), {"variant": 1})
+        msp7 = time_call(lambda: pp7.run(x7, wt7, 20), stream, 1)
+        gp7 = c7 * 20 / (msp7 * 1e-3) / 1e9
+        extras["star2d_r2_16384"] = {"gcells": round(g7, 1), "ms_per_run": round(ms7, 2), "k": t7["k"],
+                                     "seg_len": t7["seg_len"], "gcells_one_step": round(gp7, 1),
+                                     "pct_single_pass_roofline": round(100 * g7 / (HBM_PEAK_GBS / 8), 1)}
+        pl7.close()
+        pp7.close()
+        del x7
+        torch.cuda.empty_cache()
+        log("[bench] radius-2 star 2D: %.1f GCell/s (one step per pass %.1f)" % (g7, gp7))
+
     if not args.quick:
         # 3D diffusion 512^3, 200 steps: temporal-blocked vs plain
         w3 = WORKLOADS["diffusion3d_512"]

@@ -27,7 +27,8 @@ STATUS = {0: "STENCIL_OK", -1: "STENCIL_ERR_INVALID_ARG", -2: "STENCIL_ERR_UNSUP
 
 EXPORTED = ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoint", "stencil_run_batched",
             "stencil_batch_destroy", "stencil_get_tuning", "stencil_destroy", "stencil_status_string",
-            "stencil_last_error", "stencil_model_estimate", "stencil_plan_model")
+            "stencil_last_error", "stencil_model_estimate", "stencil_plan_model", "stencil_create_star",
+            "stencil_run_star")
 
 
 class StencilError(RuntimeError):
@@ -104,9 +105,11 @@ def lib():
             L.stencil_last_error.restype = ctypes.c_char_p
             L.stencil_model_estimate.argtypes = [ctypes.POINTER(ModelParams), ctypes.POINTER(ModelResult)]
             L.stencil_plan_model.argtypes = [vp, i, ctypes.POINTER(PlanModel)]
+            L.stencil_create_star.argtypes = [ctypes.POINTER(vp), i, i, i, i, i, ctypes.POINTER(Tuning), vp]
+            L.stencil_run_star.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float), i]
             for name in ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoint",
                          "stencil_run_batched", "stencil_get_tuning", "stencil_model_estimate",
-                         "stencil_plan_model"):
+                         "stencil_plan_model", "stencil_create_star", "stencil_run_star"):
                 getattr(L, name).restype = i
             _lib = L
     return _lib
@@ -156,6 +159,20 @@ def stencil_create(form, ndim, nx, ny, nz, tuning=None, stream=None):
     _check(lib().stencil_create(ctypes.byref(h), int(form), int(ndim), int(nx), int(ny), int(nz),
                                 ctypes.byref(t) if t is not None else None, _stream(stream)))
     return h
+
+
+def stencil_create_star(ndim, rad, nx, ny, nz, tuning=None, stream=None):
+    h = ctypes.c_void_p()
+    t = make_tuning(tuning)
+    _check(lib().stencil_create_star(ctypes.byref(h), int(ndim), int(rad), int(nx), int(ny), int(nz),
+                                     ctypes.byref(t) if t is not None else None, _stream(stream)))
+    return h
+
+
+def stencil_run_star(plan, grid, weights, T):
+    import numpy as np
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    _check(lib().stencil_run_star(plan, _ptr(grid), w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(T)))
 
 
 def stencil_run(plan, grid, power, coeffs, T):
@@ -274,6 +291,40 @@ class Plan:
 
     def model(self, T):
         return stencil_plan_model(self.handle, T)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            stencil_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class StarPlan:
+    """A plan for the radius-r 2D star stencil of a (ny, nx) grid (stencil_create_star)."""
+
+    def __init__(self, rad, shape, tuning=None, stream=None):
+        if len(shape) != 2:
+            raise ValueError("the radius-r star stencil takes (ny, nx) grids")
+        self.rad = int(rad)
+        self.shape = (int(shape[0]), int(shape[1]))
+        self.handle = stencil_create_star(2, self.rad, self.shape[1], self.shape[0], 1, tuning, stream)
+
+    def run(self, grid, weights, T):
+        """weights: 1 + 4*rad values, cc; w_d, e_d (d = 1..rad); s_1..s_rad; n_1..n_rad."""
+        _check_tensor(grid, "grid")
+        if len(weights) != 1 + 4 * self.rad:
+            raise ValueError("weights must have 1 + 4*rad entries")
+        stencil_run_star(self.handle, grid, weights, T)
+        return grid
+
+    @property
+    def tuning(self):
+        return stencil_get_tuning(self.handle)
 
     def close(self):
         if self.handle is not None and self.handle.value:

@@ -4,10 +4,11 @@
 #include "tb2d.hpp"
 #include "tb3d.hpp"
 #include "plain.hpp"
+#include "star2d.hpp"
 
 // Kernel mode: forward diffusion, forward hotspot, transposed step (adjoint) without / with
 // grad_p accumulation, or the forward step of Table 2's physical Hotspot 2D formula (2D only).
-enum KMode { KM_DIFF = 0, KM_HOT = 1, KM_ADJ = 2, KM_ADJ_ACC = 3, KM_PHYS = 4 };
+enum KMode { KM_DIFF = 0, KM_HOT = 1, KM_ADJ = 2, KM_ADJ_ACC = 3, KM_PHYS = 4, KM_STAR = 5 };
 
 // Tile shapes of the temporal-blocked kernels.
 // 3D windows: 128 x 48 cells forward, 128 x 32 for the transposed (adjoint) step.  The
@@ -29,6 +30,10 @@ hipError_t launch_tb2d(int K, KMode m, bool full, const Tb2dArgs& a, hipStream_t
 hipError_t launch_tb3d(int K, KMode m, bool full, const Tb3dArgs& a, hipStream_t s);
 hipError_t launch_plain(KMode m, const PlainArgs& a, hipStream_t s);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
+// Radius-r 2D star kernels (star2d.hpp): instantiated K values (ascending) for radius R, and
+// the launch of one pass.
+int star_instantiated(int R, const int** ks);
+hipError_t launch_star2d(int R, int K, const Star2dArgs& a, hipStream_t s);
 hipError_t launch_fill_int(int* p, size_t n, int v, hipStream_t s);
 
 // Per-mode launchers (one translation unit each).

@@ -67,6 +67,18 @@ Geom2D geom2d(int K, int nx, int ny, int seg) {
   return g;
 }
 
+Geom2D geom_star(int R, int K, int nx, int ny, int seg) {
+  Geom2D g;
+  g.K = K;
+  const int W = 64 * kTb2dV;
+  g.kr = round_up(R * K, 4);
+  g.cs = floor_to(W - R * K - g.kr, 4);
+  g.ntx = ceil_div(nx, g.cs);
+  g.seg = std::max(1, std::min(seg, ny));
+  g.nseg = ceil_div(ny, g.seg);
+  return g;
+}
+
 Geom3D geom3d(int K, bool adj, int nx, int ny, int nz, int segz) {
   Geom3D g;
   g.K = K;
@@ -280,6 +292,15 @@ KMode form_mode(stencil_form_t f) {
 }
 KMode fwd_mode(const stencil_plan_s* p) { return form_mode(p->form); }
 
+// Smallest instantiated K >= k of the radius-R star kernels (the largest if none is).
+int star_k_for(int R, int k) {
+  const int* ks;
+  const int n = star_instantiated(R, &ks);
+  for (int i = 0; i < n; ++i)
+    if (ks[i] >= k) return ks[i];
+  return ks[n - 1];
+}
+
 // Smallest instantiated K >= k.
 int inst_k_for(int ndim, KMode m, int k) {
   const int* ks;
@@ -307,8 +328,20 @@ void interior_rect2d(const Geom2D& g, int nx, int ny, int keff, int* x0, int* x1
 }
 
 // One pass of keff fused steps from src to dst.
+hipError_t run_star_pass(const stencil_plan_s* p, int K, int keff, const float* src, float* dst) {
+  const Geom2D g = geom_star(p->rad, K, p->nx, p->ny, p->tuning.seg_len);
+  Star2dArgs a;
+  a.src = src; a.dst = dst;
+  a.nx = p->nx; a.ny = p->ny; a.keff = keff;
+  a.cs = g.cs; a.kr = g.kr; a.ntx = g.ntx; a.seg = g.seg; a.nseg = g.nseg;
+  a.aligned = ((p->nx & 3) == 0) && aligned16(src) && aligned16(dst) ? 1 : 0;
+  a.cf = p->star_cf;
+  return launch_star2d(p->rad, K, a, p->stream);
+}
+
 hipError_t run_pass(const stencil_plan_s* p, KMode m, int K, int keff, const float* src, float* dst,
                     const float* power, float* gp, const DevCoef& cf) {
+  if (m == KM_STAR) return run_star_pass(p, K, keff, src, dst);
   const bool full = (keff == K);
   if (p->ndim == 2) {
     const Geom2D g = geom2d(K, p->nx, p->ny, p->tuning.seg_len);
@@ -412,7 +445,8 @@ stencil_status_t run_sequence(stencil_plan_s* p, KMode m, bool plain, int K, con
     } else {
       // a pass that fuses fewer steps than K runs on the smallest instantiation that holds
       // them: surplus levels would only forward their input at the full pass's cost
-      const int Ki = steps[i] < K ? inst_k_for(p->ndim, m, steps[i]) : K;
+      const int Ki = steps[i] < K ? (m == KM_STAR ? star_k_for(p->rad, steps[i]) : inst_k_for(p->ndim, m, steps[i]))
+                                  : K;
       e = run_pass(p, m, Ki, steps[i], src, dst, power, gp, cf);
     }
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -685,6 +719,88 @@ stencil_status_t check_plan(stencil_plan_t plan) {
   return STENCIL_OK;
 }
 
+// Segment length of a radius-R star pass: the fewest row segments that give about two waves
+// per SIMD in full rounds, as pick_seg2d does for the radius-1 kernels.
+int pick_seg_star(int R, int K, int nx, int ny) {
+  const DeviceInfo& d = device_info();
+  const Geom2D g0 = geom_star(R, K, nx, ny, ny);
+  const long slots = (long)d.cus * 8;
+  int best_seg = ny;
+  double best = 1e300;
+  for (int nseg = 1; nseg <= std::max(1, ny / std::max(1, 2 * R * K)); ++nseg) {
+    const int seg = ceil_div(ny, nseg);
+    const double tiles = (double)g0.ntx * ceil_div(ny, seg);
+    const double cost = std::ceil(tiles / slots) * (seg + 2.0 * R * K + 2.0);
+    if (cost < best * 0.999) {
+      best = cost;
+      best_seg = seg;
+    }
+    if (tiles > 64.0 * slots) break;
+  }
+  return best_seg;
+}
+
+// Blocking of a radius-R star plan: every instantiated K, each on its own segment length, is
+// timed on scratch memory (three rounds of at least ~12 ms after a warm-up) and the fastest
+// kept; grids below 2^16 cells take K = 4 untimed.
+void star_tune(stencil_plan_s* p) {
+  const int* ks;
+  const int nk = star_instantiated(p->rad, &ks);
+  int bestK = ks[std::min(2, nk - 1)];
+  const bool timed = !env_flag("STENCIL_MODEL_ONLY") && p->cells >= (size_t)1 << 16;
+  float* tmp = nullptr;
+  if (timed && hipMalloc(&tmp, p->cells * sizeof(float)) == hipSuccess) {
+    launch_fill(tmp, p->cells, 0.5f, p->stream);
+    launch_fill(p->scratch, p->cells, 0.5f, p->stream);
+    StarCoef c{};
+    c.c0 = 0.5f;
+    for (int d = 0; d < p->rad; ++d) c.w[d] = c.e[d] = c.s[d] = c.n[d] = 0.125f / p->rad;
+    p->star_cf = c;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    auto time_k = [&](int K) -> double {
+      stencil_plan_s q = *p;
+      q.tuning.k = K;
+      q.tuning.seg_len = pick_seg_star(p->rad, K, p->nx, p->ny);
+      const double per_pass = (double)K * (double)p->cells;
+      const int reps = std::max(2, std::min(192, (int)std::ceil(2.0e10 / per_pass)));
+      run_star_pass(&q, K, K, tmp, p->scratch);
+      hipEventRecord(e0, p->stream);
+      for (int r = 0; r < reps; ++r) {
+        const bool even = (r % 2) == 0;
+        run_star_pass(&q, K, K, even ? p->scratch : tmp, even ? tmp : p->scratch);
+      }
+      hipEventRecord(e1, p->stream);
+      hipEventSynchronize(e1);
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      return ms > 0 ? reps * per_pass / (ms * 1e-3) : 0.0;
+    };
+    for (int w = 0; w < 2; ++w) time_k(ks[nk - 1]);
+    std::vector<double> rate(nk, 0.0);
+    for (int round = 0; round < 3; ++round)
+      for (int i = 0; i < nk; ++i) rate[i] = std::max(rate[i], time_k(ks[i]));
+    double best = 0;
+    for (int i = 0; i < nk; ++i) {
+      if (log_enabled())
+        std::fprintf(stderr, "[stencil] tune star r=%d K=%d measured=%.1f GCell/s\n", p->rad, ks[i], rate[i] * 1e-9);
+      if (rate[i] > best) {
+        best = rate[i];
+        bestK = ks[i];
+      }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipStreamSynchronize(p->stream);
+    hipFree(tmp);
+  }
+  hipGetLastError();
+  p->tuning.variant = 2;
+  p->tuning.k = bestK;
+  p->tuning.seg_len = pick_seg_star(p->rad, bestK, p->nx, p->ny);
+}
+
 stencil_status_t set_device(const stencil_plan_s* p) {
   hipError_t e = hipSetDevice(p->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -909,6 +1025,7 @@ stencil_status_t stencil_get_tuning(stencil_plan_t plan, stencil_tuning_t* out) 
 stencil_status_t stencil_plan_model(stencil_plan_t p, int T, stencil_plan_model_t* out) {
   if (!p || !out) return fail(STENCIL_ERR_INVALID_ARG, "NULL argument");
   if (T < 0) return fail(STENCIL_ERR_INVALID_ARG, "T must be >= 0");
+  if (p->star) return fail(STENCIL_ERR_UNSUPPORTED, "the time model covers the radius-1 kernels");
   const KMode m = fwd_mode(p);
   const bool hot = p->form != STENCIL_DIFFUSION;
   int K;
@@ -963,6 +1080,7 @@ stencil_status_t stencil_run(stencil_plan_t plan, float* grid, const float* powe
                              int T) {
   stencil_status_t st = check_plan(plan);
   if (st != STENCIL_OK) return st;
+  if (plan->star) return fail(STENCIL_ERR_INVALID_ARG, "a radius-r star plan runs through stencil_run_star");
   return forward(plan, grid, power, coeffs, T, 0, false);
 }
 
@@ -970,6 +1088,7 @@ stencil_status_t stencil_run_ckpt(stencil_plan_t plan, float* grid, const float*
                                   const stencil_coeffs_t* coeffs, int T, int ckpt_every) {
   stencil_status_t st = check_plan(plan);
   if (st != STENCIL_OK) return st;
+  if (plan->star) return fail(STENCIL_ERR_UNSUPPORTED, "checkpointed runs are not offered for radius-r star plans");
   if (ckpt_every < 0) return fail(STENCIL_ERR_INVALID_ARG, "ckpt_every must be >= 0");
   return forward(plan, grid, power, coeffs, T, ckpt_every, true);
 }
@@ -981,6 +1100,7 @@ stencil_status_t stencil_adjoint(stencil_plan_t p, const float* cot, const float
   if (st != STENCIL_OK) return st;
   if (p->form == STENCIL_HOTSPOT_PHYS)
     return fail(STENCIL_ERR_UNSUPPORTED, "no adjoint for the physical hotspot form (use the weighted form)");
+  if (p->star) return fail(STENCIL_ERR_UNSUPPORTED, "no adjoint for radius-r star plans");
   if (!cot || !grad_x0) return fail(STENCIL_ERR_INVALID_ARG, "cotangent and grad_x0 are required");
   if (!coeffs) return fail(STENCIL_ERR_INVALID_ARG, "coeffs is NULL");
   if (T < 0) return fail(STENCIL_ERR_INVALID_ARG, "T must be >= 0");
@@ -1106,6 +1226,75 @@ stencil_status_t stencil_model_estimate(const stencil_model_params_t* q, stencil
   r->run_time_s = passes * (r->t_read + r->t_write) * q->size_cell / (1e9 * r->th_mem_gbs);
   r->throughput_gbs = r->run_time_s > 0 ? nacc * size_input * q->size_cell * q->iter / (1e9 * r->run_time_s) : 0.0;
   return STENCIL_OK;
+}
+
+stencil_status_t stencil_create_star(stencil_plan_t* out, int ndim, int rad, int nx, int ny, int nz,
+                                     const stencil_tuning_t* tuning, void* hip_stream) {
+  if (!out) return fail(STENCIL_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (ndim != 2) return fail(ndim == 3 ? STENCIL_ERR_UNSUPPORTED : STENCIL_ERR_INVALID_ARG,
+                             "radius-r star stencils are offered in 2D");
+  if (rad < 1) return fail(STENCIL_ERR_INVALID_ARG, "rad must be >= 1");
+  if (rad > kStarMaxR) return fail(STENCIL_ERR_UNSUPPORTED, "rad is at most 4 (the x-neighbours of a lane's 4 cells)");
+  stencil_tuning_t t{};
+  if (tuning) t = *tuning;
+  if (t.variant < 0 || t.variant > 2 || t.k < 0 || t.vec < 0 || t.bsize_x < 0 || t.bsize_y < 0 || t.seg_len < 0)
+    return fail(STENCIL_ERR_INVALID_ARG, "tuning fields must be >= 0 (variant 0..2)");
+  if (t.vec != 0 && t.vec != kTb2dV) return fail(STENCIL_ERR_UNSUPPORTED, "vec is fixed at 4");
+  // the plan itself (scratch, streams) without the radius-1 tuner: its blocking is set below
+  stencil_tuning_t fixed{2, 1, 0, 0, 0, 1};
+  stencil_status_t st = stencil_create(out, STENCIL_DIFFUSION, ndim, nx, ny, nz, &fixed, hip_stream);
+  if (st != STENCIL_OK) return st;
+  stencil_plan_s* p = *out;
+  p->star = true;
+  p->rad = rad;
+  const int* ks;
+  const int nk = star_instantiated(rad, &ks);
+  p->tuning = t;
+  if (t.variant == 1) {
+    p->tuning.k = 1;
+    p->tuning.seg_len = t.seg_len > 0 ? t.seg_len : pick_seg_star(rad, 1, nx, ny);
+  } else if (t.k > 0) {
+    p->tuning.variant = 2;
+    p->tuning.k = std::min(t.k, ks[nk - 1]);
+    p->tuning.seg_len = t.seg_len > 0 ? t.seg_len : pick_seg_star(rad, star_k_for(rad, p->tuning.k), nx, ny);
+  } else {
+    star_tune(p);
+  }
+  p->tuning.vec = kTb2dV;
+  p->tuning.bsize_x = 64 * kTb2dV;
+  if (log_enabled())
+    std::fprintf(stderr, "[stencil] star plan r=%d %dx%d -> k=%d seg=%d\n", rad, nx, ny, p->tuning.k, p->tuning.seg_len);
+  return STENCIL_OK;
+}
+
+stencil_status_t stencil_run_star(stencil_plan_t p, float* grid, const float* weights, int T) {
+  stencil_status_t st = check_plan(p);
+  if (st != STENCIL_OK) return st;
+  if (!p->star) return fail(STENCIL_ERR_INVALID_ARG, "not a radius-r star plan (stencil_create_star)");
+  if (!grid || !weights) return fail(STENCIL_ERR_INVALID_ARG, "grid and weights are required");
+  if (T < 0) return fail(STENCIL_ERR_INVALID_ARG, "T must be >= 0");
+  if (reinterpret_cast<uintptr_t>(grid) & 3) return fail(STENCIL_ERR_INVALID_ARG, "grid must be 4-byte aligned");
+  const int R = p->rad;
+  for (int i = 0; i < 1 + 4 * R; ++i)
+    if (!std::isfinite(weights[i])) return fail(STENCIL_ERR_INVALID_ARG, "weights must be finite");
+  StarCoef c{};
+  c.c0 = weights[0];
+  for (int d = 1; d <= R; ++d) {
+    c.w[d - 1] = weights[2 * d - 1];
+    c.e[d - 1] = weights[2 * d];
+    c.s[d - 1] = weights[2 * R + d];
+    c.n[d - 1] = weights[3 * R + d];
+  }
+  p->star_cf = c;
+  st = set_device(p);
+  if (st != STENCIL_OK) return st;
+  if (hipError_t e = poison_scratch(p); e != hipSuccess) return hip_fail(e, "poison fill");
+  const int K = star_k_for(R, std::max(1, p->tuning.k));
+  const int kpass = std::min(K, std::max(1, p->tuning.k));
+  int counter = 0;
+  return run_sequence(p, KM_STAR, false, K, split_steps(T, kpass), grid, grid, p->scratch, nullptr, nullptr, DevCoef{},
+                      &counter);
 }
 
 }  // extern "C"

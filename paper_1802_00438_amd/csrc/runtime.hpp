@@ -33,6 +33,8 @@ struct Geom3D {
   int ax = 0, ay = 0, fx = 0, fy = 0;  // edge-flush tiling per axis (see Tb3dArgs)
 };
 Geom2D geom2d(int K, int nx, int ny, int seg);
+// Geometry of a radius-R star pass: halo R*K per side (left halo rounded up to 4).
+Geom2D geom_star(int R, int K, int nx, int ny, int seg);
 // Memory and arithmetic parts of a modelled time, summed over the passes (seconds).
 struct ModelParts {
   double mem = 0.0, alu = 0.0;
@@ -60,6 +62,9 @@ bool coeffs_finite(const stencil_coeffs_t& c);
 struct stencil_plan_s {
   stencil_form_t form;
   int ndim, nx, ny, nz;
+  int rad = 1;           // > 0 with star = true: a radius-rad star plan (stencil_create_star)
+  bool star = false;
+  StarCoef star_cf{};    // weights of the current stencil_run_star call
   size_t cells;
   hipStream_t stream;
   int device;

@@ -75,6 +75,8 @@ def test_calls_on_null_plan_are_rejected():
     assert L.stencil_get_tuning(None, None) == -1
     m = S.PlanModel()
     assert L.stencil_plan_model(None, 10, ctypes.byref(m)) == -1
+    w = (ctypes.c_float * 9)(*([0.5] + [0.0625] * 8))
+    assert L.stencil_run_star(None, None, w, 1) == -1
     L.stencil_destroy(None)        # no-op
     L.stencil_batch_destroy(None)  # no-op
 
@@ -166,3 +168,15 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(mod, "_lib", None)
     with pytest.raises(ImportError):
         mod.lib()
+
+
+def test_create_star_rejects_bad_arguments_before_device_work():
+    L = S.lib()
+    h = ctypes.c_void_p(1234)
+    assert L.stencil_create_star(ctypes.byref(h), 3, 2, 8, 8, 8, None, None) == -2  # 3D: unsupported
+    assert h.value is None
+    assert L.stencil_create_star(ctypes.byref(h), 2, 0, 8, 8, 1, None, None) == -1  # rad < 1
+    assert L.stencil_create_star(ctypes.byref(h), 2, 5, 8, 8, 1, None, None) == -2  # rad > 4
+    t = S.Tuning(variant=3)
+    assert L.stencil_create_star(ctypes.byref(h), 2, 2, 8, 8, 1, ctypes.byref(t), None) == -1
+    assert L.stencil_create_star(None, 2, 2, 8, 8, 1, None, None) == -1

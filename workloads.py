@@ -165,6 +165,15 @@ WORKLOADS = {
 }
 BATCH_SEED = 4000
 
+# Radius-r star stencil workload (Eq. 1, Eq. 2 with rad = 2): 2D diffusion form, weights
+# STAR_SETS[2], the large 2D grid and step count of the paper's 2D runs; listed seventh, so
+# its seed is 7000.
+STAR_WORKLOAD = {"name": "star2d_r2_16384", "rad": 2, "nx": 16384, "ny": 16384, "T": 1000, "seed": 7000}
+
+
+def star_field(wl=STAR_WORKLOAD) -> np.ndarray:
+    return uniform((wl["ny"], wl["nx"]), 0.0, 1.0, wl["seed"])
+
 
 @dataclass
 class BatchGrid:
