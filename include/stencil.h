@@ -49,7 +49,9 @@ typedef enum {
  *     out = c + sdc*(p + ((n + s) - 2c)*Ry_1 + ((e + w) - 2c)*Rx_1 + (TEMP_AMB - c)*Rz_1),
  * every operation rounded in FP32 in that order, each "x + y*z" as one FMA and the final
  * c + sdc*(...) as fma(sdc, ..., c).  A field at TEMP_AMB with zero power is then an exact
- * fixed point.  It has no adjoint and no batched launch (both return UNSUPPORTED). */
+ * fixed point.  Its linear part is symmetric, so stencil_adjoint applies the same formula
+ * with no power and TEMP_AMB = 0 as the transposed step.  It has no batched launch
+ * (UNSUPPORTED). */
 typedef enum { STENCIL_DIFFUSION = 0, STENCIL_HOTSPOT = 1, STENCIL_HOTSPOT_PHYS = 2 } stencil_form_t;
 
 /* Stencil weights (Table 2).  cb, ca are ignored for 2D; cp, c_amb, t_amb for diffusion.

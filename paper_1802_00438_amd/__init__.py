@@ -356,15 +356,17 @@ def _stencil_fn():
     import torch
 
     class StencilFn(torch.autograd.Function):
-        """x_T = T steps of the stencil applied to x0 (hotspot when power is given).
+        """x_T = T steps of the stencil applied to x0 (hotspot when power is given; form may
+        name HOTSPOT_PHYS for Table 2's physical Hotspot 2D formula).
 
         backward returns dJ/dx0 and dJ/dpower from the library's adjoint kernels; forward keeps
         checkpoints every ckpt_every steps (0 = sqrt(T)), and recompute=1 re-runs and checks them
         during backward."""
 
         @staticmethod
-        def forward(ctx, x0, power, coeffs, T, ckpt_every=0, recompute=0, tuning=None):
-            form = HOTSPOT if power is not None else DIFFUSION
+        def forward(ctx, x0, power, coeffs, T, ckpt_every=0, recompute=0, tuning=None, form=None):
+            if form is None:
+                form = HOTSPOT if power is not None else DIFFUSION
             plan = Plan(form, x0.shape, tuning)
             x = x0.detach().clone()
             plan.run_ckpt(x, coeffs, T, ckpt_every, power)
@@ -384,7 +386,7 @@ def _stencil_fn():
             gp = torch.empty_like(g) if ctx.has_power else None
             ctx.plan.adjoint(g, ctx.coeffs, ctx.T, gx, gp, power if ctx.has_power else None, ctx.recompute)
             ctx.plan.close()
-            return gx, gp, None, None, None, None, None
+            return gx, gp, None, None, None, None, None, None
 
     return StencilFn
 

@@ -27,7 +27,7 @@ int tb_instantiated(int ndim, KMode m, const int** ks) {
   if (ndim == 2) {
     if (m == KM_DIFF) { *ks = kK2D; return 6; }
     if (m == KM_HOT || m == KM_PHYS) { *ks = kK2H; return 4; }
-    *ks = kK2A; return 3;
+    *ks = kK2A; return 3;  // transposed steps
   }
   if (m == KM_DIFF) { *ks = kK3D; return 6; }
   if (m == KM_HOT) { *ks = kK3H; return 4; }
@@ -47,6 +47,9 @@ hipError_t launch_tb2d(int K, KMode m, bool full, const Tb2dArgs& a, hipStream_t
     case KM_ADJ: return launch_tb2d_adj(K, false, full, a, s);
     case KM_ADJ_ACC: return launch_tb2d_adj(K, true, full, a, s);
     case KM_PHYS: return launch_tb2d_phys(K, full, a, s);
+    case KM_PHYS_ADJ: return launch_tb2d_phys_adj(K, false, full, a, s);
+    case KM_PHYS_ADJ_ACC: return launch_tb2d_phys_adj(K, true, full, a, s);
+    case KM_STAR: break;
   }
   return hipErrorInvalidValue;
 }
@@ -57,7 +60,10 @@ hipError_t launch_tb3d(int K, KMode m, bool full, const Tb3dArgs& a, hipStream_t
     case KM_HOT: return launch_tb3d_hot(K, full, a, s);
     case KM_ADJ: return launch_tb3d_adj(K, false, full, a, s);
     case KM_ADJ_ACC: return launch_tb3d_adj(K, true, full, a, s);
-    case KM_PHYS: break;  // 2D only
+    case KM_PHYS:
+    case KM_PHYS_ADJ:
+    case KM_PHYS_ADJ_ACC:
+    case KM_STAR: break;  // 2D only
   }
   return hipErrorInvalidValue;
 }
@@ -73,6 +79,15 @@ hipError_t launch_plain(KMode m, const PlainArgs& a, hipStream_t s) {
       if (a.ndim != 2) return hipErrorInvalidValue;
       hipLaunchKernelGGL((plain_kernel<true, false, false, true>), dim3(nb), dim3(256), 0, s, a);
       break;
+    case KM_PHYS_ADJ:
+      if (a.ndim != 2) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((plain_kernel<false, true, false, true>), dim3(nb), dim3(256), 0, s, a);
+      break;
+    case KM_PHYS_ADJ_ACC:
+      if (a.ndim != 2) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((plain_kernel<false, true, true, true>), dim3(nb), dim3(256), 0, s, a);
+      break;
+    case KM_STAR: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

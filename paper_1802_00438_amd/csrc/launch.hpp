@@ -8,7 +8,10 @@
 
 // Kernel mode: forward diffusion, forward hotspot, transposed step (adjoint) without / with
 // grad_p accumulation, or the forward step of Table 2's physical Hotspot 2D formula (2D only).
-enum KMode { KM_DIFF = 0, KM_HOT = 1, KM_ADJ = 2, KM_ADJ_ACC = 3, KM_PHYS = 4, KM_STAR = 5 };
+enum KMode {
+  KM_DIFF = 0, KM_HOT = 1, KM_ADJ = 2, KM_ADJ_ACC = 3, KM_PHYS = 4, KM_STAR = 5,
+  KM_PHYS_ADJ = 6, KM_PHYS_ADJ_ACC = 7  // transposed step of the physical form, without / with grad_p
+};
 
 // Tile shapes of the temporal-blocked kernels.
 // 3D windows: 128 x 48 cells forward, 128 x 32 for the transposed (adjoint) step.  The
@@ -41,6 +44,7 @@ hipError_t launch_tb2d_diff(int K, bool full, const Tb2dArgs& a, hipStream_t s);
 hipError_t launch_tb2d_hot(int K, bool full, const Tb2dArgs& a, hipStream_t s);
 hipError_t launch_tb2d_adj(int K, bool acc, bool full, const Tb2dArgs& a, hipStream_t s);
 hipError_t launch_tb2d_phys(int K, bool full, const Tb2dArgs& a, hipStream_t s);
+hipError_t launch_tb2d_phys_adj(int K, bool acc, bool full, const Tb2dArgs& a, hipStream_t s);
 hipError_t launch_tb3d_diff(int K, bool full, const Tb3dArgs& a, hipStream_t s);
 hipError_t launch_tb3d_hot(int K, bool full, const Tb3dArgs& a, hipStream_t s);
 hipError_t launch_tb3d_adj(int K, bool acc, bool full, const Tb3dArgs& a, hipStream_t s);

@@ -38,10 +38,11 @@ __device__ __forceinline__ void plain_ld4(const float* r, int x0, int nx, bool v
 }
 
 // PHYS (2D only): Table 2's physical Hotspot 2D formula in its printed order (see DevCoef
-// for where its parameters travel).
+// for where its parameters travel); with ADJ, its symmetric linear part (no power, TEMP_AMB
+// = 0) as the transposed step.
 template <bool HOT, bool ADJ, bool ACC, bool PHYS = false>
 __global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
-  static_assert(!PHYS || (HOT && !ADJ && !ACC), "the physical form is a forward hotspot step");
+  static_assert(!PHYS || (HOT && !ADJ && !ACC) || (!HOT && ADJ), "physical form: forward hotspot or transposed step");
   const int chunk = blockIdx.x % a.chunks;
   const int strip = blockIdx.x / a.chunks;  // y-strips (2D) or (y, z-strip) pairs (3D)
   const int x0 = chunk * 1024 + threadIdx.x * 4;
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
         const float dy = __builtin_fmaf(-2.0f, c, yn + ys);  // (n + s) - 2c, one rounding each
         const float dx = __builtin_fmaf(-2.0f, c, xp + xm);  // (e + w) - 2c
         const float dz = a.cf.kamb - c;                      // TEMP_AMB - c
-        acc = __builtin_fmaf(dy, a.cf.wy_m, p4[v]);
+        acc = __builtin_fmaf(dy, a.cf.wy_m, (HOT && !ADJ) ? p4[v] : 0.0f);
         acc = __builtin_fmaf(dx, a.cf.wx_m, acc);
         acc = __builtin_fmaf(dz, a.cf.wz_m, acc);
         acc = __builtin_fmaf(a.cf.cp, acc, c);

@@ -1098,8 +1098,6 @@ stencil_status_t stencil_adjoint(stencil_plan_t p, const float* cot, const float
                                  int recompute) {
   stencil_status_t st = check_plan(p);
   if (st != STENCIL_OK) return st;
-  if (p->form == STENCIL_HOTSPOT_PHYS)
-    return fail(STENCIL_ERR_UNSUPPORTED, "no adjoint for the physical hotspot form (use the weighted form)");
   if (p->star) return fail(STENCIL_ERR_UNSUPPORTED, "no adjoint for radius-r star plans");
   if (!cot || !grad_x0) return fail(STENCIL_ERR_INVALID_ARG, "cotangent and grad_x0 are required");
   if (!coeffs) return fail(STENCIL_ERR_INVALID_ARG, "coeffs is NULL");
@@ -1111,15 +1109,23 @@ stencil_status_t stencil_adjoint(stencil_plan_t p, const float* cot, const float
   if (recompute) {
     if (p->ckpt_T != T || p->ckpts.empty())
       return fail(STENCIL_ERR_INVALID_ARG, "recompute needs checkpoints of a stencil_run_ckpt with the same T");
-    if (p->form == STENCIL_HOTSPOT && !power) return fail(STENCIL_ERR_INVALID_ARG, "recompute of hotspot needs power");
+    if (p->form != STENCIL_DIFFUSION && !power) return fail(STENCIL_ERR_INVALID_ARG, "recompute of hotspot needs power");
   }
   st = set_device(p);
   if (st != STENCIL_OK) return st;
   if (hipError_t e = poison_scratch(p); e != hipSuccess) return hip_fail(e, "poison fill");
-  const bool hot = p->form == STENCIL_HOTSPOT;
+  const bool hot = p->form != STENCIL_DIFFUSION;
+  const bool phys = p->form == STENCIL_HOTSPOT_PHYS;
   float* gp = hot ? grad_power : nullptr;
-  const KMode m = gp ? KM_ADJ_ACC : KM_ADJ;
-  const DevCoef cf = dev_coef(*coeffs, true);
+  // The physical form's linear part is symmetric: its transposed step is the same formula
+  // with no power and an ambient temperature of 0.
+  KMode m = gp ? KM_ADJ_ACC : KM_ADJ;
+  DevCoef cf = dev_coef(*coeffs, true);
+  if (phys) {
+    m = gp ? KM_PHYS_ADJ_ACC : KM_PHYS_ADJ;
+    cf = dev_coef(*coeffs, false, true);
+    cf.kamb = 0.0f;
+  }
   if (gp) {
     hipError_t e = launch_fill(gp, p->cells, 0.0f, p->stream);
     if (e != hipSuccess) return hip_fail(e, "fill");
@@ -1152,7 +1158,7 @@ stencil_status_t stencil_adjoint(stencil_plan_t p, const float* cot, const float
   const int ce = p->ckpt_every;
   const int nck = (int)p->ckpts.size();
   const KMode fm = fwd_mode(p);
-  const DevCoef fcf = dev_coef(*coeffs, false);
+  const DevCoef fcf = dev_coef(*coeffs, false, phys);
   int Kf;
   bool plainf;
   resolve_k(p, fm, &Kf, &plainf);

@@ -9,9 +9,15 @@
 //     16-byte access per row).  x-neighbours at distance d <= 4 are in the lane itself or,
 //     for the first / last d cells, in the lower / upper lane: R DPP moves per side per row.
 //   * Level s (1..K) keeps the last 2R+1 rows of level s-1 in registers.  When level s-1
-//     produces row i, level s computes row i+R in one go (centre, x-terms, then the R rows
-//     below and the R rows above), so level s trails level s-1 by R rows.  The row loop is
-//     unrolled by 2R+1, which makes every window slot a compile-time register set.
+//     produces row i, level s computes row i+R (centre, x-terms, then the R rows below and the
+//     R rows above), so level s trails level s-1 by R rows.  The row loop is unrolled by 2R+1,
+//     which makes every window slot a compile-time register set.
+//   * Only the last term (the row R above, which level s-1 produces in the same step) depends
+//     on this step's work of the level below.  Away from the first and last grid rows, each
+//     step therefore runs in two phases: every level sums all its other terms (independent
+//     work across levels) into the window slot its new row will occupy, which is free; then,
+//     bottom level first, each adds the last term.  Tiles near the first or last row, whose
+//     row clamp may substitute that term, evaluate each level in one go.
 //   * Clamp (Section 5.1 at every distance): an index beyond the grid is the nearest
 //     boundary index.  For a cell at x, the clamped neighbour at distance d is its neighbour at
 //     distance min(d, x) (left) or min(d, nx-1-x) (right), so edge tiles select, per
@@ -44,7 +50,9 @@ struct Star2dArgs {
   StarCoef cf;
 };
 
-template <int R, int K>
+// FULL: the pass fuses all K steps (keff == K), so no level needs the run-time keff test that
+// would split the unrolled step into one basic block per level.
+template <int R, int K, bool FULL>
 struct Star2dTile {
   static_assert(R >= 1 && R <= kStarMaxR, "radius");
   static constexpr int V = 4;
@@ -87,9 +95,10 @@ struct Star2dTile {
     }
   }
 
-  // Row j of level s from the window P of level s-1, whose newest row (slot `nw`) is row
-  // j - R.  The row that arrived u steps ago sits in slot (nw - u) mod NR and is row j - R + u.
-  template <bool XE, bool YE, int NW>
+  // Row j of level s from the window P of level s-1, whose newest row (slot NW) is row j - R.
+  // The row that arrived u steps ago sits in slot (NW - u) mod NR and is row j - R + u.  With
+  // LAST = false the final term (n_R times the newest row) is left out.
+  template <bool XE, bool YE, int NW, bool LAST = true>
   __device__ __forceinline__ void level_row(const float (&P)[NR][V], int j, float (&o)[V]) const {
     constexpr int CS = (NW - R + 2 * NR) % NR;  // centre slot (u = R)
     const float(&C)[V] = P[CS];
@@ -127,8 +136,6 @@ struct Star2dTile {
     }
 #pragma unroll
     for (int d = 1; d <= R; ++d) {
-      constexpr int dummy = 0;
-      (void)dummy;
       const int ss = (NW - (R + d) + 2 * NR) % NR;
       const int sn = (NW - (R - d) + 2 * NR) % NR;
       bool okS = true, okN = true;
@@ -153,7 +160,7 @@ struct Star2dTile {
 #pragma unroll
       for (int d = 1; d <= R; ++d) acc = __builtin_fmaf(a.cf.s[d - 1], ys[d][v], acc);
 #pragma unroll
-      for (int d = 1; d <= R; ++d) acc = __builtin_fmaf(a.cf.n[d - 1], yn[d][v], acc);
+      for (int d = 1; d <= (LAST ? R : R - 1); ++d) acc = __builtin_fmaf(a.cf.n[d - 1], yn[d][v], acc);
       o[v] = acc;
     }
   }
@@ -164,11 +171,53 @@ struct Star2dTile {
 #pragma unroll
     for (int v = 0; v < V; ++v) win[0][T][v] = Lb[v];
     load_row<VEC>(r - 1, Lb);
+    if constexpr (!YE) {
+      constexpr int CS = (T - R + 2 * NR) % NR;
+      // phase 1, top level first: all terms but the last, into slot T of the level's own
+      // window (its previous occupant, 2R+1 rows old, is dead)
+      float top[V];
+#pragma unroll
+      for (int s = K; s >= 1; --s) {
+        float o[V];
+        if (FULL || s <= a.keff) {
+          level_row<XE, false, T, false>(win[s - 1], r + s * R, o);
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) o[v] = 0.0f;  // surplus level: set in phase 2
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          if (s == K) top[v] = o[v];
+          else win[s][T][v] = o[v];
+        }
+      }
+      // phase 2, bottom level first: the last term, from the row level s-1 has just made
+#pragma unroll
+      for (int s = 1; s <= K; ++s) {
+        const int j = r + s * R;
+        float o[V];
+        if (FULL || s <= a.keff) {
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+            o[v] = __builtin_fmaf(a.cf.n[R - 1], win[s - 1][T][v], s == K ? top[v] : win[s][T][v]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) o[v] = win[s - 1][CS][v];  // surplus level: forward its input
+        }
+        if (s < K) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) win[s][T][v] = o[v];
+        } else if (j >= y0 && j < y1) {
+          store_row<VEC>(j, o, XE);
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int s = 1; s <= K; ++s) {
       const int j = r + s * R;
       float o[V];
-      if (s <= a.keff) {
+      if (FULL || s <= a.keff) {
         level_row<XE, YE, T>(win[s - 1], j, o);
       } else {
         // levels past keff forward their input row (the centre of the window below)
@@ -232,9 +281,9 @@ struct Star2dTile {
   }
 };
 
-template <int R, int K>
+template <int R, int K, bool FULL>
 __global__ __launch_bounds__(64) void star2d_kernel(Star2dArgs a) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  Star2dTile<R, K> t(a, threadIdx.x);
+  Star2dTile<R, K, FULL> t(a, threadIdx.x);
   t.process(tile);
 }

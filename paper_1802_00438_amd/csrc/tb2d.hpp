@@ -38,7 +38,9 @@
 //     + (TEMP_AMB-c)*Rz_1), each operation rounded in that order.  Its first operation needs
 //     the oldest and the newest row together, so phase 1 keeps the oldest row in place of a
 //     partial sum (same registers) and phase 2 evaluates the whole formula; the ring holds the
-//     raw power rows.
+//     raw power rows.  Its linear part has equal weights on both sides of each axis, so with
+//     the clamp it is a symmetric matrix: the transposed step (ADJ) is the same formula with
+//     no power and TEMP_AMB = 0.
 #pragma once
 #include "device_common.hpp"
 
@@ -89,7 +91,7 @@ __device__ __forceinline__ int tb2d_part_tile(const Tb2dArgs& a, int i) {
 template <int K, int V, bool HOT, bool ADJ, bool ACC, bool FULL, int D = 2, bool PHYS = false>
 struct Tb2dTile {
   static_assert(V == 4 || V == 8, "V");
-  static_assert(!PHYS || (HOT && !ADJ && !ACC), "the physical form is a forward hotspot step");
+  static_assert(!PHYS || (HOT && !ADJ && !ACC) || (!HOT && ADJ), "physical form: forward hotspot or transposed step");
   static_assert(D == 2 || D == 4 || D == 6, "prefetch depth must be even");
   static constexpr int W = 64 * V;    // window width
   static constexpr int RING = tb2d_ring_rows(K);  // hotspot source rows kept in LDS
@@ -240,7 +242,7 @@ struct Tb2dTile {
         const float dy = __builtin_fmaf(-2.0f, c, yn + o[v]);
         const float dx = __builtin_fmaf(-2.0f, c, sx[v]);
         const float dz = a.cf.kamb - c;
-        float acc = __builtin_fmaf(dy, a.cf.wy_m, q[v]);
+        float acc = __builtin_fmaf(dy, a.cf.wy_m, (HOT && !ADJ) ? q[v] : 0.0f);
         acc = __builtin_fmaf(dx, a.cf.wx_m, acc);
         acc = __builtin_fmaf(dz, a.cf.wz_m, acc);
         o[v] = __builtin_fmaf(a.cf.cp, acc, c);

@@ -1,5 +1,8 @@
 """GPU parity of the paper-literal hotspot forms against the CPU oracle.
 
+* The adjoint of the physical form (its symmetric linear part as the transposed step) against
+  the oracle's scatter adjoint, within max normwise error 1e-5.
+
 * Hotspot 2D in Table 2's physical form (STENCIL_HOTSPOT_PHYS): the kernels evaluate the
   printed formula in its own order, so results must equal the FP32 oracle bit for bit, across
   every instantiated k, ragged shapes, both tile launches (single and split), the plain
@@ -103,8 +106,9 @@ def test_phys_rejections():
     try:
         g = dev(np.ones((64, 64)))
         with pytest.raises(S.StencilError) as e:
-            plan.adjoint(g, SETS["HPr"], 3, torch.empty_like(g))
-        assert e.value.status == -2
+            S.stencil_run_batched([S.BatchItem(HOTSPOT_PHYS, 2, 64, 64, 1, g.data_ptr(), g.data_ptr(),
+                                               S.make_coeffs(SETS["HPr"]), 3)], None, None)
+        assert e.value.status == -2  # UNSUPPORTED: no batched launch of the physical form
         with pytest.raises(S.StencilError) as e:
             plan.run(g, SETS["HPr"], 3, None)
         assert e.value.status == -1  # INVALID_ARG: needs a power map
@@ -119,3 +123,85 @@ def test_hotspot3d_ambient_coefficient_equal_to_ca(shape, k):
     p = uniform(shape, 0.0, 1e-3, 6501 + k)
     for T in sorted({1, k, 2 * k + 1}):
         check(x0, p, "H3p", T, HOTSPOT, {"variant": 2, "k": k})
+
+
+# ------------------------------------------------------------------ adjoint of the physical form
+
+def normrel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def gpu_phys_adjoint(g, cf, T, tuning=None):
+    gg = dev(g)
+    plan = S.Plan(HOTSPOT_PHYS, g.shape, tuning)
+    try:
+        gx = torch.empty_like(gg)
+        gp = torch.empty_like(gg)
+        plan.adjoint(gg, cf, T, gx, gp)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    return gx.cpu().numpy(), gp.cpu().numpy()
+
+
+@pytest.mark.parametrize("shape", [(131, 257), (64, 300), (1, 33), (40, 1)])
+@pytest.mark.parametrize("tuning", [{"variant": 1}, {"variant": 2, "k": 4, "seg_len": 30},
+                                    {"variant": 2, "k": 8, "seg_len": 30}, {"variant": 2, "k": 12, "seg_len": 50}])
+def test_phys_adjoint_matches_oracle(shape, tuning):
+    """The oracle's adjoint is the literal scatter of each term's partial derivative; the
+    library applies the symmetric linear part as a gather."""
+    cf = SETS["HPr"]
+    g = uniform(shape, -1.0, 1.0, 6601)
+    for T in (1, 5, 13):
+        gx, gp = gpu_phys_adjoint(g, cf, T, tuning)
+        rx, rp = oracle.adjoint(g, cf, T, form=HOTSPOT_PHYS)
+        assert normrel(gx, rx) <= TOL, (shape, tuning, T)
+        assert normrel(gp, rp) <= TOL, (shape, tuning, T)
+
+
+def test_phys_adjoint_split_launch_and_dot_product():
+    """Split 2D passes, and the dot-product identity <A^T y, x> = <y, A x> with the library's
+    forward (zero power, TEMP_AMB = 0: the linear part) and adjoint."""
+    cf = SETS["HPr"].copy()
+    cf[9] = 0.0  # TEMP_AMB
+    shape = (1500, 2060)
+    x = uniform(shape, 0.0, 1.0, 6602)
+    y = uniform(shape, 0.0, 1.0, 6603)
+    tuning = {"variant": 2, "k": 8, "seg_len": 8}
+    for T in (1, 19):
+        xx = dev(x)
+        plan = S.Plan(HOTSPOT_PHYS, shape, tuning)
+        try:
+            plan.run(xx, cf, T, dev(np.zeros(shape, np.float32)))
+            torch.cuda.synchronize()
+        finally:
+            plan.close()
+        aty, _ = gpu_phys_adjoint(y, cf, T, tuning)
+        a = float(np.vdot(aty.astype(np.float64), x.astype(np.float64)))
+        b = float(np.vdot(y.astype(np.float64), xx.cpu().numpy().astype(np.float64)))
+        assert abs(a - b) / max(abs(a), abs(b)) <= TOL, (T, a, b)
+    rx, rp = oracle.adjoint(y, cf, 19, form=HOTSPOT_PHYS)
+    gx, gp = gpu_phys_adjoint(y, cf, 19, tuning)
+    assert normrel(gx, rx) <= TOL and normrel(gp, rp) <= TOL
+
+
+def test_phys_autograd_with_recompute():
+    """StencilFn with the physical form: gradients against the oracle's adjoint of the same
+    cotangent, with checkpoints re-run and checked bit for bit during backward."""
+    cf = SETS["HPr"]
+    shape, T = (96, 200), 30
+    x0 = uniform(shape, 300.0, 350.0, 6604)
+    p = uniform(shape, 0.0, 1e-3, 6605)
+    y = uniform(shape, 300.0, 350.0, 6606)
+    xt = dev(x0).requires_grad_(True)
+    pt = dev(p).requires_grad_(True)
+    out = S.StencilFn.apply(xt, pt, cf, T, 6, 1, {"variant": 2, "k": 4, "seg_len": 32}, HOTSPOT_PHYS)
+    loss = 0.5 * ((out - dev(y)) ** 2).sum()
+    loss.backward()
+    xT = oracle.forward(x0, cf, T, power=p, form=HOTSPOT_PHYS, dtype=np.float32)
+    assert np.array_equal(out.detach().cpu().numpy(), xT)
+    rx, rp = oracle.adjoint(xT.astype(np.float64) - y, cf, T, form=HOTSPOT_PHYS)
+    assert normrel(xt.grad.cpu().numpy(), rx) <= TOL
+    assert normrel(pt.grad.cpu().numpy(), rp) <= TOL
