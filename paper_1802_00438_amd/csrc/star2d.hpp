@@ -63,7 +63,7 @@ struct Star2dTile {
   const int lane;
   int ws, ox0, ox1, y0, y1;
   float win[K][NR][V];  // win[s]: the last NR rows of level s (s = 0: input rows), by arrival slot
-  float Lb[V];          // the next input row, loaded one step ahead
+  float Lb[NR][V];      // input rows in flight: the row of step t is loaded NR steps ahead into slot t % NR
   int xl[V];            // column of each of the lane's cells
 
   __device__ __forceinline__ Star2dTile(const Star2dArgs& args, int ln) : a(args), lane(ln) {}
@@ -169,8 +169,8 @@ struct Star2dTile {
   template <int T, bool XE, bool YE, bool VEC>
   __device__ __forceinline__ void step(int r) {
 #pragma unroll
-    for (int v = 0; v < V; ++v) win[0][T][v] = Lb[v];
-    load_row<VEC>(r - 1, Lb);
+    for (int v = 0; v < V; ++v) win[0][T][v] = Lb[T][v];
+    load_row<VEC>(r - NR, Lb[T]);
     if constexpr (!YE) {
       constexpr int CS = (T - R + 2 * NR) % NR;
       // phase 1, top level first: all terms but the last, into slot T of the level's own
@@ -255,7 +255,8 @@ struct Star2dTile {
     const int r0 = y1 - 1 + K * R;
     int nit = (y1 - y0) + 2 * K * R;
     nit = (nit + NR - 1) / NR * NR;  // the extra steps only touch rows outside [y0, y1)
-    load_row<VEC>(r0, Lb);
+#pragma unroll
+    for (int b = 0; b < NR; ++b) load_row<VEC>(r0 - b, Lb[b]);
     for (int it = 0; it < nit; it += NR) steps<0, XE, YE, VEC>(r0 - it);
   }
 
