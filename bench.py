@@ -74,6 +74,42 @@ def tb2d_bytes_flops(nx, ny, K, keff, seg, hot=True, interior_only=False):
     return bytes_, flops
 
 
+def run_roofline(nx, ny, T, k, kinst, seg, R, nread, flops_per, ms):
+    """Whole-run rates of a temporal-blocked 2D workload against both roofs: algorithmic HBM
+    bytes (each tile's window rows read once per pass, nread fields, one write per cell) and
+    executed FLOPs (flops_per per computed cell and level, halos included) summed over the
+    passes of T steps (full passes of k steps, then one of T mod k on the smallest instantiated
+    K that holds it), over the measured run time in ms."""
+    def one(K, keff):
+        W = 256
+        kr = (R * K + 3) // 4 * 4
+        cs = (W - R * K - kr) // 4 * 4
+        sg = max(1, min(seg, ny))
+        tiles = math.ceil(nx / cs) * math.ceil(ny / sg)
+        b = tiles * (sg + 2 * R * keff) * W * 4 * nread + nx * ny * 4
+        f = tiles * W * (sg + R * keff) * keff * flops_per
+        return b, f
+    nfull, rem = divmod(T, k)
+    b, f = one(kinst(k), k)
+    B, F = nfull * b, nfull * f
+    if rem:
+        b, f = one(kinst(rem), rem)
+        B, F = B + b, F + f
+    gbs = B / (ms * 1e-3) / 1e9
+    tf = F / (ms * 1e-3) / 1e12
+    fh, fa = gbs / HBM_PEAK_GBS, tf / ALU_PEAK_TFLOPS
+    if fa >= fh:
+        r = {"bound": "alu", "achieved": round(tf, 3), "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s", "frac": round(fa, 4)}
+    else:
+        r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(fh, 4)}
+    r.update({"frac_alu": round(fa, 4), "frac_hbm": round(fh, 4), "scope": "whole run (all passes and kernels)"})
+    return r
+
+
+def smallest_at_least(ks):
+    return lambda k: min([K for K in ks if K >= k] or [max(ks)])
+
+
 # Kernel sources whose hash identifies the measured build of the dominant kernel.
 TB2D_SOURCES = ["tb2d.hpp", "device_common.hpp", "k_tb2d_hot.hip"]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "tb2d_hotspot_16384_hbm_counters.md")
@@ -330,9 +366,15 @@ def main():
         ms6 = time_call(lambda: pl6.run(x6, w6.coeffs, w6.T, p6), stream, 2)
         g6 = w6.cells * w6.T / (ms6 * 1e-3) / 1e9
         study["hotspot2d_phys_16384"] = model_row(S, pl6, w6.T, ms6, 2, 2, (w6.nx, w6.ny, 1), (256, 0))
+        t6 = pl6.tuning
         extras["hotspot2d_phys_16384"] = {"gcells": round(g6, 1), "ms_per_run": round(ms6, 2),
-                                          "k": pl6.tuning["k"], "seg_len": pl6.tuning["seg_len"],
-                                          "pct_single_pass_roofline": round(100 * g6 / (HBM_PEAK_GBS / 12), 1)}
+                                          "k": t6["k"], "seg_len": t6["seg_len"],
+                                          "pct_single_pass_roofline": round(100 * g6 / (HBM_PEAK_GBS / 12), 1),
+                                          # Table 2's 15 FLOP per cell update: 2 adds, 2 FMAs for the
+                                          # differences, 1 subtraction, 4 FMAs
+                                          "roofline": run_roofline(w6.nx, w6.ny, w6.T, t6["k"],
+                                                                   smallest_at_least([4, 8, 12, 16]), t6["seg_len"],
+                                                                   1, 2, 15, ms6)}
         pl6.close()
         del x6, p6
         torch.cuda.empty_cache()
@@ -354,7 +396,11 @@ def main():
         gp7 = c7 * 20 / (msp7 * 1e-3) / 1e9
         extras["star2d_r2_16384"] = {"gcells": round(g7, 1), "ms_per_run": round(ms7, 2), "k": t7["k"],
                                      "seg_len": t7["seg_len"], "gcells_one_step": round(gp7, 1),
-                                     "pct_single_pass_roofline": round(100 * g7 / (HBM_PEAK_GBS / 8), 1)}
+                                     "pct_single_pass_roofline": round(100 * g7 / (HBM_PEAK_GBS / 8), 1),
+                                     # a multiply and 4r FMAs per cell update: 8r + 1 FLOP
+                                     "roofline": run_roofline(w7["nx"], w7["ny"], w7["T"], t7["k"],
+                                                              smallest_at_least([1, 2, 4, 8]), t7["seg_len"],
+                                                              w7["rad"], 1, 8 * w7["rad"] + 1, ms7)}
         pl7.close()
         pp7.close()
         del x7
