@@ -142,7 +142,7 @@ def measured_traffic(K, seg):
             rec["write_kib_per_dispatch"] * 1024.0 / rec["copy_write_factor"])
 
 
-def model_row(S, plan, T, ms, ndim, nread, dims, bsize):
+def model_row(S, plan, T, ms, ndim, nread, dims, bsize, rad=1):
     """Measured against modelled for one workload: the library's own plan model (the tuner's)
     and the paper's Eq. 3-9 external-memory model at this blocking, with the HBM peak as
     th_max and one cell per lane per clock as the pipeline rate (so Eq. 3 gives th_max).  Ratios
@@ -151,7 +151,7 @@ def model_row(S, plan, T, ms, ndim, nread, dims, bsize):
     k = 1 if tun["variant"] == 1 else tun["k"]
     gm = plan.model(T)
     nx, ny, nz = dims
-    eq = S.stencil_model_estimate(ndim=ndim, rad=1, par_vec=16384, par_time=k, f_max_hz=2.4e9, size_cell=4,
+    eq = S.stencil_model_estimate(ndim=ndim, rad=rad, par_vec=16384, par_time=k, f_max_hz=2.4e9, size_cell=4,
                                   num_read=nread, num_write=1, bsize_x=bsize[0], bsize_y=bsize[1], dim_x=nx,
                                   dim_y=ny, dim_z=nz, iter=T, th_max_gbs=HBM_PEAK_GBS)
     cells = nx * ny * nz
@@ -394,6 +394,8 @@ def main():
         pp7 = S.StarPlan(w7["rad"], (w7["ny"], w7["nx"]), {"variant": 1})
         msp7 = time_call(lambda: pp7.run(x7, wt7, 20), stream, 1)
         gp7 = c7 * 20 / (msp7 * 1e-3) / 1e9
+        study["star2d_r2_16384"] = model_row(S, pl7, w7["T"], ms7, 2, 1, (w7["nx"], w7["ny"], 1), (256, 0),
+                                             rad=w7["rad"])
         extras["star2d_r2_16384"] = {"gcells": round(g7, 1), "ms_per_run": round(ms7, 2), "k": t7["k"],
                                      "seg_len": t7["seg_len"], "gcells_one_step": round(gp7, 1),
                                      "pct_single_pass_roofline": round(100 * g7 / (HBM_PEAK_GBS / 8), 1),

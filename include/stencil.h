@@ -188,8 +188,8 @@ const char* stencil_last_error(void); /* thread-local; "" if none */
  * UNSUPPORTED), 1 <= rad <= 4 (larger rad returns UNSUPPORTED).  tuning as for
  * stencil_create; with k == 0 the fused step count is chosen by timing each instantiated k
  * on plan scratch (rad 1, 2: k <= 8; rad 3, 4: k <= 4).  The plan serves stencil_run_star,
- * stencil_get_tuning and stencil_destroy; stencil_run, stencil_run_ckpt, stencil_adjoint and
- * stencil_plan_model reject it.
+ * stencil_get_tuning, stencil_plan_model (its passes priced with a halo of rad*k) and
+ * stencil_destroy; stencil_run, stencil_run_ckpt and stencil_adjoint reject it.
  *
  * stencil_run_star: exactly T >= 0 steps in place on grid (device, nx*ny FP32).  weights is a
  * HOST array of 1 + 4*rad finite floats, in the stencil's FMA evaluation order: cc; then w_d,

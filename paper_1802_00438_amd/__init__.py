@@ -326,6 +326,9 @@ class StarPlan:
     def tuning(self):
         return stencil_get_tuning(self.handle)
 
+    def model(self, T):
+        return stencil_plan_model(self.handle, T)
+
     def close(self):
         if self.handle is not None and self.handle.value:
             stencil_destroy(self.handle)

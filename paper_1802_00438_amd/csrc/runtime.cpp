@@ -138,6 +138,24 @@ double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj
   return passes * (std::max(tm, ta) + 4e-6);
 }
 
+// Radius-R star passes: the same pricing with a halo of R*K rows and columns per side, and
+// 4R+1 FMAs plus R DPP moves per side (per 4 cells) for each computed cell and level.
+double model_time_star(const Geom2D& g, int R, int nx, int ny, long T, ModelParts* parts) {
+  const DeviceInfo& d = device_info();
+  const int W = 64 * kTb2dV;
+  const long passes = (T + g.K - 1) / g.K;
+  const double tiles = (double)g.ntx * g.nseg;
+  const double bytes = tiles * (g.seg + 2.0 * R * g.K) * W * 4.0 + (double)nx * ny * 4.0;
+  const double ops = tiles * W * (g.seg + (double)R * g.K) * g.K * (4.0 * R + 1.0 + 0.5 * R);
+  const double slots = (double)d.cus * 4 * 2;
+  const double rounds = std::ceil(tiles / slots);
+  const double quant = tiles / (rounds * slots);
+  const double tm = bytes / (d.hbm_gbs * 1e9 * d.achievable_frac);
+  const double ta = ops / (d.valu_lane_ops * 0.8) / quant;
+  if (parts) *parts = ModelParts{passes * tm, passes * ta};
+  return passes * (std::max(tm, ta) + 4e-6);
+}
+
 double model_time_3d(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj, ModelParts* parts) {
   const DeviceInfo& d = device_info();
   const int WX = 64 * kTb3dV;
@@ -1025,7 +1043,20 @@ stencil_status_t stencil_get_tuning(stencil_plan_t plan, stencil_tuning_t* out) 
 stencil_status_t stencil_plan_model(stencil_plan_t p, int T, stencil_plan_model_t* out) {
   if (!p || !out) return fail(STENCIL_ERR_INVALID_ARG, "NULL argument");
   if (T < 0) return fail(STENCIL_ERR_INVALID_ARG, "T must be >= 0");
-  if (p->star) return fail(STENCIL_ERR_UNSUPPORTED, "the time model covers the radius-1 kernels");
+  if (p->star) {
+    const int K = star_k_for(p->rad, std::max(1, p->tuning.k));
+    const int kpass = std::min(K, std::max(1, p->tuning.k));
+    Geom2D g = geom_star(p->rad, K, p->nx, p->ny, p->tuning.seg_len);
+    g.K = kpass;
+    ModelParts mp;
+    stencil_plan_model_t r{};
+    r.seconds = model_time_star(g, p->rad, p->nx, p->ny, T, &mp);
+    r.mem_seconds = mp.mem;
+    r.alu_seconds = mp.alu;
+    r.passes = (T + kpass - 1) / kpass;
+    *out = r;
+    return STENCIL_OK;
+  }
   const KMode m = fwd_mode(p);
   const bool hot = p->form != STENCIL_DIFFUSION;
   int K;

@@ -44,6 +44,7 @@ Geom3D geom3d(int K, bool adj, int nx, int ny, int nz, int segz);
 double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj, bool phys = false,
                      ModelParts* parts = nullptr);
 double model_time_3d(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj, ModelParts* parts = nullptr);
+double model_time_star(const Geom2D& g, int R, int nx, int ny, long T, ModelParts* parts = nullptr);
 // The same for the balanced 3D launch of nwork workgroups (equal shares of column planes).
 double model_time_3d_bal(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj, int nwork,
                          ModelParts* parts = nullptr);

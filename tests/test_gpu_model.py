@@ -50,3 +50,15 @@ def test_plan_model_of_the_plain_kernel():
         assert abs(m["mem_seconds"] - 37 * one["mem_seconds"]) <= 1e-12
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("r,k", [(2, 4), (3, 2), (4, 1)])
+def test_plan_model_of_star_plans(r, k):
+    plan = S.StarPlan(r, (300, 700), {"variant": 2, "k": k, "seg_len": 64})
+    try:
+        for T in (0, 1, k, 7 * k + 1):
+            m = plan.model(T)
+            assert m["passes"] == math.ceil(T / k)
+            assert m["seconds"] >= max(m["mem_seconds"], m["alu_seconds"]) - 1e-15
+    finally:
+        plan.close()
