@@ -205,3 +205,37 @@ def test_phys_autograd_with_recompute():
     rx, rp = oracle.adjoint(xT.astype(np.float64) - y, cf, T, form=HOTSPOT_PHYS)
     assert normrel(xt.grad.cpu().numpy(), rx) <= TOL
     assert normrel(pt.grad.cpu().numpy(), rp) <= TOL
+
+
+def test_phys_run_captured_in_a_graph():
+    """The physical form's split 2D passes (two streams, fork/join) record into a HIP graph;
+    every replay equals the same steps run eagerly."""
+    cf = SETS["HPr"]
+    shape, T = (1500, 2060), 27
+    x0 = uniform(shape, 300.0, 350.0, 6701)
+    p = dev(uniform(shape, 0.0, 1e-3, 6702))
+    tuning = {"variant": 2, "k": 8, "seg_len": 8}
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan = S.Plan(HOTSPOT_PHYS, shape, tuning)
+        ref_plan = S.Plan(HOTSPOT_PHYS, shape, tuning)
+    try:
+        x = dev(x0)
+        y = dev(x0)
+        with torch.cuda.stream(s):
+            plan.run(x, cf, T, p)
+            ref_plan.run(y, cf, T, p)
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            plan.run(x, cf, T, p)
+        for _ in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                ref_plan.run(y, cf, T, p)
+            s.synchronize()
+            assert torch.equal(x, y)
+    finally:
+        plan.close()
+        ref_plan.close()

@@ -138,3 +138,35 @@ def test_star2d_r2_16384_full_size_samples():
         assert got[idx] == rv, (idx, got[idx], rv)
     # convex weights: the field stays within the bounds of the initial data
     assert got.min() >= x0.min() and got.max() <= x0.max()
+
+
+def test_star_run_captured_in_a_graph():
+    """stencil_run_star records into a HIP graph (its passes and the parity copy); every replay
+    equals the same steps run eagerly, with eager work and synchronisation between replays."""
+    r, T = 3, 9  # odd pass count with k = 2: the parity copy is in the graph too
+    x0 = uniform((333, 700), 0.0, 1.0, 7401)
+    w = STAR_SETS[r]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan = S.StarPlan(r, x0.shape, {"variant": 2, "k": 2, "seg_len": 48})
+        ref_plan = S.StarPlan(r, x0.shape, {"variant": 2, "k": 2, "seg_len": 48})
+    try:
+        x = dev(x0)
+        y = dev(x0)
+        with torch.cuda.stream(s):
+            plan.run(x, w, T)
+            ref_plan.run(y, w, T)
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            plan.run(x, w, T)
+        for _ in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                ref_plan.run(y, w, T)
+            s.synchronize()
+            assert torch.equal(x, y)
+    finally:
+        plan.close()
+        ref_plan.close()
