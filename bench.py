@@ -334,6 +334,9 @@ def main():
         "effective_gbs_eq9": round(gcells * 12.0, 1),
         "effective_gflops_table2": round(gcells * 15.0, 1),
         "roofline": roof,
+        # context only (another machine and stencil): the paper's headline results, Diffusion 2D
+        # and 3D on an Arria 10 GX 1150 FPGA (Section 6, abstract)
+        "paper_context_gflops": {"diffusion2d_arria10": 758.2, "diffusion3d_arria10": 374.7},
     }
 
     extras = {}
