@@ -72,6 +72,21 @@ __device__ __forceinline__ void fma_pair_dpp(float wl, float xl, float& al, floa
       : "v"(xl), "v"(wl), "v"(xu), "v"(wu));
 }
 
+// Single fused forms: acc += w * (x of lane i-1), acc += w * (x of lane i+1), each one
+// v_fmac_f32_dpp behind its own "s_nop 1" (the DPP read hazard); end lanes add w * 0.
+__device__ __forceinline__ float fma_from_lower_dpp(float w, float x, float acc) {
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "+v"(acc)
+      : "v"(x), "v"(w));
+  return acc;
+}
+__device__ __forceinline__ float fma_from_upper_dpp(float w, float x, float acc) {
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "+v"(acc)
+      : "v"(x), "v"(w));
+  return acc;
+}
+
 // The same pairing for sums: sl = (xl of lane i-1) + yl and su = (xu of lane i+1) + yu, each
 // one v_add_f32 whose first source is read through DPP (end lanes read 0; halo columns only).
 // The outputs are early-clobber: the first add must not overwrite an operand of the second.

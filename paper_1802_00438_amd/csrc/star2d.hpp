@@ -154,8 +154,17 @@ struct Star2dTile {
       float acc = a.cf.c0 * C[v];
 #pragma unroll
       for (int d = 1; d <= R; ++d) {
-        acc = __builtin_fmaf(a.cf.w[d - 1], xm[d][v], acc);
-        acc = __builtin_fmaf(a.cf.e[d - 1], xp[d][v], acc);
+        const int im = v - d, ip = v + d;
+        if constexpr (!XE) {
+          // a neighbour in the next lane: the move is fused into the multiply-add
+          if (im < 0) acc = fma_from_lower_dpp(a.cf.w[d - 1], C[(V - 1 - (-im - 1)) & (V - 1)], acc);
+          else acc = __builtin_fmaf(a.cf.w[d - 1], xm[d][v], acc);
+          if (ip >= V) acc = fma_from_upper_dpp(a.cf.e[d - 1], C[(ip - V) & (V - 1)], acc);
+          else acc = __builtin_fmaf(a.cf.e[d - 1], xp[d][v], acc);
+        } else {
+          acc = __builtin_fmaf(a.cf.w[d - 1], xm[d][v], acc);
+          acc = __builtin_fmaf(a.cf.e[d - 1], xp[d][v], acc);
+        }
       }
 #pragma unroll
       for (int d = 1; d <= R; ++d) acc = __builtin_fmaf(a.cf.s[d - 1], ys[d][v], acc);
