@@ -884,12 +884,16 @@ stencil_status_t forward(stencil_plan_s* p, float* grid, const float* power, con
   }
   p->ckpt_every = ckpt_every;
   p->ckpt_T = T;
-  for (int j = 0; j < nck; ++j) {
-    hipError_t e = hipMemcpyAsync(p->ckpts[j], grid, p->cells * sizeof(float), hipMemcpyDeviceToDevice, p->stream);
+  // x_0 is copied into checkpoint 0 once; segment j then runs from checkpoint j straight into
+  // checkpoint j+1 (the last segment into grid), so no other checkpoint needs a copy
+  if (nck > 0) {
+    hipError_t e = hipMemcpyAsync(p->ckpts[0], grid, p->cells * sizeof(float), hipMemcpyDeviceToDevice, p->stream);
     if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+  }
+  for (int j = 0; j < nck; ++j) {
     const int seg_T = std::min(ckpt_every, T - j * ckpt_every);
-    // start from the checkpoint copy so no parity copy is needed
-    st = run_sequence(p, m, plain, K, split_steps(seg_T, kpass), p->ckpts[j], grid, p->scratch, pw, nullptr, cf,
+    float* out = (j + 1 < nck) ? p->ckpts[j + 1] : grid;
+    st = run_sequence(p, m, plain, K, split_steps(seg_T, kpass), p->ckpts[j], out, p->scratch, pw, nullptr, cf,
                       &counter);
     if (st != STENCIL_OK) return st;
   }
