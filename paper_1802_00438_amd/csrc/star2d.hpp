@@ -7,7 +7,8 @@
 // gfx950 mapping:
 //   * One 64-lane wavefront owns a 256-column window, 4 consecutive cells per lane (one
 //     16-byte access per row).  x-neighbours at distance d <= 4 are in the lane itself or,
-//     for the first / last d cells, in the lower / upper lane: R DPP moves per side per row.
+//     for the first / last d cells, in the lower / upper lane, read through DPP; in tiles away
+//     from the x edges that read is fused into the multiply-add (v_fmac_f32_dpp).
 //   * Level s (1..K) keeps the last 2R+1 rows of level s-1 in registers.  When level s-1
 //     produces row i, level s computes row i+R (centre, x-terms, then the R rows below and the
 //     R rows above), so level s trails level s-1 by R rows.  The row loop is unrolled by 2R+1,
@@ -63,7 +64,7 @@ struct Star2dTile {
   const int lane;
   int ws, ox0, ox1, y0, y1;
   float win[K][NR][V];  // win[s]: the last NR rows of level s (s = 0: input rows), by arrival slot
-  float Lb[NR][V];      // input rows in flight: the row of step t is loaded NR steps ahead into slot t % NR
+  float Lb[NR][V];      // input rows in flight: the row of step t is loaded NR steps ahead, into slot t % NR
   int xl[V];            // column of each of the lane's cells
 
   __device__ __forceinline__ Star2dTile(const Star2dArgs& args, int ln) : a(args), lane(ln) {}
