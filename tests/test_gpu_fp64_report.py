@@ -16,7 +16,7 @@ import pytest
 import oracle
 import paper_1802_00438_amd as S
 from conftest import FP64_REPORT
-from workloads import WORKLOADS, SETS, DIFFUSION, HOTSPOT, batch_grids
+from workloads import WORKLOADS, SETS, DIFFUSION, HOTSPOT, STAR_SETS, STAR_WORKLOAD, batch_grids, star_field
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -32,11 +32,11 @@ def bound(T):
     return 8.0 * max(T, 1) * 2.0 ** -24
 
 
-def cone64(x0, power, cf, T, idx):
+def cone64(x0, power, cf, T, idx, form=None):
     sl = tuple(slice(max(0, i - T), min(n, i + T + 1)) for i, n in zip(idx, x0.shape))
     sub = np.ascontiguousarray(x0[sl])
     psub = np.ascontiguousarray(power[sl]) if power is not None else None
-    out = oracle.forward(sub, cf, T, power=psub, dtype=np.float64)
+    out = oracle.forward(sub, cf, T, power=psub, dtype=np.float64, form=form)
     return out[tuple(i - s.start for i, s in zip(idx, sl))]
 
 
@@ -74,6 +74,39 @@ def test_fp64_hotspot2d_16384():
     err = max(abs(float(got[i]) - cone64(x0, p, wl.coeffs, wl.T, i)) / abs(cone64(x0, p, wl.coeffs, wl.T, i))
               for i in idx)
     report(wl.name, "forward, %d cone samples" % len(idx), err, "T=%d" % wl.T, wl.T)
+
+
+def test_fp64_hotspot2d_phys_16384():
+    wl = WORKLOADS["hotspot2d_phys_16384"]
+    x0, p = wl.field(), wl.power()
+    got = gpu_run(wl, x0, p)
+    n = wl.nx
+    idx = [(n // 2 + 3, n // 5 + 11), (0, 0), (n - 1, 4321)]
+    refs = [cone64(x0, p, wl.coeffs, wl.T, i, form=wl.form) for i in idx]
+    err = max(abs(float(got[i]) - r) / abs(r) for i, r in zip(idx, refs))
+    report(wl.name, "forward, %d cone samples" % len(idx), err, "T=%d" % wl.T, wl.T)
+
+
+def test_fp64_star2d_r2_16384():
+    wl = STAR_WORKLOAD
+    r, T = wl["rad"], wl["T"]
+    x0 = star_field(wl)
+    x = torch.from_numpy(x0).cuda()
+    plan = S.StarPlan(r, x0.shape)
+    try:
+        plan.run(x, STAR_SETS[r], T)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    got = x.cpu().numpy()
+    n = wl["nx"]
+    errs = []
+    for idx in [(n // 2 + 7, n // 3 + 1), (0, 0)]:
+        sl = tuple(slice(max(0, i - r * T), min(n, i + r * T + 1)) for i in idx)
+        ref = oracle.star2d(np.ascontiguousarray(x0[sl]), STAR_SETS[r], T, dtype=np.float64)
+        rv = ref[tuple(i - s.start for i, s in zip(idx, sl))]
+        errs.append(abs(float(got[idx]) - rv) / abs(rv))
+    report(wl["name"], "forward, 2 cone samples", max(errs), "T=%d, radius %d" % (T, r), T)
 
 
 def test_fp64_diffusion3d_512():
