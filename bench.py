@@ -423,7 +423,8 @@ def main():
         pp3 = S.Plan(DIFFUSION, w3.shape, {"variant": 1})
         msp3 = time_call(lambda: pp3.run(x3, w3.coeffs, 40), stream, 1)
         gp3 = w3.cells * 40 / (msp3 * 1e-3) / 1e9
-        study["diffusion3d_512"] = model_row(S, pl3, w3.T, ms3, 3, 1, (w3.nx, w3.ny, w3.nz), (128, 48))
+        study["diffusion3d_512"] = model_row(S, pl3, w3.T, ms3, 3, 1, (w3.nx, w3.ny, w3.nz),
+                                             (pl3.tuning["bsize_x"], pl3.tuning["bsize_y"]))
         extras["diffusion3d_512"] = {"gcells_tb": round(g3, 1), "ms_tb": round(ms3, 2), "k": pl3.tuning["k"],
                                      "gcells_plain": round(gp3, 1),
                                      "pct_single_pass_roofline": round(100 * g3 / (HBM_PEAK_GBS / 8), 1)}
@@ -452,7 +453,8 @@ def main():
         pl5.run(xs, w5.coeffs, 4, p5)
         xs.copy_(x5)
         fwd_ms = time_call(lambda: pl5.run_ckpt(xs, w5.coeffs, w5.T, w5.ckpt_every, p5), stream, 1)
-        study["hotspot3d_256"] = model_row(S, pl5, w5.T, fwd_ms, 3, 2, (w5.nx, w5.ny, w5.nz), (128, 48))
+        study["hotspot3d_256"] = model_row(S, pl5, w5.T, fwd_ms, 3, 2, (w5.nx, w5.ny, w5.nz),
+                                             (pl5.tuning["bsize_x"], pl5.tuning["bsize_y"]))
         cot = (xs - y5).contiguous()
         gx = torch.empty_like(x5)
         gp = torch.empty_like(x5)
