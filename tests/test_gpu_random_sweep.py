@@ -1,0 +1,153 @@
+"""GPU parity over a seeded random sweep of shapes, step counts and blockings.
+
+The hand-picked shapes of the other parity tests aim at known corner cases (one tile, a tail
+of one cell, windows flush with an edge).  Here every case draws its grid size log-uniformly,
+its step count, fused-step count and segment length uniformly, and its form and coefficient
+set from the library's whole surface (2D diffusion, Rodinia hotspot and Table 2's physical
+hotspot; 3D diffusion and hotspot with the tile and the balanced launch; radius-r stars), so
+that tilings nobody thought of get exercised too.  The bar is the same: bit-identical to the
+FP32 oracle (each kernel keeps the oracle's FMA order), and within max-rel 1e-5 of it.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1802_00438_amd as S
+from workloads import SETS, STAR_SETS, DIFFUSION, HOTSPOT, HOTSPOT_PHYS, rng, uniform
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+N2D, N3D, NSTAR = 96, 64, 48
+
+# largest fused-step count served per (dimensionality, form); any k up to it runs on the
+# smallest instantiated kernel at or above it
+KMAX_2D = {DIFFUSION: 24, HOTSPOT: 16, HOTSPOT_PHYS: 16}
+KMAX_3D = {DIFFUSION: 6, HOTSPOT: 4}
+KMAX_STAR = {1: 8, 2: 8, 3: 4, 4: 4}
+
+
+def log_uniform(g, lo, hi):
+    return int(round(math.exp(g.uniform(math.log(lo), math.log(hi)))))
+
+
+def maxrel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-30))) if a.size else 0.0
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def draw_2d(i):
+    g = rng(9100 + i)
+    form = [DIFFUSION, HOTSPOT, HOTSPOT_PHYS][i % 3]
+    cset = {DIFFUSION: ["D2", "A2"], HOTSPOT: ["H2", "AH2"], HOTSPOT_PHYS: ["HP2", "HPr"]}[form][int(g.integers(2))]
+    lo = 1 if i % 4 == 0 else 150  # every fourth case small, the rest several tiles wide
+    shape = (log_uniform(g, lo, 2000), log_uniform(g, lo, 2000))
+    T = int(g.integers(0, 61))
+    k = int(g.integers(1, KMAX_2D[form] + 1))
+    seg = int(g.integers(1, 400))
+    return form, cset, shape, T, {"variant": 2, "k": k, "seg_len": seg}
+
+
+def draw_3d(i):
+    g = rng(9200 + i)
+    form = [DIFFUSION, HOTSPOT][i % 2]
+    cset = {DIFFUSION: ["D3", "A3"], HOTSPOT: ["H3", "AH3", "H3p"]}[form][int(g.integers(2 if form == DIFFUSION else 3))]
+    lo = 1 if i % 4 == 3 else 24
+    shape = (log_uniform(g, 1, 80), log_uniform(g, lo, 200), log_uniform(g, 2 * lo, 400))
+    T = int(g.integers(0, 15))
+    k = int(g.integers(1, KMAX_3D[form] + 1))
+    # segment length 0 with k given: the balanced launch; otherwise one workgroup per tile
+    seg = 0 if (i // 2) % 2 == 0 else int(g.integers(1, 80))
+    return form, cset, shape, T, {"variant": 2, "k": k, "seg_len": seg}
+
+
+def draw_star(i):
+    g = rng(9300 + i)
+    r = 1 + i % 4
+    lo = 1 if i % 4 == 0 else 100
+    shape = (log_uniform(g, lo, 1500), log_uniform(g, lo, 1500))
+    T = int(g.integers(0, 31))
+    k = int(g.integers(1, KMAX_STAR[r] + 1))
+    seg = int(g.integers(1, 300))
+    return r, shape, T, {"variant": 2, "k": k, "seg_len": seg}
+
+
+def fields(form, shape, seed):
+    if form == DIFFUSION:
+        return uniform(shape, 0.0, 1.0, seed), None
+    return uniform(shape, 300.0, 350.0, seed), uniform(shape, 0.0, 1e-3, seed + 1)
+
+
+def run_and_compare(form, cset, shape, T, tuning, seed):
+    cf = SETS[cset]
+    x0, p = fields(form, shape, seed)
+    x = dev(x0)
+    plan = S.Plan(form, shape, tuning)
+    try:
+        plan.run(x, cf, T, dev(p) if p is not None else None)
+        torch.cuda.synchronize()
+        used = plan.tuning
+    finally:
+        plan.close()
+    got = x.cpu().numpy()
+    ref = oracle.forward(x0, cf, T, power=p, form=form, dtype=np.float32)
+    case = (form, cset, shape, T, tuning, used)
+    assert maxrel(got, ref) <= TOL, case
+    assert np.array_equal(got, ref), (case, maxrel(got, ref))
+
+
+@pytest.mark.parametrize("i", range(N2D))
+def test_random_2d(i):
+    form, cset, shape, T, tuning = draw_2d(i)
+    print("case 2d", i, form, cset, shape, T, tuning, flush=True)
+    run_and_compare(form, cset, shape, T, tuning, 9500 + i)
+
+
+@pytest.mark.parametrize("i", range(N3D))
+def test_random_3d(i):
+    form, cset, shape, T, tuning = draw_3d(i)
+    print("case 3d", i, form, cset, shape, T, tuning, flush=True)
+    run_and_compare(form, cset, shape, T, tuning, 9600 + i)
+
+
+@pytest.mark.parametrize("i", range(NSTAR))
+def test_random_star(i):
+    r, shape, T, tuning = draw_star(i)
+    print("case star", i, r, shape, T, tuning, flush=True)
+    if r == 1:
+        cf = SETS["A2"]  # cc, cw, ce, cn, cs -> cc, w1, e1, s1, n1
+        w = np.array([cf[0], cf[1], cf[2], cf[4], cf[3]], dtype=np.float32)
+    else:
+        w = STAR_SETS[r]
+    x0 = uniform(shape, 0.0, 1.0, 9700 + i)
+    x = dev(x0)
+    plan = S.StarPlan(r, shape, tuning)
+    try:
+        plan.run(x, w, T)
+        torch.cuda.synchronize()
+        used = plan.tuning
+    finally:
+        plan.close()
+    got = x.cpu().numpy()
+    ref = oracle.star2d(x0, w, T, dtype=np.float32)
+    assert maxrel(got, ref) <= TOL, (r, shape, T, tuning, used)
+    assert np.array_equal(got, ref), (r, shape, T, tuning, used, maxrel(got, ref))
+
+
+def test_draws_cover_the_surface():
+    """The sweep reaches every form, both 3D launch shapes, every radius and odd sizes."""
+    d2 = [draw_2d(i) for i in range(N2D)]
+    d3 = [draw_3d(i) for i in range(N3D)]
+    ds = [draw_star(i) for i in range(NSTAR)]
+    assert {f for f, *_ in d2} == {DIFFUSION, HOTSPOT, HOTSPOT_PHYS}
+    assert {t["seg_len"] == 0 for *_, t in d3} == {True, False}
+    assert {r for r, *_ in ds} == {1, 2, 3, 4}
+    assert any(s[0] % 2 for _, _, s, _, _ in d2) and any(s[2] % 2 for _, _, s, _, _ in d3)
