@@ -151,3 +151,69 @@ def test_draws_cover_the_surface():
     assert {t["seg_len"] == 0 for *_, t in d3} == {True, False}
     assert {r for r, *_ in ds} == {1, 2, 3, 4}
     assert any(s[0] % 2 for _, _, s, _, _ in d2) and any(s[2] % 2 for _, _, s, _, _ in d3)
+
+
+# ------------------------------------------------------------------ adjoint sweep
+
+NADJ = 48
+KMAX_ADJ = {2: 12, 3: 4}
+
+
+def draw_adjoint(i):
+    g = rng(9400 + i)
+    ndim = 2 if i % 3 else 3
+    if ndim == 2:
+        form = [DIFFUSION, HOTSPOT, HOTSPOT_PHYS][(i // 3) % 3]
+        cset = {DIFFUSION: "A2", HOTSPOT: "AH2", HOTSPOT_PHYS: "HPr"}[form]
+        lo = 1 if i % 5 == 0 else 100
+        shape = (log_uniform(g, lo, 1200), log_uniform(g, lo, 1200))
+        T = int(g.integers(0, 31))
+    else:
+        form = [DIFFUSION, HOTSPOT][(i // 3) % 2]
+        cset = {DIFFUSION: "A3", HOTSPOT: "AH3"}[form]
+        lo = 1 if i % 5 == 0 else 24
+        shape = (log_uniform(g, 1, 60), log_uniform(g, lo, 150), log_uniform(g, 2 * lo, 300))
+        T = int(g.integers(0, 13))
+    k = int(g.integers(1, KMAX_ADJ[ndim] + 1))
+    seg = int(g.integers(1, 200))
+    # every fourth case recomputes the forward tiles from checkpoints (and verifies them)
+    recompute = 1 if (i % 4 == 1 and T > 0) else 0
+    ckpt_every = int(g.integers(1, T + 1)) if recompute else 0
+    return form, cset, shape, T, {"variant": 2, "k": k, "seg_len": seg}, recompute, ckpt_every
+
+
+@pytest.mark.parametrize("i", range(NADJ))
+def test_random_adjoint(i):
+    form, cset, shape, T, tuning, recompute, ckpt_every = draw_adjoint(i)
+    print("case adjoint", i, form, cset, shape, T, tuning, recompute, ckpt_every, flush=True)
+    cf = SETS[cset]
+    cot = uniform(shape, -1.0, 1.0, 9800 + i)
+    x0, p = fields(form, shape, 9900 + i)
+    hot = form != DIFFUSION
+    plan = S.Plan(form, shape, tuning)
+    try:
+        c = dev(cot)
+        gx = torch.empty_like(c)
+        gp = torch.empty_like(c) if hot else None
+        pw = dev(p) if hot else None
+        if recompute:
+            plan.run_ckpt(dev(x0), cf, T, ckpt_every, pw)
+        plan.adjoint(c, cf, T, gx, gp, pw, recompute)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    rx, rp = oracle.adjoint(cot, cf, T, form=form)
+    gxn = gx.cpu().numpy()
+    scale = max(float(np.max(np.abs(rx))), 1e-300)
+    assert float(np.max(np.abs(gxn - rx))) / scale <= TOL, (form, cset, shape, T, tuning)
+    if hot:
+        gpn = gp.cpu().numpy()
+        scale = max(float(np.max(np.abs(rp))), 1e-300)
+        assert float(np.max(np.abs(gpn - rp))) / scale <= TOL, (form, cset, shape, T, tuning)
+
+
+def test_adjoint_draws_cover_the_surface():
+    d = [draw_adjoint(i) for i in range(NADJ)]
+    assert {(len(s), f) for f, _, s, *_ in d} == {(2, DIFFUSION), (2, HOTSPOT), (2, HOTSPOT_PHYS), (3, DIFFUSION),
+                                                 (3, HOTSPOT)}
+    assert any(r for *_, r, _ in d) and any(T == 0 for _, _, _, T, *_ in d)
