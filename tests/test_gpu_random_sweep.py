@@ -217,3 +217,51 @@ def test_adjoint_draws_cover_the_surface():
     assert {(len(s), f) for f, _, s, *_ in d} == {(2, DIFFUSION), (2, HOTSPOT), (2, HOTSPOT_PHYS), (3, DIFFUSION),
                                                  (3, HOTSPOT)}
     assert any(r for *_, r, _ in d) and any(T == 0 for _, _, _, T, *_ in d)
+
+
+# ------------------------------------------------------------------ batched sweep
+
+NBATCH = 8
+
+
+def draw_batch(b):
+    """A batch of 2-12 diffusion grids of mixed dimensionality, sizes and step counts."""
+    g = rng(9450 + b)
+    n = int(g.integers(2, 13))
+    out = []
+    for j in range(n):
+        lo = 1 if j % 2 else 40  # half the grids small, half several windows wide
+        if g.random() < 0.6:
+            shape = (log_uniform(g, lo, 700), log_uniform(g, 3 * lo, 900))
+            cset = ["D2", "A2"][int(g.integers(2))]
+        else:
+            shape = (log_uniform(g, 1, 48), log_uniform(g, lo, 160), log_uniform(g, 3 * lo, 300))
+            cset = ["D3", "A3"][int(g.integers(2))]
+        out.append((shape, cset, int(g.integers(0, 45))))
+    return out
+
+
+@pytest.mark.parametrize("b", range(NBATCH))
+def test_random_batched(b):
+    batch = draw_batch(b)
+    print("case batch", b, batch, flush=True)
+    xs = [uniform(sh, 0.0, 1.0, 10000 + 100 * b + j) for j, (sh, _, _) in enumerate(batch)]
+    cfs = [SETS[c] for _, c, _ in batch]
+    ts = [T for _, _, T in batch]
+    dts = [dev(x) for x in xs]
+    refs = [oracle.forward(x, c, T, dtype=np.float32) for x, c, T in zip(xs, cfs, ts)]
+    cache = S.run_batched(dts, cfs, ts)
+    try:
+        torch.cuda.synchronize()
+        for (sh, c, T), d, ref in zip(batch, dts, refs):
+            assert np.array_equal(d.cpu().numpy(), ref), (sh, c, T)
+        # one graph replay on reset inputs
+        for d, x in zip(dts, xs):
+            d.copy_(dev(x))
+        torch.cuda.synchronize()
+        S.run_batched(dts, cfs, ts, cache=cache)
+        torch.cuda.synchronize()
+        for (sh, c, T), d, ref in zip(batch, dts, refs):
+            assert np.array_equal(d.cpu().numpy(), ref), ("replay", sh, c, T)
+    finally:
+        S.stencil_batch_destroy(cache)
