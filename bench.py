@@ -204,6 +204,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--k", type=int, default=0, help="fix the fused steps per pass (skips auto-tuning)")
     ap.add_argument("--seg", type=int, default=0, help="fix the rows per tile pass (with --k)")
+    ap.add_argument("--star-k", type=int, default=0,
+                    help="fix the fused steps per pass of the radius-2 star workload (skips its tuning)")
+    ap.add_argument("--star-seg", type=int, default=0, help="fix its rows per tile pass (with --star-k)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first copy one grid-sized buffer three times (a known-size kernel for "
                          "calibrating memory counters)")
@@ -387,7 +390,8 @@ def main():
         from workloads import STAR_WORKLOAD, STAR_SETS, star_field
         w7 = STAR_WORKLOAD
         x7 = torch.from_numpy(star_field(w7)).to(dev)
-        pl7 = S.StarPlan(w7["rad"], (w7["ny"], w7["nx"]))
+        pl7 = S.StarPlan(w7["rad"], (w7["ny"], w7["nx"]),
+                         {"variant": 2, "k": args.star_k, "seg_len": args.star_seg} if args.star_k > 0 else None)
         wt7 = STAR_SETS[w7["rad"]]
         pl7.run(x7, wt7, 16)
         ms7 = time_call(lambda: pl7.run(x7, wt7, w7["T"]), stream, 2)

@@ -5,11 +5,13 @@
 
 // Instantiated fused-step counts per radius: the level windows, K x (2R+1) rows of 4 cells,
 // must fit the register file.
-static const int kStarK12[] = {1, 2, 4, 8};
+static const int kStarK1[] = {1, 2, 4, 8};
+static const int kStarK2[] = {1, 2, 4, 5, 8};
 static const int kStarK34[] = {1, 2, 4};
 
 int star_instantiated(int R, const int** ks) {
-  if (R == 1 || R == 2) { *ks = kStarK12; return 4; }
+  if (R == 1) { *ks = kStarK1; return 4; }
+  if (R == 2) { *ks = kStarK2; return 5; }
   if (R == 3 || R == 4) { *ks = kStarK34; return 3; }
   *ks = nullptr;
   return 0;

@@ -10,7 +10,7 @@
 hipError_t launch_star2d_r12(int R, int K, const Star2dArgs& a, hipStream_t s) {
   switch (R) {
     case 1: switch (K) { SL(1, 1) SL(1, 2) SL(1, 4) SL(1, 8) default: return hipErrorInvalidValue; } break;
-    case 2: switch (K) { SL(2, 1) SL(2, 2) SL(2, 4) SL(2, 8) default: return hipErrorInvalidValue; } break;
+    case 2: switch (K) { SL(2, 1) SL(2, 2) SL(2, 4) SL(2, 5) SL(2, 8) default: return hipErrorInvalidValue; } break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

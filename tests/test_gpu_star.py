@@ -18,7 +18,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
-KS = {1: [1, 2, 4, 8], 2: [1, 2, 4, 8], 3: [1, 2, 4], 4: [1, 2, 4]}
+KS = {1: [1, 2, 4, 8], 2: [1, 2, 4, 5, 8], 3: [1, 2, 4], 4: [1, 2, 4]}
 
 
 def dev(a):
