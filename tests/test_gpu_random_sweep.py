@@ -265,3 +265,29 @@ def test_random_batched(b):
             assert np.array_equal(d.cpu().numpy(), ref), ("replay", sh, c, T)
     finally:
         S.stencil_batch_destroy(cache)
+
+
+# ------------------------------------------------------------------ checkpointed forward sweep
+
+NCKPT = 24
+
+
+@pytest.mark.parametrize("i", range(NCKPT))
+def test_random_checkpointed_forward(i):
+    """run_ckpt with a random checkpoint interval (0: the library's sqrt(T)) ends on the same
+    field as the oracle, bit for bit, whatever the interval and the blocking."""
+    form, cset, shape, T, tuning = draw_2d(i) if i % 2 == 0 else draw_3d(i)
+    g = rng(9470 + i)
+    every = 0 if i % 3 == 0 else int(g.integers(1, max(T, 1) + 1))
+    print("case ckpt", i, form, cset, shape, T, tuning, every, flush=True)
+    cf = SETS[cset]
+    x0, p = fields(form, shape, 10900 + i)
+    x = dev(x0)
+    plan = S.Plan(form, shape, tuning)
+    try:
+        plan.run_ckpt(x, cf, T, every, dev(p) if p is not None else None)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    ref = oracle.forward(x0, cf, T, power=p, form=form, dtype=np.float32)
+    assert np.array_equal(x.cpu().numpy(), ref), (form, cset, shape, T, tuning, every)
