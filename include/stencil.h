@@ -80,11 +80,14 @@ typedef struct {
 
 typedef struct stencil_plan_s* stencil_plan_t;
 
-/* Create a plan for a grid of nx*ny*nz cells (ndim 2: nz must be 1).  Allocates the plan's
- * ping-pong scratch (one grid) on the current device and, when tuning is NULL or has zero
- * fields, picks the blocking from the bandwidth/halo cost model and short timed trials on
- * scratch memory (cached per shape).  hip_stream: a hipStream_t, or NULL for the default
- * stream.  *out receives the plan; on error *out is NULL. */
+/* Create a plan for a grid of nx*ny*nz cells (ndim 2: nz must be 1).  The plan fixes the
+ * blocking of Sections 3.1-3.2: spatial blocks overlapping by a halo of k cells per side
+ * (Eq. 2, 4, 5) that stream along the outermost axis and carry k fused time steps per pass.
+ * Allocates the plan's ping-pong scratch (one grid) on the current device and, when tuning is
+ * NULL or has zero fields, picks k and the block shape as Section 5.3 does: the
+ * bandwidth/halo cost model (Section 4) prunes the candidates and short timed trials on
+ * scratch memory decide among the best (cached per shape).  hip_stream: a hipStream_t, or
+ * NULL for the default stream.  *out receives the plan; on error *out is NULL. */
 stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int ndim, int nx, int ny,
                                 int nz, const stencil_tuning_t* tuning, void* hip_stream);
 
@@ -102,6 +105,27 @@ stencil_status_t stencil_run(stencil_plan_t plan, float* grid, const float* powe
  * checkpoints replace any earlier ones.  Returns OUT_OF_MEMORY if they do not fit. */
 stencil_status_t stencil_run_ckpt(stencil_plan_t plan, float* grid, const float* power,
                                   const stencil_coeffs_t* coeffs, int T, int ckpt_every);
+
+/* One temporal-blocked pass over a slab whose faces along the streamed axis (z in 3D, y in 2D)
+ * may be ghost faces: the spatial blocking of Sections 3.1-3.2 lifted to a whole device, where
+ * a grid too large for one device is cut into slabs along the streamed axis and each slab
+ * carries copies of its neighbours' cells (Section 1 motivates spatial blocking by exactly
+ * this distribution of large inputs; Section 8 names multi-device distribution as future work).
+ * The plan's grid is the slab with its ghost planes: the first ghost_lo and the last ghost_hi
+ * planes (rows in 2D) are ghost planes, supplied by the caller; a depth of 0 marks a true grid
+ * face, which is clamped (Section 5.1).  Runs T fused steps from src to dst (both device,
+ * plan-shaped, out of place) in one pass and writes only the interior planes
+ * [ghost_lo, n - ghost_hi) of dst; dst's ghost planes are not written.  The interior then
+ * equals T steps of the whole grid restricted to the slab, because a step moves information
+ * one plane, so the far side of a ghost region (where the slab array ends) reaches at most T
+ * planes inward.  Requires T <= every non-zero ghost depth (INVALID_ARG) and T <= the largest
+ * fused step count of the kernels (UNSUPPORTED beyond it: 24 for 2D diffusion, 16 for 2D
+ * hotspot, 6 for 3D diffusion, 4 for 3D hotspot); T = 0 copies the interior.  power (hotspot)
+ * is the slab's power map with the same ghost planes.  Not for plain (variant 1) or star
+ * plans (UNSUPPORTED).  Asynchronous on the plan's stream.  A multi-device run alternates
+ * this pass with an exchange of the ghost planes between neighbouring slabs. */
+stencil_status_t stencil_run_slab(stencil_plan_t plan, const float* src, float* dst, const float* power,
+                                  const stencil_coeffs_t* coeffs, int T, int ghost_lo, int ghost_hi);
 
 /* Adjoint (vector-Jacobian product) of T steps.  cotangent = dJ/dx_T (device, read only).
  * Writes grad_x0 = dJ/dx_0 (device) and, if grad_power is not NULL and the plan is
@@ -144,12 +168,23 @@ typedef struct stencil_batch_s* stencil_batch_t;
  *                there; otherwise replay *graph_cache, which must have been built from
  *                items with identical shapes, T, grid pointers and coefficients
  *                (INVALID_ARG otherwise).
- * Items must not share grid memory.  Asynchronous on hip_stream. */
+ * Every dependency wait is bounded: a wait that exceeds its bound (a scheduling fault) ends
+ * with STENCIL_ERR_INTERNAL instead of a hang (see stencil_batch_sync for replays).
+ * Items must not share grid memory.  Asynchronous on hip_stream when graph_cache is not NULL;
+ * the uncached call synchronises and returns the launch's status. */
 stencil_status_t stencil_run_batched(int n, const stencil_batch_item_t* items, void* hip_stream,
                                      stencil_batch_t* graph_cache);
 
+/* Wait for the latest replay of a captured batch and report it: STENCIL_ERR_INTERNAL when a
+ * dependency wait of any replay so far exceeded its bound (a scheduling fault: the results are
+ * invalid and the batch should be destroyed), else OK.  A replay also reports, without
+ * waiting, such a failure of an earlier replay that has completed; the uncached call reports
+ * its own. */
+stencil_status_t stencil_batch_sync(stencil_batch_t batch);
+
 /* Free a captured batch (synchronises its stream first).  NULL is a no-op. */
 void stencil_batch_destroy(stencil_batch_t batch);
+
 
 /* Report the blocking the plan resolved to (after auto-tuning). */
 stencil_status_t stencil_get_tuning(stencil_plan_t plan, stencil_tuning_t* out);

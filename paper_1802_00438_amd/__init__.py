@@ -28,7 +28,7 @@ STATUS = {0: "STENCIL_OK", -1: "STENCIL_ERR_INVALID_ARG", -2: "STENCIL_ERR_UNSUP
 EXPORTED = ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoint", "stencil_run_batched",
             "stencil_batch_destroy", "stencil_get_tuning", "stencil_destroy", "stencil_status_string",
             "stencil_last_error", "stencil_model_estimate", "stencil_plan_model", "stencil_create_star",
-            "stencil_run_star")
+            "stencil_run_star", "stencil_batch_sync", "stencil_run_slab")
 
 
 class StencilError(RuntimeError):
@@ -93,7 +93,9 @@ def lib():
             L.stencil_run.argtypes = [vp, vp, vp, ctypes.POINTER(Coeffs), i]
             L.stencil_run_ckpt.argtypes = [vp, vp, vp, ctypes.POINTER(Coeffs), i, i]
             L.stencil_adjoint.argtypes = [vp, vp, vp, ctypes.POINTER(Coeffs), i, vp, vp, i]
+            L.stencil_run_slab.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Coeffs), i, i, i]
             L.stencil_run_batched.argtypes = [i, ctypes.POINTER(BatchItem), vp, ctypes.POINTER(vp)]
+            L.stencil_batch_sync.argtypes = [vp]
             L.stencil_batch_destroy.argtypes = [vp]
             L.stencil_batch_destroy.restype = None
             L.stencil_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
@@ -109,7 +111,8 @@ def lib():
             L.stencil_run_star.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float), i]
             for name in ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoint",
                          "stencil_run_batched", "stencil_get_tuning", "stencil_model_estimate",
-                         "stencil_plan_model", "stencil_create_star", "stencil_run_star"):
+                         "stencil_plan_model", "stencil_create_star", "stencil_run_star", "stencil_batch_sync",
+                         "stencil_run_slab"):
                 getattr(L, name).restype = i
             _lib = L
     return _lib
@@ -185,6 +188,12 @@ def stencil_run_ckpt(plan, grid, power, coeffs, T, ckpt_every=0):
     _check(lib().stencil_run_ckpt(plan, _ptr(grid), _ptr(power), ctypes.byref(c), int(T), int(ckpt_every)))
 
 
+def stencil_run_slab(plan, src, dst, power, coeffs, T, ghost_lo, ghost_hi):
+    c = make_coeffs(coeffs)
+    _check(lib().stencil_run_slab(plan, _ptr(src), _ptr(dst), _ptr(power), ctypes.byref(c), int(T), int(ghost_lo),
+                                  int(ghost_hi)))
+
+
 def stencil_adjoint(plan, cotangent, power, coeffs, T, grad_x0, grad_power=None, recompute=0):
     c = make_coeffs(coeffs)
     _check(lib().stencil_adjoint(plan, _ptr(cotangent), _ptr(power), ctypes.byref(c), int(T), _ptr(grad_x0),
@@ -198,6 +207,11 @@ def stencil_run_batched(items, stream=None, cache=None):
     _check(lib().stencil_run_batched(len(items), arr, _stream(stream),
                                      ctypes.byref(cache) if cache is not None else None))
     return cache
+
+
+def stencil_batch_sync(cache):
+    """Wait for the latest replay of a captured batch; raises if a dependency wait failed."""
+    _check(lib().stencil_batch_sync(cache))
 
 
 def stencil_batch_destroy(cache):
@@ -248,10 +262,22 @@ def _dims(x):
     raise ValueError("grid must be (ny, nx) or (nz, ny, nx)")
 
 
-def _check_tensor(x, name):
+def _check_tensor(x, name, shape=None, device=None):
+    """Reject what the kernels cannot take: anything but a contiguous float32 device tensor, a
+    tensor whose shape differs from the plan's (the kernels would read or write past it) and a
+    tensor on another device than the plan's."""
     import torch
     if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float32 or not x.is_contiguous():
         raise ValueError("%s must be a contiguous float32 CUDA/HIP tensor" % name)
+    if shape is not None and tuple(x.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, the plan was made for %s" % (name, tuple(x.shape), tuple(shape)))
+    if device is not None and x.device.index != device:
+        raise ValueError("%s is on cuda:%s, the plan on cuda:%d" % (name, x.device.index, device))
+
+
+def _current_device():
+    import torch
+    return torch.cuda.current_device()
 
 
 class Plan:
@@ -265,23 +291,49 @@ class Plan:
         else:
             ndim, nx, ny, nz = 3, self.shape[2], self.shape[1], self.shape[0]
         self.ndim = ndim
+        self.device = _current_device()
+        self.handle = None
         self.handle = stencil_create(self.form, ndim, nx, ny, nz, tuning, stream)
 
-    def run(self, grid, coeffs, T, power=None):
-        _check_tensor(grid, "grid")
+    def _check(self, t, name):
+        _check_tensor(t, name, self.shape, self.device)
+
+    def _check_power(self, power):
         if power is not None:
-            _check_tensor(power, "power")
+            self._check(power, "power")
+        elif self.form != DIFFUSION:
+            raise ValueError("the hotspot forms need a power map")
+
+    def run(self, grid, coeffs, T, power=None):
+        self._check(grid, "grid")
+        self._check_power(power)
         stencil_run(self.handle, grid, power, coeffs, T)
         return grid
 
     def run_ckpt(self, grid, coeffs, T, ckpt_every=0, power=None):
-        _check_tensor(grid, "grid")
+        self._check(grid, "grid")
+        self._check_power(power)
         stencil_run_ckpt(self.handle, grid, power, coeffs, T, ckpt_every)
         return grid
 
+    def run_slab(self, src, dst, coeffs, T, ghost_lo, ghost_hi, power=None):
+        """One pass of T fused steps over a slab with ghost planes (rows in 2D): reads src, writes
+        the interior [ghost_lo, n - ghost_hi) of dst along the slowest axis."""
+        self._check(src, "src")
+        self._check(dst, "dst")
+        self._check_power(power)
+        stencil_run_slab(self.handle, src, dst, power, coeffs, T, ghost_lo, ghost_hi)
+        return dst
+
     def adjoint(self, cotangent, coeffs, T, grad_x0, grad_power=None, power=None, recompute=0):
-        _check_tensor(cotangent, "cotangent")
-        _check_tensor(grad_x0, "grad_x0")
+        self._check(cotangent, "cotangent")
+        self._check(grad_x0, "grad_x0")
+        if grad_power is not None:
+            self._check(grad_power, "grad_power")
+        if power is not None:
+            self._check(power, "power")
+        elif recompute and self.form != DIFFUSION:
+            raise ValueError("recompute of a hotspot form needs the power map")
         stencil_adjoint(self.handle, cotangent, power, coeffs, T, grad_x0, grad_power, recompute)
         return grad_x0, grad_power
 
@@ -312,11 +364,13 @@ class StarPlan:
             raise ValueError("the radius-r star stencil takes (ny, nx) grids")
         self.rad = int(rad)
         self.shape = (int(shape[0]), int(shape[1]))
+        self.device = _current_device()
+        self.handle = None
         self.handle = stencil_create_star(2, self.rad, self.shape[1], self.shape[0], 1, tuning, stream)
 
     def run(self, grid, weights, T):
         """weights: 1 + 4*rad values, cc; w_d, e_d (d = 1..rad); s_1..s_rad; n_1..n_rad."""
-        _check_tensor(grid, "grid")
+        _check_tensor(grid, "grid", self.shape, self.device)
         if len(weights) != 1 + 4 * self.rad:
             raise ValueError("weights must have 1 + 4*rad entries")
         stencil_run_star(self.handle, grid, weights, T)
@@ -355,6 +409,52 @@ def run(x, coeffs, T, power=None, tuning=None, form=None):
     return x
 
 
+class _PlanPool:
+    """Plans kept for reuse by StencilFn, per (form, shape, tuning, device).  A plan is taken
+    for one forward and comes back when that forward's autograd node is released, so two
+    live graphs never share a plan (each plan holds the checkpoints of its own forward)."""
+
+    def __init__(self):
+        self._free = {}
+        self._mu = threading.Lock()
+
+    def take(self, form, shape, tuning):
+        key = (int(form), tuple(int(s) for s in shape), None if tuning is None else tuple(sorted(tuning.items())),
+               _current_device())
+        with self._mu:
+            lst = self._free.get(key)
+            if lst:
+                return key, lst.pop()
+        return key, Plan(form, shape, tuning)
+
+    def give(self, key, plan):
+        with self._mu:
+            self._free.setdefault(key, []).append(plan)
+
+    def clear(self):
+        with self._mu:
+            plans = [p for lst in self._free.values() for p in lst]
+            self._free.clear()
+        for p in plans:
+            p.close()
+
+
+_plan_pool = _PlanPool()
+
+
+class _PlanLease:
+    """Holds a pooled plan for the lifetime of one autograd node."""
+
+    def __init__(self, key, plan):
+        self.key, self.plan = key, plan
+
+    def __del__(self):
+        try:
+            _plan_pool.give(self.key, self.plan)
+        except Exception:
+            pass
+
+
 def _stencil_fn():
     import torch
 
@@ -364,16 +464,19 @@ def _stencil_fn():
 
         backward returns dJ/dx0 and dJ/dpower from the library's adjoint kernels; forward keeps
         checkpoints every ckpt_every steps (0 = sqrt(T)), and recompute=1 re-runs and checks them
-        during backward."""
+        during backward.  The plan (scratch and checkpoints) stays with the autograd node until
+        the node is released, so backward may run more than once (retain_graph=True); plans
+        are then reused by later forwards of the same shape."""
 
         @staticmethod
         def forward(ctx, x0, power, coeffs, T, ckpt_every=0, recompute=0, tuning=None, form=None):
             if form is None:
                 form = HOTSPOT if power is not None else DIFFUSION
-            plan = Plan(form, x0.shape, tuning)
+            key, plan = _plan_pool.take(form, x0.shape, tuning)
+            lease = _PlanLease(key, plan)
             x = x0.detach().clone()
             plan.run_ckpt(x, coeffs, T, ckpt_every, power)
-            ctx.plan = plan
+            ctx.lease = lease
             ctx.coeffs = coeffs
             ctx.T = T
             ctx.recompute = recompute
@@ -387,8 +490,7 @@ def _stencil_fn():
             g = g.contiguous()
             gx = torch.empty_like(g)
             gp = torch.empty_like(g) if ctx.has_power else None
-            ctx.plan.adjoint(g, ctx.coeffs, ctx.T, gx, gp, power if ctx.has_power else None, ctx.recompute)
-            ctx.plan.close()
+            ctx.lease.plan.adjoint(g, ctx.coeffs, ctx.T, gx, gp, power if ctx.has_power else None, ctx.recompute)
             return gx, gp, None, None, None, None, None, None
 
     return StencilFn
@@ -405,14 +507,19 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
-def run_batched(grids, coeffs_list, steps, stream=None, cache=None):
-    """Run grids[i] (device tensors, 2D or 3D, diffusion) for steps[i] steps each, in one
-    persistent launch captured in a HIP graph.  Pass the returned cache back to replay."""
+def _batch_items(grids, coeffs_list, steps):
     items = []
     for x, c, T in zip(grids, coeffs_list, steps):
         _check_tensor(x, "grid")
         ndim, nx, ny, nz = _dims(x)
         items.append(BatchItem(DIFFUSION, ndim, nx, ny, nz, x.data_ptr(), None, make_coeffs(c), int(T)))
+    return items
+
+
+def run_batched(grids, coeffs_list, steps, stream=None, cache=None):
+    """Run grids[i] (device tensors, 2D or 3D, diffusion) for steps[i] steps each, in one
+    persistent launch captured in a HIP graph.  Pass the returned cache back to replay."""
+    items = _batch_items(grids, coeffs_list, steps)
     if cache is None:
         cache = ctypes.c_void_p()
     return stencil_run_batched(items, stream, cache)

@@ -44,14 +44,35 @@ struct BItem {
   int g, p, tile, keff;
 };
 
-// Every lane of the wave spins on the same flag with relaxed agent-scope loads; the loaded
-// value is made wave-uniform (readfirstlane) so that the loop exit is a scalar branch.  One
-// acquire fence after all of an item's waits (wait_neighbours) orders the item's reads after
-// the producers' release stores.
-__device__ __forceinline__ void wait_flag(const int* f, int want) {
-  for (;;) {
+// Arguments of the persistent kernels.  err is a sticky flag (0 = no failure) that a wait
+// sets when it gives up; spin_limit bounds the polls of one wait.
+struct BLaunch {
+  const BGrid* grids;
+  const BItem* items;
+  int nitems;
+  int* counter;
+  int* flags;
+  int* err;
+  int spin_limit;
+};
+
+// Every lane of the wave polls the same flag with relaxed agent-scope loads; the loaded value
+// is made wave-uniform (readfirstlane) so that the loop exit is a scalar branch.  One acquire
+// fence after all of an item's waits (wait_neighbours) orders the item's reads after the
+// producers' release stores.  A wait is bounded: after spin_limit unsuccessful polls (about a
+// microsecond each), or as soon as another wave has given up, it sets the sticky error flag
+// and returns, so a scheduling fault ends the launch with an error instead of a hang (the
+// item then runs on whatever its inputs hold; the host reports the error).
+__device__ __forceinline__ void wait_flag(const int* f, int want, const BLaunch& L) {
+  for (int n = 0;; ++n) {
     const int v = __builtin_amdgcn_readfirstlane(__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    if (v >= want) break;
+    if (v >= want) return;
+    const int e = __builtin_amdgcn_readfirstlane(__hip_atomic_load(L.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (e != 0) return;
+    if (n >= L.spin_limit) {
+      __hip_atomic_store(L.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
     __builtin_amdgcn_s_sleep(2);
   }
 }
@@ -67,26 +88,25 @@ __device__ __forceinline__ int wave_claim(int* counter) {
   return __builtin_amdgcn_readfirstlane(atomicAdd(counter, lane == 0 ? 1 : 0));
 }
 
-__device__ __forceinline__ void wait_neighbours(const int* flags, int off, int tx, int ty, int ntx, int nty, int p) {
+__device__ __forceinline__ void wait_neighbours(const BLaunch& L, int off, int tx, int ty, int ntx, int nty, int p) {
   if (p == 0) return;
   for (int dy = -1; dy <= 1; ++dy)
     for (int dx = -1; dx <= 1; ++dx) {
       const int x = tx + dx, y = ty + dy;
       if (x < 0 || y < 0 || x >= ntx || y >= nty) continue;
-      wait_flag(flags + off + y * ntx + x, p);
+      wait_flag(L.flags + off + y * ntx + x, p, L);
     }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
-__global__ __launch_bounds__(64) void batched2d_kernel(const BGrid* __restrict__ grids, const BItem* __restrict__ items,
-                                                       int nitems, int* counter, int* flags) {
+__global__ __launch_bounds__(64) void batched2d_kernel(BLaunch L) {
   for (;;) {
-    const int it = wave_claim(counter);
-    if (it >= nitems) break;
-    const BItem w = items[it];
-    const BGrid& g = grids[w.g];
+    const int it = wave_claim(L.counter);
+    if (it >= L.nitems) break;
+    const BItem w = L.items[it];
+    const BGrid& g = L.grids[w.g];
     const int tx = w.tile % g.ntx, ty = w.tile / g.ntx;
-    wait_neighbours(flags, g.flag_off, tx, ty, g.ntx, g.nseg, w.p);
+    wait_neighbours(L, g.flag_off, tx, ty, g.ntx, g.nseg, w.p);
     Tb2dArgs a;
     a.src = g.buf[w.p & 1];
     a.dst = g.buf[(w.p + 1) & 1];
@@ -96,36 +116,35 @@ __global__ __launch_bounds__(64) void batched2d_kernel(const BGrid* __restrict__
     a.cs = g.cs; a.kr = g.kr; a.ntx = g.ntx; a.seg = g.seg; a.nseg = g.nseg;
     a.aligned = g.aligned;
     a.part = 0; a.ix0 = a.ix1 = a.iy0 = a.iy1 = 0;
+    a.ylo = 0; a.yhi = g.ny;
     a.cf = g.cf;
     {
       Tb2dTile<kBatchK2, kTb2dV, false, false, false, false> t(a, threadIdx.x, nullptr);
       t.process(w.tile);
     }
     // all lanes publish the same flag value (release orders the wave's stores before it)
-    st_release(flags + g.flag_off + w.tile, w.p + 1);
+    st_release(L.flags + g.flag_off + w.tile, w.p + 1);
   }
 }
 
-__global__ __launch_bounds__(64 * kBatchNW3) void batched3d_kernel(const BGrid* __restrict__ grids,
-                                                                 const BItem* __restrict__ items, int nitems,
-                                                                 int* counter, int* flags) {
+__global__ __launch_bounds__(64 * kBatchNW3) void batched3d_kernel(BLaunch L) {
   __shared__ __align__(16) float hal[2 * kBatchK3 * kBatchNW3 * 2 * 64 * kTb3dV];
   __shared__ int sh;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (;;) {
-    if (wave == 0) sh = wave_claim(counter);  // wave-uniform branch
+    if (wave == 0) sh = wave_claim(L.counter);  // wave-uniform branch
     __syncthreads();
     const int it = __builtin_amdgcn_readfirstlane(sh);
     __syncthreads();
-    if (it >= nitems) break;
-    const BItem w = items[it];
-    const BGrid& g = grids[w.g];
+    if (it >= L.nitems) break;
+    const BItem w = L.items[it];
+    const BGrid& g = L.grids[w.g];
     const int tx = w.tile % g.ntx, rest = w.tile / g.ntx, ty = rest % g.nty, tz = rest / g.nty;
     if (w.p > 0) {
       for (int dz = -1; dz <= 1; ++dz) {
         const int z = tz + dz;
         if (z < 0 || z >= g.nsegz) continue;
-        wait_neighbours(flags, g.flag_off + z * g.ntx * g.nty, tx, ty, g.ntx, g.nty, w.p);
+        wait_neighbours(L, g.flag_off + z * g.ntx * g.nty, tx, ty, g.ntx, g.nty, w.p);
       }
     }
     Tb3dArgs a;
@@ -139,6 +158,7 @@ __global__ __launch_bounds__(64 * kBatchNW3) void batched3d_kernel(const BGrid* 
     a.nwork = 0;
     a.ax = g.ax; a.ay = g.ay; a.fx = g.fx; a.fy = g.fy;
     a.aligned = g.aligned;
+    a.zlo = 0; a.zhi = g.nz;
     a.cf = g.cf;
     {
       Tb3dTile<kBatchK3, kTb3dV, kBatchR3, kBatchNW3, false, false, false, false> t(a, threadIdx.x & 63, threadIdx.x >> 6,
@@ -146,14 +166,16 @@ __global__ __launch_bounds__(64 * kBatchNW3) void batched3d_kernel(const BGrid* 
       t.process(w.tile);
     }
     __syncthreads();  // every wave's stores of this item precede wave 0's release
-    if (wave == 0) st_release(flags + g.flag_off + w.tile, w.p + 1);
+    if (wave == 0) st_release(L.flags + g.flag_off + w.tile, w.p + 1);
   }
 }
 
-__global__ void reset_kernel(int* flags, int nflags, int* counters) {
+// Clears the pass flags and the two claim counters before a launch; clear_err also clears
+// the error flag (counters[2]), which the graph path keeps sticky across replays.
+__global__ void reset_kernel(int* flags, int nflags, int* counters, int clear_err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nflags) flags[i] = 0;
-  if (i < 2) counters[i] = 0;
+  if (i < 2 || (clear_err && i == 2)) counters[i] = 0;
 }
 
 }  // namespace
@@ -163,11 +185,11 @@ struct stencil_batch_s {
   int device = 0;
   std::vector<stencil_batch_item_t> items;  // what was captured
   std::vector<float*> scratch;
-  BGrid* d_grids = nullptr;
-  BItem* d_items2 = nullptr;
-  BItem* d_items3 = nullptr;
-  int* d_flags = nullptr;
-  int* d_counters = nullptr;
+  void* d_mem = nullptr;  // grid table, work lists, flags and counters (layout of BLayout)
+  size_t err_off = 0;       // byte offset of the error flag in d_mem
+  int* err_host = nullptr;  // pinned copy of the error flag after the latest replay
+  hipEvent_t done = nullptr;
+  bool launched = false;
   int n2 = 0, n3 = 0, nflags = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -177,16 +199,82 @@ using namespace stn;
 
 namespace {
 
+// Everything the persistent kernels need, planned on the host before it is placed in device
+// memory (allocated by the graph path).
+struct BPlan {
+  std::vector<BGrid> grids;
+  std::vector<BItem> it2, it3;
+  int nflags = 0;
+  int g2 = 1, g3 = 1;  // persistent workgroups of the 2D and 3D launches
+  std::vector<int> passes, ntiles, seg;
+};
+
+// Byte offsets of the device tables of a plan, in one block.
+struct BLayout {
+  size_t grids, items2, items3, flags, counters, total;
+};
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+BLayout layout_of(const BPlan& P) {
+  BLayout L;
+  L.grids = 0;
+  L.items2 = align256(L.grids + sizeof(BGrid) * P.grids.size());
+  L.items3 = align256(L.items2 + sizeof(BItem) * P.it2.size());
+  L.flags = align256(L.items3 + sizeof(BItem) * P.it3.size());
+  L.counters = align256(L.flags + sizeof(int) * (size_t)P.nflags);
+  L.total = align256(L.counters + sizeof(int) * 4);
+  return L;
+}
+
+// The host image of the tables (grid table, work lists; the flags and counters are cleared by
+// the reset kernel), laid out as layout_of says, up to L.flags.
+std::vector<unsigned char> table_image(const BPlan& P, const BLayout& L) {
+  std::vector<unsigned char> img(L.flags, 0);
+  if (!P.grids.empty()) std::memcpy(img.data() + L.grids, P.grids.data(), sizeof(BGrid) * P.grids.size());
+  if (!P.it2.empty()) std::memcpy(img.data() + L.items2, P.it2.data(), sizeof(BItem) * P.it2.size());
+  if (!P.it3.empty()) std::memcpy(img.data() + L.items3, P.it3.data(), sizeof(BItem) * P.it3.size());
+  return img;
+}
+
+// Kernel arguments of the two persistent launches over tables based at `base`.
+void launch_args(const BPlan& P, const BLayout& L, unsigned char* base, int spin_limit, BLaunch* a2, BLaunch* a3) {
+  int* counters = reinterpret_cast<int*>(base + L.counters);
+  int* flags = reinterpret_cast<int*>(base + L.flags);
+  const BGrid* grids = reinterpret_cast<const BGrid*>(base + L.grids);
+  *a2 = BLaunch{grids, reinterpret_cast<const BItem*>(base + L.items2), (int)P.it2.size(), counters, flags,
+                counters + 2, spin_limit};
+  *a3 = BLaunch{grids, reinterpret_cast<const BItem*>(base + L.items3), (int)P.it3.size(), counters + 1, flags,
+                counters + 2, spin_limit};
+}
+
+// Polls one wait may make before it gives up (about a microsecond each, so tens of seconds):
+// far longer than any dependency of a real batch.  STENCIL_DEBUG_SPIN_LIMIT overrides it, so
+// tests can make every unsatisfied wait give up at once and check the error path.
+int spin_limit() {
+  const char* v = std::getenv("STENCIL_DEBUG_SPIN_LIMIT");
+  if (v && *v) return std::max(0, std::atoi(v));
+  return 1 << 25;
+}
+
+// Enqueue the reset and the two persistent kernels on stream s.
+hipError_t enqueue_launch(const BPlan& P, const BLayout& L, unsigned char* base, int clear_err, hipStream_t s) {
+  BLaunch a2, a3;
+  launch_args(P, L, base, spin_limit(), &a2, &a3);
+  const int nr = std::max(P.nflags, 3);
+  hipLaunchKernelGGL(reset_kernel, dim3((nr + 255) / 256), dim3(256), 0, s, a2.flags, P.nflags,
+                     reinterpret_cast<int*>(base + L.counters), clear_err);
+  if (!P.it2.empty()) hipLaunchKernelGGL(batched2d_kernel, dim3(P.g2), dim3(64), 0, s, a2);
+  if (!P.it3.empty()) hipLaunchKernelGGL(batched3d_kernel, dim3(P.g3), dim3(64 * kBatchNW3), 0, s, a3);
+  return hipGetLastError();
+}
+
 void release(stencil_batch_s* b) {
   if (!b) return;
   if (b->exec) hipGraphExecDestroy(b->exec);
   if (b->graph) hipGraphDestroy(b->graph);
   for (float* s : b->scratch) hipFree(s);
-  hipFree(b->d_grids);
-  hipFree(b->d_items2);
-  hipFree(b->d_items3);
-  hipFree(b->d_flags);
-  hipFree(b->d_counters);
+  hipFree(b->d_mem);
+  if (b->err_host) hipHostFree(b->err_host);
+  if (b->done) hipEventDestroy(b->done);
   delete b;
 }
 
@@ -213,7 +301,6 @@ std::vector<int> even_split(int T, int kcap) {
   return v;
 }
 
-// The persistent 3D kernel keeps the uniform tiling (its tile decoding has no edge-flush case).
 // Whether, along one axis, every tile's window reads only cells that its own tile and its two
 // neighbours output: an item waits only for those neighbours of the previous pass.  Tile
 // ranges follow the kernel's edge-flush tiling (flush = 1) or uniform tiling (flush = 0).
@@ -303,38 +390,31 @@ std::vector<int> choose_segments(const std::vector<int>& idx, const std::vector<
   return seg;
 }
 
-stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t stream, stencil_batch_s** out) {
-  stencil_batch_s* b = new stencil_batch_s();
-  b->stream = stream;
-  hipGetDevice(&b->device);
-  b->items.assign(items, items + n);
-  std::vector<BGrid> grids(n);
+// Plan a batch: per-grid pass split and tiling, the flag offsets and the two work lists in
+// claim order.  partners[i] is grid i's ping-pong partner (device, same size as the grid).
+BPlan plan_batch(int n, const stencil_batch_item_t* items, float* const* partners) {
+  BPlan P;
+  P.grids.resize(n);
   std::vector<std::vector<int>> steps(n);
-  std::vector<int> ntiles(n), passes(n), len(n);
+  P.ntiles.assign(n, 0);
+  P.passes.assign(n, 0);
+  P.seg.assign(n, 0);
+  std::vector<int> len(n);
   std::vector<int> idx2, idx3;
-  int nflags = 0;
   for (int i = 0; i < n; ++i) {
     const stencil_batch_item_t& it = items[i];
-    BGrid& g = grids[i];
+    BGrid& g = P.grids[i];
     std::memset(&g, 0, sizeof(g));
     g.nx = it.nx; g.ny = it.ny; g.nz = it.ndim == 3 ? it.nz : 1;
     g.cf = dev_coef(it.coeffs, false);
-    const size_t cells = (size_t)g.nx * g.ny * g.nz;
-    float* s = nullptr;
-    if (hipMalloc(&s, cells * sizeof(float)) != hipSuccess) {
-      hipGetLastError();
-      release(b);
-      return fail(STENCIL_ERR_OUT_OF_MEMORY, "batch scratch allocation failed");
-    }
-    b->scratch.push_back(s);
     g.buf[0] = it.grid;
-    g.buf[1] = s;
+    g.buf[1] = partners[i];
     // The persistent kernels fuse up to kBatchK2 (2D) / kBatchK3 (3D) steps per pass, and a
     // pass costs the same for any number of fused steps up to that (levels past keff forward
     // their input), so each grid takes the fewest passes (even, so the result lands in its own
     // buffer), with the steps spread evenly over them.
     steps[i] = even_split(it.T, it.ndim == 2 ? kBatchK2 : kBatchK3);
-    passes[i] = (int)steps[i].size();
+    P.passes[i] = (int)steps[i].size();
     len[i] = it.ndim == 2 ? g.ny : g.nz;
     (it.ndim == 2 ? idx2 : idx3).push_back(i);
   }
@@ -345,25 +425,26 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
   hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ3, batched3d_kernel, 64 * kBatchNW3, 0);
   const int slots2 = d.cus * std::max(1, occ2), slots3 = d.cus * std::max(1, occ3);
   auto geom2 = [&](int i, int sg) {
-    const Geom2D gg = geom2d(kBatchK2, grids[i].nx, grids[i].ny, sg);
+    const Geom2D gg = geom2d(kBatchK2, P.grids[i].nx, P.grids[i].ny, sg);
     return std::make_pair(gg.ntx * gg.nseg, gg);
   };
   auto geom3 = [&](int i, int sz) {
-    const Geom3D gg = batch_geom3d(grids[i], sz);
+    const Geom3D gg = batch_geom3d(P.grids[i], sz);
     return std::make_pair(gg.ntx * gg.nty * gg.nsegz, gg);
   };
-  const std::vector<int> seg2 = choose_segments(idx2, passes, len, {512, 384, 256, 192, 128, 96, 64, 48}, slots2,
+  const std::vector<int> seg2 = choose_segments(idx2, P.passes, len, {512, 384, 256, 192, 128, 96, 64, 48}, slots2,
                                                 geom2, item_work2d);
-  const std::vector<int> seg3 = choose_segments(idx3, passes, len, {64, 48, 32, 24, 16, 12, 8}, slots3, geom3,
+  const std::vector<int> seg3 = choose_segments(idx3, P.passes, len, {64, 48, 32, 24, 16, 12, 8}, slots3, geom3,
                                                 item_work3d);
   std::vector<double> t_item(n, 0.0);
   for (int i = 0; i < n; ++i) {
-    BGrid& g = grids[i];
+    BGrid& g = P.grids[i];
     if (items[i].ndim == 2) {
       const Geom2D gg = geom2d(kBatchK2, g.nx, g.ny, seg2[i]);
       g.cs = gg.cs; g.kr = gg.kr; g.ntx = gg.ntx; g.seg = gg.seg; g.nseg = gg.nseg;
       g.aligned = ((g.nx & 3) == 0) && ((reinterpret_cast<uintptr_t>(g.buf[0]) | reinterpret_cast<uintptr_t>(g.buf[1])) & 15) == 0;
-      ntiles[i] = gg.ntx * gg.nseg;
+      P.ntiles[i] = gg.ntx * gg.nseg;
+      P.seg[i] = gg.seg;
       t_item[i] = item_work2d(gg);
     } else {
       const Geom3D gg = batch_geom3d(g, seg3[i]);
@@ -371,11 +452,12 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
       g.segz = gg.segz; g.nsegz = gg.nsegz;
       g.ax = gg.ax; g.ay = gg.ay; g.fx = gg.fx; g.fy = gg.fy;
       g.aligned = ((g.nx & 1) == 0) && ((reinterpret_cast<uintptr_t>(g.buf[0]) | reinterpret_cast<uintptr_t>(g.buf[1])) & 7) == 0;
-      ntiles[i] = gg.ntx * gg.nty * gg.nsegz;
+      P.ntiles[i] = gg.ntx * gg.nty * gg.nsegz;
+      P.seg[i] = gg.segz;
       t_item[i] = item_work3d(gg);
     }
-    g.flag_off = nflags;
-    nflags += ntiles[i];
+    g.flag_off = P.nflags;
+    P.nflags += P.ntiles[i];
   }
   // Claim order: latest start time first (critical path priority).  Scheduled as late as
   // possible against the longest chain, pass p of grid g may start no later than
@@ -388,13 +470,15 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
   };
   std::vector<Keyed> k2, k3;
   double chain2 = 0.0, chain3 = 0.0;
-  for (int i = 0; i < n; ++i) (items[i].ndim == 2 ? chain2 : chain3) = std::max(
-      items[i].ndim == 2 ? chain2 : chain3, passes[i] * t_item[i]);
+  for (int i = 0; i < n; ++i) {
+    double& c = items[i].ndim == 2 ? chain2 : chain3;
+    c = std::max(c, P.passes[i] * t_item[i]);
+  }
   for (int i = 0; i < n; ++i) {
     const double chain = items[i].ndim == 2 ? chain2 : chain3;
-    for (int p = 0; p < passes[i]; ++p) {
-      const double lst = chain - (passes[i] - p) * t_item[i];
-      for (int t = 0; t < ntiles[i]; ++t) (items[i].ndim == 2 ? k2 : k3).push_back({lst, {i, p, t, steps[i][p]}});
+    for (int p = 0; p < P.passes[i]; ++p) {
+      const double lst = chain - (P.passes[i] - p) * t_item[i];
+      for (int t = 0; t < P.ntiles[i]; ++t) (items[i].ndim == 2 ? k2 : k3).push_back({lst, {i, p, t, steps[i][p]}});
     }
   }
   auto order = [](const Keyed& x, const Keyed& y) {
@@ -405,43 +489,69 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
   };
   std::stable_sort(k2.begin(), k2.end(), order);
   std::stable_sort(k3.begin(), k3.end(), order);
-  std::vector<BItem> it2, it3;
-  for (const Keyed& x : k2) it2.push_back(x.it);
-  for (const Keyed& x : k3) it3.push_back(x.it);
-  b->n2 = (int)it2.size();
-  b->n3 = (int)it3.size();
-  b->nflags = nflags;
-  hipError_t e = hipSuccess;
-  e = hipMalloc(&b->d_grids, sizeof(BGrid) * std::max(1, n));
-  if (e == hipSuccess) e = hipMalloc(&b->d_items2, sizeof(BItem) * std::max(1, b->n2));
-  if (e == hipSuccess) e = hipMalloc(&b->d_items3, sizeof(BItem) * std::max(1, b->n3));
-  if (e == hipSuccess) e = hipMalloc(&b->d_flags, sizeof(int) * std::max(1, nflags));
-  if (e == hipSuccess) e = hipMalloc(&b->d_counters, sizeof(int) * 2);
-  if (e == hipSuccess && n) e = hipMemcpy(b->d_grids, grids.data(), sizeof(BGrid) * n, hipMemcpyHostToDevice);
-  if (e == hipSuccess && b->n2) e = hipMemcpy(b->d_items2, it2.data(), sizeof(BItem) * b->n2, hipMemcpyHostToDevice);
-  if (e == hipSuccess && b->n3) e = hipMemcpy(b->d_items3, it3.data(), sizeof(BItem) * b->n3, hipMemcpyHostToDevice);
+  for (const Keyed& x : k2) P.it2.push_back(x.it);
+  for (const Keyed& x : k3) P.it3.push_back(x.it);
+  // persistent grid sizes: resident capacity of the device
+  P.g2 = std::max(1, std::min((int)P.it2.size(), slots2));
+  P.g3 = std::max(1, std::min((int)P.it3.size(), slots3));
+  return P;
+}
+
+void log_plan(int n, const stencil_batch_item_t* items, const BPlan& P, const char* how) {
+  if (!log_enabled()) return;
+  std::fprintf(stderr, "[stencil] batch (%s): %d grids, %zu 2D items (%d WGs), %zu 3D items (%d WGs)\n", how, n,
+               P.it2.size(), P.g2, P.it3.size(), P.g3);
+  for (int i = 0; i < n; ++i)
+    std::fprintf(stderr, "[stencil]   grid %d: %dD %dx%dx%d T=%d passes=%d tiles=%d seg=%d\n", i, items[i].ndim,
+                 items[i].nx, items[i].ny, items[i].nz, items[i].T, P.passes[i], P.ntiles[i], P.seg[i]);
+}
+
+// Graph path: plan-owned partner grids and tables, captured once.
+stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t stream, stencil_batch_s** out) {
+  stencil_batch_s* b = new stencil_batch_s();
+  b->stream = stream;
+  hipGetDevice(&b->device);
+  b->items.assign(items, items + n);
+  for (int i = 0; i < n; ++i) {
+    const stencil_batch_item_t& it = items[i];
+    const size_t cells = (size_t)it.nx * it.ny * (it.ndim == 3 ? it.nz : 1);
+    float* s = nullptr;
+    if (hipMalloc(&s, cells * sizeof(float)) != hipSuccess) {
+      hipGetLastError();
+      release(b);
+      return fail(STENCIL_ERR_OUT_OF_MEMORY, "batch scratch allocation failed");
+    }
+    b->scratch.push_back(s);
+  }
+  const BPlan P = plan_batch(n, items, b->scratch.data());
+  const BLayout L = layout_of(P);
+  b->n2 = (int)P.it2.size();
+  b->n3 = (int)P.it3.size();
+  b->nflags = P.nflags;
+  b->err_off = L.counters + 2 * sizeof(int);
+  const std::vector<unsigned char> img = table_image(P, L);
+  hipError_t e = hipMalloc(&b->d_mem, L.total);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->err_host), sizeof(int));
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+  if (e == hipSuccess && !img.empty()) e = hipMemcpy(b->d_mem, img.data(), img.size(), hipMemcpyHostToDevice);
+  // the error flag is cleared once here and stays set across replays once a wait gives up
+  unsigned char* base = static_cast<unsigned char*>(b->d_mem);
+  if (e == hipSuccess) e = launch_fill_int(reinterpret_cast<int*>(base + L.counters), 4, 0, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
     stencil_status_t st = hip_fail(e, "batch setup");
     release(b);
     return st;
   }
-  // persistent grid sizes: resident capacity of the device
-  const int g2 = std::max(1, std::min(b->n2, slots2));
-  const int g3 = std::max(1, std::min(b->n3, slots3));
+  if (b->err_host) *b->err_host = 0;
   // capture: reset flags/counters, then the two persistent kernels
   hipStream_t cs = nullptr;
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    const int nr = std::max(nflags, 2);
-    hipLaunchKernelGGL(reset_kernel, dim3((nr + 255) / 256), dim3(256), 0, cs, b->d_flags, nflags, b->d_counters);
-    if (b->n2)
-      hipLaunchKernelGGL(batched2d_kernel, dim3(g2), dim3(64), 0, cs, b->d_grids, b->d_items2, b->n2, b->d_counters,
-                         b->d_flags);
-    if (b->n3)
-      hipLaunchKernelGGL(batched3d_kernel, dim3(g3), dim3(64 * kBatchNW3), 0, cs, b->d_grids, b->d_items3, b->n3,
-                         b->d_counters + 1, b->d_flags);
+    const hipError_t le = enqueue_launch(P, L, base, 0, cs);
     e = hipStreamEndCapture(cs, &b->graph);
+    if (e == hipSuccess) e = le;
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
   if (cs) hipStreamDestroy(cs);
@@ -450,24 +560,12 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
     release(b);
     return st;
   }
-  if (log_enabled()) {
-    std::fprintf(stderr, "[stencil] batch: %d grids, %d 2D items (%d WGs), %d 3D items (%d WGs)\n", n, b->n2, g2,
-                 b->n3, g3);
-    for (int i = 0; i < n; ++i)
-      std::fprintf(stderr, "[stencil]   grid %d: %dD %dx%dx%d T=%d passes=%d tiles=%d seg=%d\n", i, items[i].ndim,
-                   items[i].nx, items[i].ny, items[i].nz, items[i].T, passes[i], ntiles[i],
-                   items[i].ndim == 2 ? grids[i].seg : grids[i].segz);
-  }
+  log_plan(n, items, P, "graph");
   *out = b;
   return STENCIL_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-stencil_status_t stencil_run_batched(int n, const stencil_batch_item_t* items, void* hip_stream,
-                                     stencil_batch_t* graph_cache) {
+stencil_status_t check_items(int n, const stencil_batch_item_t* items) {
   if (n < 0 || (n > 0 && !items)) return fail(STENCIL_ERR_INVALID_ARG, "invalid item list");
   for (int i = 0; i < n; ++i) {
     const stencil_batch_item_t& it = items[i];
@@ -484,32 +582,73 @@ stencil_status_t stencil_run_batched(int n, const stencil_batch_item_t* items, v
     for (int j = 0; j < i; ++j)
       if (items[j].grid == it.grid) return fail(STENCIL_ERR_INVALID_ARG, "items share a grid");
   }
+  return STENCIL_OK;
+}
+
+// Error of the latest replay of b that has completed, if any (non-blocking).
+stencil_status_t replay_status(stencil_batch_s* b, bool wait) {
+  if (!b->launched) return STENCIL_OK;
+  if (wait) {
+    hipError_t e = hipEventSynchronize(b->done);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  } else if (hipEventQuery(b->done) != hipSuccess) {
+    hipGetLastError();  // hipErrorNotReady: the latest replay is still running
+    return STENCIL_OK;
+  }
+  if (*b->err_host)
+    return fail(STENCIL_ERR_INTERNAL, "a dependency wait of the batched launch exceeded its bound (the results are invalid)");
+  return STENCIL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+stencil_status_t stencil_run_batched(int n, const stencil_batch_item_t* items, void* hip_stream,
+                                     stencil_batch_t* graph_cache) {
+  stencil_status_t st = check_items(n, items);
+  if (st != STENCIL_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   stencil_batch_s* b = nullptr;
   if (graph_cache && *graph_cache) {
     b = *graph_cache;
     if (!same_items(b, n, items))
       return fail(STENCIL_ERR_INVALID_ARG, "cached batch was built from different items");
+    st = replay_status(b, false);
+    if (st != STENCIL_OK) return st;
   } else {
-    stencil_status_t st = build(n, items, s, &b);
+    st = build(n, items, s, &b);
     if (st != STENCIL_OK) return st;
     if (graph_cache) *graph_cache = b;
   }
   hipError_t e = hipGraphLaunch(b->exec, s);
+  // the error flag of this replay goes to pinned host memory, read once the replay is done
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->err_host, static_cast<unsigned char*>(b->d_mem) + b->err_off, sizeof(int),
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipEventRecord(b->done, s);
   if (e != hipSuccess) {
-    stencil_status_t st = hip_fail(e, "hipGraphLaunch");
+    st = hip_fail(e, "hipGraphLaunch");
     if (!graph_cache) {
       hipStreamSynchronize(s);
       release(b);
     }
     return st;
   }
+  b->launched = true;
   if (!graph_cache) {
-    e = hipStreamSynchronize(s);
+    st = replay_status(b, true);
     release(b);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return st;
   }
   return STENCIL_OK;
+}
+
+stencil_status_t stencil_batch_sync(stencil_batch_t b) {
+  if (!b) return fail(STENCIL_ERR_INVALID_ARG, "batch is NULL");
+  hipError_t e = hipSetDevice(b->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return replay_status(b, true);
 }
 
 void stencil_batch_destroy(stencil_batch_t b) {

@@ -332,7 +332,9 @@ int inst_k_for(int ndim, KMode m, int k) {
 // rows (with the keff-row halo) stay clear of the first and last grid row, i.e. the tiles for
 // which the kernel takes its edge-free body.  Both conditions are per axis, so those tiles form
 // a rectangle [*x0, *x1) x [*y0, *y1) of tile indices (empty if x0 >= x1 or y0 >= y1).
-void interior_rect2d(const Geom2D& g, int nx, int ny, int keff, int* x0, int* x1, int* y0, int* y1) {
+// Segments cover the output rows [ylo, yhi).
+void interior_rect2d(const Geom2D& g, int nx, int ny, int keff, int ylo, int yhi, int* x0, int* x1, int* y0,
+                     int* y1) {
   const int W = 64 * kTb2dV;
   *x0 = g.ntx; *x1 = 0; *y0 = g.nseg; *y1 = 0;
   for (int tx = 0; tx < g.ntx; ++tx) {
@@ -340,7 +342,7 @@ void interior_rect2d(const Geom2D& g, int nx, int ny, int keff, int* x0, int* x1
     if (ws >= 0 && ws + W <= nx) { *x0 = std::min(*x0, tx); *x1 = std::max(*x1, tx + 1); }
   }
   for (int sg = 0; sg < g.nseg; ++sg) {
-    const int r0 = sg * g.seg, r1 = std::min(r0 + g.seg, ny);
+    const int r0 = ylo + sg * g.seg, r1 = std::min(r0 + g.seg, yhi);
     if (r0 - keff > 0 && r1 + keff < ny) { *y0 = std::min(*y0, sg); *y1 = std::max(*y1, sg + 1); }
   }
 }
@@ -357,20 +359,26 @@ hipError_t run_star_pass(const stencil_plan_s* p, int K, int keff, const float* 
   return launch_star2d(p->rad, K, a, p->stream);
 }
 
+// One pass of keff fused steps from src to dst.  Output cells along the streamed axis (y in
+// 2D, z in 3D) are [lo, hi); hi < 0 means every cell (a slab pass narrows it to its interior).
 hipError_t run_pass(const stencil_plan_s* p, KMode m, int K, int keff, const float* src, float* dst,
-                    const float* power, float* gp, const DevCoef& cf) {
+                    const float* power, float* gp, const DevCoef& cf, int lo = 0, int hi = -1) {
   if (m == KM_STAR) return run_star_pass(p, K, keff, src, dst);
   const bool full = (keff == K);
   if (p->ndim == 2) {
-    const Geom2D g = geom2d(K, p->nx, p->ny, p->tuning.seg_len);
+    if (hi < 0) hi = p->ny;
+    const Geom2D g = geom2d(K, p->nx, hi - lo, p->tuning.seg_len);
     Tb2dArgs a;
     a.src = src; a.dst = dst; a.power = power; a.gp = gp;
     a.nx = p->nx; a.ny = p->ny; a.keff = keff;
     a.cs = g.cs; a.kr = g.kr; a.ntx = g.ntx; a.seg = g.seg; a.nseg = g.nseg;
-    a.aligned = ((p->nx & 3) == 0) && aligned16(src) && aligned16(dst) && (!power || aligned16(power)) ? 1 : 0;
+    a.aligned = ((p->nx & 3) == 0) && aligned16(src) && aligned16(dst) && (!power || aligned16(power)) &&
+                (!gp || aligned16(gp)) ? 1 : 0;
     a.cf = cf;
     a.part = 0;
-    interior_rect2d(g, p->nx, p->ny, keff, &a.ix0, &a.ix1, &a.iy0, &a.iy1);
+    a.ylo = lo;
+    a.yhi = hi;
+    interior_rect2d(g, p->nx, p->ny, keff, lo, hi, &a.ix0, &a.ix1, &a.iy0, &a.iy1);
     const long interior = (a.ix1 > a.ix0 && a.iy1 > a.iy0) ? (long)(a.ix1 - a.ix0) * (a.iy1 - a.iy0) : 0;
     const long total = (long)g.ntx * g.nseg;
     // Split when the interior kernel has enough tiles to fill the device and some tiles are
@@ -394,7 +402,10 @@ hipError_t run_pass(const stencil_plan_s* p, KMode m, int K, int keff, const flo
     return hipStreamWaitEvent(p->stream, p->ev_join, 0);
   }
   const bool adj = (m == KM_ADJ || m == KM_ADJ_ACC);
-  const Geom3D g = geom3d(K, adj, p->nx, p->ny, p->nz, p->tuning.seg_len);
+  if (hi < 0) hi = p->nz;
+  Geom3D g = geom3d(K, adj, p->nx, p->ny, p->nz, p->tuning.seg_len);
+  g.segz = std::max(1, std::min(g.segz, hi - lo));
+  g.nsegz = ceil_div(hi - lo, g.segz);
   Tb3dArgs a;
   a.src = src; a.dst = dst; a.power = power; a.gp = gp;
   a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.keff = keff;
@@ -402,7 +413,12 @@ hipError_t run_pass(const stencil_plan_s* p, KMode m, int K, int keff, const flo
   a.segz = g.segz; a.nsegz = g.nsegz;
   a.ax = g.ax; a.ay = g.ay; a.fx = g.fx; a.fy = g.fy;
   a.nwork = p->nwork3d;
-  a.aligned = ((p->nx & 1) == 0) && ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 7) == 0 ? 1 : 0;
+  // 8-byte vector accesses of the field, the power map (hotspot) and grad_p (adjoint)
+  const uintptr_t bits = reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst) |
+                         reinterpret_cast<uintptr_t>(power) | reinterpret_cast<uintptr_t>(gp);
+  a.aligned = ((p->nx & 1) == 0) && (bits & 7) == 0 ? 1 : 0;
+  a.zlo = lo;
+  a.zhi = hi;
   a.cf = cf;
   return launch_tb3d(K, m, full, a, p->stream);
 }
@@ -1128,6 +1144,44 @@ stencil_status_t stencil_run_ckpt(stencil_plan_t plan, float* grid, const float*
   return forward(plan, grid, power, coeffs, T, ckpt_every, true);
 }
 
+stencil_status_t stencil_run_slab(stencil_plan_t p, const float* src, float* dst, const float* power,
+                                  const stencil_coeffs_t* coeffs, int T, int ghost_lo, int ghost_hi) {
+  stencil_status_t st = check_plan(p);
+  if (st != STENCIL_OK) return st;
+  if (p->star) return fail(STENCIL_ERR_UNSUPPORTED, "no slab pass for radius-r star plans");
+  if (p->tuning.variant == 1) return fail(STENCIL_ERR_UNSUPPORTED, "the slab pass runs the temporal-blocked kernel");
+  if (!src || !dst || !coeffs) return fail(STENCIL_ERR_INVALID_ARG, "src, dst and coeffs are required");
+  if (src == dst) return fail(STENCIL_ERR_INVALID_ARG, "the slab pass is out of place: dst must not be src");
+  if (p->form != STENCIL_DIFFUSION && !power) return fail(STENCIL_ERR_INVALID_ARG, "hotspot needs a power map");
+  if (power && (power == dst)) return fail(STENCIL_ERR_INVALID_ARG, "power must not alias dst");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(power)) & 3)
+    return fail(STENCIL_ERR_INVALID_ARG, "buffers must be 4-byte aligned");
+  if (!coeffs_finite(*coeffs)) return fail(STENCIL_ERR_INVALID_ARG, "coefficients must be finite");
+  const int n = p->ndim == 2 ? p->ny : p->nz;  // cells along the streamed axis, ghosts included
+  if (ghost_lo < 0 || ghost_hi < 0 || ghost_lo + ghost_hi >= n)
+    return fail(STENCIL_ERR_INVALID_ARG, "ghost depths must be >= 0 and leave at least one interior plane");
+  if (T < 0) return fail(STENCIL_ERR_INVALID_ARG, "T must be >= 0");
+  if ((ghost_lo > 0 && T > ghost_lo) || (ghost_hi > 0 && T > ghost_hi))
+    return fail(STENCIL_ERR_INVALID_ARG, "T exceeds a ghost depth: each step consumes one ghost plane per face");
+  const KMode m = fwd_mode(p);
+  if (T > tb_max_k(p->ndim, m))
+    return fail(STENCIL_ERR_UNSUPPORTED, "T exceeds the largest fused step count of one pass (" +
+                                             std::to_string(tb_max_k(p->ndim, m)) + ")");
+  st = set_device(p);
+  if (st != STENCIL_OK) return st;
+  const size_t plane = p->ndim == 2 ? (size_t)p->nx : (size_t)p->nx * p->ny;
+  const int lo = ghost_lo, hi = n - ghost_hi;
+  if (T == 0) {
+    hipError_t e = hipMemcpyAsync(dst + lo * plane, src + lo * plane, (size_t)(hi - lo) * plane * sizeof(float),
+                                  hipMemcpyDeviceToDevice, p->stream);
+    return e == hipSuccess ? STENCIL_OK : hip_fail(e, "hipMemcpyAsync");
+  }
+  const DevCoef cf = dev_coef(*coeffs, false, p->form == STENCIL_HOTSPOT_PHYS);
+  const int K = inst_k_for(p->ndim, m, T);
+  hipError_t e = run_pass(p, m, K, T, src, dst, p->form != STENCIL_DIFFUSION ? power : nullptr, nullptr, cf, lo, hi);
+  return e == hipSuccess ? STENCIL_OK : hip_fail(e, "kernel launch");
+}
+
 stencil_status_t stencil_adjoint(stencil_plan_t p, const float* cot, const float* power,
                                  const stencil_coeffs_t* coeffs, int T, float* grad_x0, float* grad_power,
                                  int recompute) {
@@ -1140,6 +1194,9 @@ stencil_status_t stencil_adjoint(stencil_plan_t p, const float* cot, const float
   if (!coeffs_finite(*coeffs)) return fail(STENCIL_ERR_INVALID_ARG, "coefficients must be finite");
   if (grad_x0 == cot || grad_power == cot || (grad_power && grad_power == grad_x0))
     return fail(STENCIL_ERR_INVALID_ARG, "outputs must not alias the cotangent or each other");
+  if ((reinterpret_cast<uintptr_t>(cot) | reinterpret_cast<uintptr_t>(grad_x0) | reinterpret_cast<uintptr_t>(grad_power) |
+       reinterpret_cast<uintptr_t>(power)) & 3)
+    return fail(STENCIL_ERR_INVALID_ARG, "buffers must be 4-byte aligned");
   if (recompute != 0 && recompute != 1) return fail(STENCIL_ERR_INVALID_ARG, "recompute must be 0 or 1");
   if (recompute) {
     if (p->ckpt_T != T || p->ckpts.empty())

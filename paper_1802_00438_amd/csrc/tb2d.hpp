@@ -69,6 +69,9 @@ struct Tb2dArgs {
   // Tiles of this launch: part 0 = every tile; part 1 = the interior rectangle
   // [ix0, ix1) x [iy0, iy1) of tiles that touch no grid edge; part 2 = the frame of all others.
   int part, ix0, ix1, iy0, iy1;
+  // Output rows [ylo, yhi) of the streamed axis; tile segments start at ylo.  Every row
+  // normally; a slab pass with ghost rows stores only the rows between them.
+  int ylo, yhi;
   DevCoef cf;
 };
 
@@ -450,8 +453,8 @@ struct Tb2dTile {
     ox0 = tx * a.cs;
     ox1 = min(ox0 + a.cs, a.nx);
     ws = ox0 - a.kr;
-    y0 = sg * a.seg;
-    y1 = min(y0 + a.seg, a.ny);
+    y0 = a.ylo + sg * a.seg;
+    y1 = min(y0 + a.seg, a.yhi);
     const bool xe = (ws < 0) || (ws + W > a.nx);
     const int keff = FULL ? K : a.keff;
     const bool ye = (y0 - keff <= 0) || (y1 + keff >= a.ny);

@@ -49,6 +49,9 @@ struct Tb3dArgs {
   // cells from it; the tiles between output csx (csy) cells each.  0: uniform tiling.
   int ax, ay, fx, fy;
   int aligned;         // 1: nx even and 8-byte aligned buffers (vector access in interior tiles)
+  // Output planes [zlo, zhi); tiles (and balanced shares) cover only them.  Every plane
+  // normally; a slab pass with ghost planes stores only the planes between them.
+  int zlo, zhi;
   DevCoef cf;
 };
 
@@ -451,7 +454,7 @@ struct Tb3dTile {
     const int rest = tile / a.ntx;
     const int ty = rest % a.nty;
     const int tz = rest / a.nty;
-    process_column(tx, ty, tz * a.segz, min(tz * a.segz + a.segz, a.nz));
+    process_column(tx, ty, a.zlo + tz * a.segz, min(a.zlo + tz * a.segz + a.segz, a.zhi));
   }
 
   // Output planes [zs, ze) of the x-y column (tx, ty).
@@ -532,14 +535,15 @@ __global__ __launch_bounds__(64 * NW) void tb3d_kernel(Tb3dArgs a) {
     return;
   }
   const int w = xcd_remap(blockIdx.x, a.nwork);
-  const long long units = (long long)a.ntx * a.nty * a.nz;
+  const int nzo = a.zhi - a.zlo;  // output planes per column
+  const long long units = (long long)a.ntx * a.nty * nzo;
   long long u = units * w / a.nwork;
   const long long u1 = units * (w + 1) / a.nwork;
   while (u < u1) {
-    const int col = (int)(u / a.nz);
-    const int zs = (int)(u - (long long)col * a.nz);
-    const int ze = (int)min((long long)a.nz, zs + (u1 - u));
-    t.process_column(col % a.ntx, col / a.ntx, zs, ze);
+    const int col = (int)(u / nzo);
+    const int zs = (int)(u - (long long)col * nzo);
+    const int ze = (int)min((long long)nzo, zs + (u1 - u));
+    t.process_column(col % a.ntx, col / a.ntx, a.zlo + zs, a.zlo + ze);
     u += ze - zs;
   }
 }

@@ -127,8 +127,13 @@ def test_hotspot3d_256_adjoint_full_size():
     lin = cf.copy()
     lin[7:] = 0.0
     ref_x = oracle.forward(gh, lin, wl.T, form=DIFFUSION, dtype=np.float32)
-    assert np.max(np.abs(gxh - ref_x)) / np.max(np.abs(ref_x)) <= TOL
     src = cf.copy()
     src[8] = 0.0  # no ambient term: the source is cp * g
     ref_p = oracle.forward(np.zeros_like(gh), src, wl.T, power=gh, form=HOTSPOT, dtype=np.float32)
-    assert np.max(np.abs(gph - ref_p)) / np.max(np.abs(ref_p)) <= TOL
+    # The cotangent x_T - y keeps one sign (x_T stays below the target's range), and the
+    # weights are non-negative, so no gradient entry comes near zero: the comparison is
+    # element by element.
+    assert np.all(gh < 0)
+    for got, ref in ((gxh, ref_x), (gph, ref_p)):
+        rel = np.abs(got.astype(np.float64) - ref) / np.abs(ref.astype(np.float64))
+        assert float(rel.max()) <= TOL, float(rel.max())

@@ -523,3 +523,80 @@ def test_injected_fault_is_reported_and_plan_recovers(monkeypatch):
         assert np.array_equal(x.cpu().numpy(), oracle.forward(x0, cf, 12, power=p, dtype=np.float32))
     finally:
         plan.close()
+
+
+# ------------------------------------------------------------------ binding argument checks
+
+def test_binding_rejects_tensors_that_do_not_fit_the_plan():
+    shape = (40, 64)
+    cf = SETS["H2"]
+    plan = S.Plan(HOTSPOT, shape, {"variant": 2, "k": 4})
+    try:
+        good = dev(uniform(shape, 300.0, 350.0, 1))
+        pw = dev(uniform(shape, 0.0, 1e-3, 2))
+        with pytest.raises(ValueError):  # smaller grid than the plan
+            plan.run(dev(uniform((40, 60), 300.0, 350.0, 1)), cf, 3, pw)
+        with pytest.raises(ValueError):  # power on the host
+            plan.run(good, cf, 3, torch.from_numpy(uniform(shape, 0.0, 1e-3, 2)))
+        with pytest.raises(ValueError):  # power of another shape
+            plan.run(good, cf, 3, dev(uniform((41, 64), 0.0, 1e-3, 2)))
+        with pytest.raises(ValueError):  # hotspot without power
+            plan.run(good, cf, 3, None)
+        with pytest.raises(ValueError):
+            plan.run_ckpt(good, cf, 3, 0, torch.from_numpy(uniform(shape, 0.0, 1e-3, 2)))
+        gx = torch.empty_like(good)
+        gp_nc = torch.empty((64, 40), device="cuda").t()  # non-contiguous, right shape
+        with pytest.raises(ValueError):
+            plan.adjoint(good, cf, 3, gx, gp_nc)
+        with pytest.raises(ValueError):  # grad_x0 of another shape
+            plan.adjoint(good, cf, 3, torch.empty((40, 63), device="cuda"))
+        # the plan still works after the rejections
+        plan.run(good, cf, 3, pw)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+
+
+def test_grad_power_offset_by_four_bytes():
+    """grad_p that is only 4-byte aligned takes the scalar path and matches the aligned one."""
+    shape = (33, 256)
+    cf = SETS["AH2"]
+    g = dev(uniform(shape, -1.0, 1.0, 77))
+    plan = S.Plan(HOTSPOT, shape, {"variant": 2, "k": 4})
+    try:
+        gx = torch.empty_like(g)
+        gp = torch.empty_like(g)
+        plan.adjoint(g, cf, 9, gx, gp)
+        big = torch.empty(g.numel() + 1, device="cuda")
+        gp_off = big[1:].view(shape)  # contiguous, 4 bytes past a 16-byte boundary
+        gx2 = torch.empty_like(g)
+        plan.adjoint(g, cf, 9, gx2, gp_off)
+        torch.cuda.synchronize()
+        assert np.array_equal(gp.cpu().numpy(), gp_off.cpu().numpy())
+        assert np.array_equal(gx.cpu().numpy(), gx2.cpu().numpy())
+    finally:
+        plan.close()
+    rx, rp = oracle.adjoint(g.cpu().numpy(), cf, 9, form=HOTSPOT)
+    assert normrel(gp.cpu().numpy(), rp) <= TOL
+
+
+def test_autograd_retain_graph_and_plan_reuse():
+    """backward twice on one graph (retain_graph) gives the same gradients; a later forward of
+    the same shape reuses the released plan."""
+    cf = SETS["AH2"]
+    shape = (20, 50)
+    x0 = uniform(shape, 300.0, 350.0, 7300)
+    p = uniform(shape, 0.0, 1e-3, 7301)
+    xt = dev(x0).requires_grad_(True)
+    pt = dev(p).requires_grad_(True)
+    out = S.StencilFn.apply(xt, pt, cf, 7, 3, 0, {"variant": 2, "k": 4})
+    loss = (out.double() ** 2).sum()
+    loss.backward(retain_graph=True)
+    g1 = (xt.grad.clone(), pt.grad.clone())
+    xt.grad = None
+    pt.grad = None
+    loss.backward()
+    assert torch.equal(g1[0], xt.grad) and torch.equal(g1[1], pt.grad)
+    del out, loss
+    out2 = S.StencilFn.apply(xt, pt, cf, 7, 3, 0, {"variant": 2, "k": 4})
+    assert np.array_equal(out2.detach().cpu().numpy(), oracle.forward(x0, cf, 7, power=p, dtype=np.float32))

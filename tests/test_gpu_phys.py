@@ -109,8 +109,10 @@ def test_phys_rejections():
             S.stencil_run_batched([S.BatchItem(HOTSPOT_PHYS, 2, 64, 64, 1, g.data_ptr(), g.data_ptr(),
                                                S.make_coeffs(SETS["HPr"]), 3)], None, None)
         assert e.value.status == -2  # UNSUPPORTED: no batched launch of the physical form
-        with pytest.raises(S.StencilError) as e:
+        with pytest.raises(ValueError):  # the binding refuses a hotspot run without power
             plan.run(g, SETS["HPr"], 3, None)
+        with pytest.raises(S.StencilError) as e:  # and so does the C ABI underneath
+            S.stencil_run(plan.handle, g, None, SETS["HPr"], 3)
         assert e.value.status == -1  # INVALID_ARG: needs a power map
     finally:
         plan.close()

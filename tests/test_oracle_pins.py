@@ -287,6 +287,12 @@ def test_adjoint_equals_dense_transpose(shape, cset):
                 assert np.all(gp == 0)
             else:
                 assert relerr(gp.ravel(), refp) < 1e-13, T
+        # the FP32 instantiation against the same dense reference, within FP32 rounding
+        gx32, gp32 = oracle.adjoint(g.reshape(shape), cf, T, form=form, dtype=np.float32)
+        assert gx32.dtype == np.float32
+        assert relerr(gx32.ravel(), ref) < 4e-6, T
+        if form == HOTSPOT and T > 0:
+            assert relerr(gp32.ravel(), refp) < 4e-6, T
 
 
 def _gather_adjoint_step(lam, cf):
