@@ -185,6 +185,18 @@ stencil_status_t stencil_batch_sync(stencil_batch_t batch);
 /* Free a captured batch (synchronises its stream first).  NULL is a no-op. */
 void stencil_batch_destroy(stencil_batch_t batch);
 
+/* The uncached stencil_run_batched for callers that cannot allocate device memory (code that
+ * must not call hipMalloc, such as tight serving loops).  It allocates nothing: the caller
+ * passes, besides the items, partners[i], a device buffer of item i's size that serves as
+ * its ping-pong partner (contents unspecified on return; it must not alias any grid or other
+ * partner); the grid table, work lists, pass flags and counters live in a fixed device array
+ * of 8 MiB that each GPU holds until the process ends.  Batches whose tables exceed it return
+ * INVALID_ARG.  Same results as stencil_run_batched, bit for bit.  Synchronous: it returns
+ * after the batch has run on hip_stream, with STENCIL_ERR_INTERNAL if a dependency wait
+ * exceeded its bound.  Calls on one GPU share the array: calls of this process are serialised
+ * by a lock, calls that overlap from other processes race.  No graph is captured. */
+stencil_status_t stencil_run_batched_noalloc(int n, const stencil_batch_item_t* items, float* const* partners,
+                                             void* hip_stream);
 
 /* Report the blocking the plan resolved to (after auto-tuning). */
 stencil_status_t stencil_get_tuning(stencil_plan_t plan, stencil_tuning_t* out);

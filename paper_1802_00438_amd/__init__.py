@@ -28,7 +28,8 @@ STATUS = {0: "STENCIL_OK", -1: "STENCIL_ERR_INVALID_ARG", -2: "STENCIL_ERR_UNSUP
 EXPORTED = ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoint", "stencil_run_batched",
             "stencil_batch_destroy", "stencil_get_tuning", "stencil_destroy", "stencil_status_string",
             "stencil_last_error", "stencil_model_estimate", "stencil_plan_model", "stencil_create_star",
-            "stencil_run_star", "stencil_batch_sync", "stencil_run_slab")
+            "stencil_run_star", "stencil_batch_sync", "stencil_run_batched_noalloc",
+            "stencil_run_slab")
 
 
 class StencilError(RuntimeError):
@@ -96,6 +97,7 @@ def lib():
             L.stencil_run_slab.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Coeffs), i, i, i]
             L.stencil_run_batched.argtypes = [i, ctypes.POINTER(BatchItem), vp, ctypes.POINTER(vp)]
             L.stencil_batch_sync.argtypes = [vp]
+            L.stencil_run_batched_noalloc.argtypes = [i, ctypes.POINTER(BatchItem), ctypes.POINTER(vp), vp]
             L.stencil_batch_destroy.argtypes = [vp]
             L.stencil_batch_destroy.restype = None
             L.stencil_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
@@ -112,7 +114,7 @@ def lib():
             for name in ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoint",
                          "stencil_run_batched", "stencil_get_tuning", "stencil_model_estimate",
                          "stencil_plan_model", "stencil_create_star", "stencil_run_star", "stencil_batch_sync",
-                         "stencil_run_slab"):
+                         "stencil_run_batched_noalloc", "stencil_run_slab"):
                 getattr(L, name).restype = i
             _lib = L
     return _lib
@@ -212,6 +214,14 @@ def stencil_run_batched(items, stream=None, cache=None):
 def stencil_batch_sync(cache):
     """Wait for the latest replay of a captured batch; raises if a dependency wait failed."""
     _check(lib().stencil_batch_sync(cache))
+
+
+def stencil_run_batched_noalloc(items, partners, stream=None):
+    """items: sequence of BatchItem; partners: device pointers (ints), one ping-pong partner
+    buffer per item, of the item's size.  Synchronous; allocates no device memory."""
+    arr = (BatchItem * len(items))(*items)
+    parr = (ctypes.c_void_p * len(items))(*[int(p) for p in partners])
+    _check(lib().stencil_run_batched_noalloc(len(items), arr, parr, _stream(stream)))
 
 
 def stencil_batch_destroy(cache):
@@ -514,6 +524,18 @@ def _batch_items(grids, coeffs_list, steps):
         ndim, nx, ny, nz = _dims(x)
         items.append(BatchItem(DIFFUSION, ndim, nx, ny, nz, x.data_ptr(), None, make_coeffs(c), int(T)))
     return items
+
+
+def run_batched_noalloc(grids, coeffs_list, steps, partners, stream=None):
+    """As run_batched without a cache, through the entry point that allocates nothing:
+    partners[i] is a device tensor of grids[i]'s shape and device (its contents are
+    overwritten)."""
+    if len(partners) != len(grids):
+        raise ValueError("one partner buffer per grid")
+    for x, q in zip(grids, partners):
+        _check_tensor(q, "partner", tuple(x.shape), x.device.index)
+    items = _batch_items(grids, coeffs_list, steps)
+    stencil_run_batched_noalloc(items, [q.data_ptr() for q in partners], stream)
 
 
 def run_batched(grids, coeffs_list, steps, stream=None, cache=None):

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -178,7 +179,15 @@ __global__ void reset_kernel(int* flags, int nflags, int* counters, int clear_er
   if (i < 2 || (clear_err && i == 2)) counters[i] = 0;
 }
 
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+
 }  // namespace
+
+// Scratch of the no-allocation launch (stencil_run_batched_noalloc): the grid table, the work
+// lists, the pass flags and the counters of one batch, 8 MiB at most.  Each GPU the library
+// runs on holds its own copy until the process ends.  Host code never uses this name as an
+// address: the per-device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 struct stencil_batch_s {
   hipStream_t stream = nullptr;
@@ -200,7 +209,7 @@ using namespace stn;
 namespace {
 
 // Everything the persistent kernels need, planned on the host before it is placed in device
-// memory (allocated by the graph path).
+// memory (allocated by the graph path, the static scratch array by the no-allocation path).
 struct BPlan {
   std::vector<BGrid> grids;
   std::vector<BItem> it2, it3;
@@ -600,6 +609,17 @@ stencil_status_t replay_status(stencil_batch_s* b, bool wait) {
   return STENCIL_OK;
 }
 
+// Per-device state of the no-allocation launch: the address of this device's copy of
+// `scratch`, looked up once with the device current, and a lock that serialises the calls of
+// this process on the device (they share the array).
+struct NoAllocDev {
+  std::mutex mu;
+  bool ready = false;
+  unsigned char* ptr = nullptr;
+};
+constexpr int kMaxDevices = 64;
+NoAllocDev g_noalloc[kMaxDevices];
+
 }  // namespace
 
 extern "C" {
@@ -656,6 +676,57 @@ void stencil_batch_destroy(stencil_batch_t b) {
   hipSetDevice(b->device);
   hipStreamSynchronize(b->stream);
   release(b);
+}
+
+stencil_status_t stencil_run_batched_noalloc(int n, const stencil_batch_item_t* items, float* const* partners,
+                                             void* hip_stream) {
+  stencil_status_t st = check_items(n, items);
+  if (st != STENCIL_OK) return st;
+  if (n > 0 && !partners) return fail(STENCIL_ERR_INVALID_ARG, "partners is NULL");
+  for (int i = 0; i < n; ++i) {
+    if (!partners[i] || (reinterpret_cast<uintptr_t>(partners[i]) & 3))
+      return fail(STENCIL_ERR_INVALID_ARG, "partner " + std::to_string(i) + ": NULL or misaligned");
+    for (int j = 0; j < n; ++j)
+      if (partners[i] == items[j].grid || (j < i && partners[j] == partners[i]))
+        return fail(STENCIL_ERR_INVALID_ARG, "partner " + std::to_string(i) + " aliases another buffer");
+  }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(STENCIL_ERR_UNSUPPORTED, "device index beyond 63");
+  NoAllocDev& D = g_noalloc[dev];
+  std::lock_guard<std::mutex> lk(D.mu);
+  if (!D.ready) {
+    // this device's copy of the scratch array, looked up with the device current
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+    D.ptr = static_cast<unsigned char*>(ptr);
+    D.ready = true;
+  }
+  if (n == 0) return STENCIL_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  const BPlan P = plan_batch(n, items, partners);
+  const BLayout L = layout_of(P);
+  if (L.total > kNoAllocScratchBytes)
+    return fail(STENCIL_ERR_INVALID_ARG, "the batch needs " + std::to_string(L.total) +
+                                             " bytes of tables; the no-allocation launch holds at most " +
+                                             std::to_string(kNoAllocScratchBytes));
+  const std::vector<unsigned char> img = table_image(P, L);
+  int err = 0;
+  if (!img.empty()) e = hipMemcpyAsync(D.ptr, img.data(), img.size(), hipMemcpyHostToDevice, s);
+  // the reset clears the flags, the claim counters and the error flag left by the last call
+  if (e == hipSuccess) e = enqueue_launch(P, L, D.ptr, 1, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&err, D.ptr + L.counters + 2 * sizeof(int), sizeof(int), hipMemcpyDeviceToHost, s);
+  // synchronous, like the uncached stencil_run_batched: the host tables and the error flag
+  // are read before the call returns
+  const hipError_t es = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = es;
+  if (e != hipSuccess) return hip_fail(e, "batched launch");
+  log_plan(n, items, P, "no allocation");
+  if (err) return fail(STENCIL_ERR_INTERNAL, "a dependency wait of the batched launch exceeded its bound (the results are invalid)");
+  return STENCIL_OK;
 }
 
 }  // extern "C"

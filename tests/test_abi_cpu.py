@@ -180,3 +180,20 @@ def test_create_star_rejects_bad_arguments_before_device_work():
     t = S.Tuning(variant=3)
     assert L.stencil_create_star(ctypes.byref(h), 2, 2, 8, 8, 1, ctypes.byref(t), None) == -1
     assert L.stencil_create_star(None, 2, 2, 8, 8, 1, None, None) == -1
+
+
+def test_noalloc_batch_rejects_bad_arguments_before_device_work():
+    """Argument errors of the no-allocation batched launch return before any device call."""
+    L = S.lib()
+    item = S.BatchItem(S.DIFFUSION, 2, 8, 8, 1, 4096, None, S.make_coeffs([0.5, 0.125, 0.125, 0.125, 0.125]), 3)
+    arr = (S.BatchItem * 1)(item)
+    assert L.stencil_run_batched_noalloc(1, arr, None, None) == -1          # no partner list
+    parr = (ctypes.c_void_p * 1)(None)
+    assert L.stencil_run_batched_noalloc(1, arr, parr, None) == -1          # NULL partner
+    parr = (ctypes.c_void_p * 1)(4096)
+    assert L.stencil_run_batched_noalloc(1, arr, parr, None) == -1          # partner aliases the grid
+    parr = (ctypes.c_void_p * 1)(8194)
+    assert L.stencil_run_batched_noalloc(1, arr, parr, None) == -1          # misaligned partner
+    bad = (S.BatchItem * 1)(S.BatchItem(S.HOTSPOT, 2, 8, 8, 1, 4096, None, S.make_coeffs([0.5]), 3))
+    assert L.stencil_run_batched_noalloc(1, bad, (ctypes.c_void_p * 1)(65536), None) == -2  # hotspot
+    assert L.stencil_run_batched_noalloc(-1, None, None, None) == -1
