@@ -20,7 +20,8 @@
 //   * In-plane neighbours: x across lanes by DPP wave shifts, y inside a lane's R rows
 //     directly, and y across waves through LDS: every new level plane publishes its first
 //     and last rows, and one barrier per plane (double-buffered by plane parity) makes them
-//     visible to the next plane's phase 1, for all k levels at once.
+//     visible to the next plane's phase 1, for all k levels at once.  In a window flush with
+//     a y edge of the grid, the outermost wave reads its own edge row there instead.
 //   * Clamp-to-edge is applied per level by using the cell's own value for an out-of-grid
 //     neighbour; tiles that touch no x/y edge run code with no boundary handling, and the z
 //     edges cost only on the few planes that meet them.
@@ -69,6 +70,11 @@ struct Tb3dTile {
   bool isL[V], isR[V];
   bool rowTop[R], rowBot[R];  // wave-uniform: strip row is grid row 0 / ny-1
   bool topA, botA;            // window flush with grid row 0 / ny-1 (edge-flush tiling)
+  // LDS sources of this wave's halo rows, as offsets within one level's block of hal: the
+  // last row of the wave above (y-1) and the first row of the wave below (y+1).  The outermost
+  // wave of a window flush with row 0 (ny-1) takes its own first (last) row instead, which is
+  // exactly the clamp, at no cost per cell.
+  int hn_off, hs_off;
   float* hal;                 // LDS: [2][K][NW][2][WX]
 
   __device__ __forceinline__ Tb3dTile(const Tb3dArgs& args, int ln, int wv, float* lds)
@@ -110,9 +116,11 @@ struct Tb3dTile {
   // Phase 1: source, in-plane terms of centre plane Cl (cross-wave rows from LDS buffer rbuf)
   // and the z-1 term of the oldest plane Pl, for output plane j.
   // XE/YE: generic clamping of every cell (windows that cross a grid edge).  EA: window flush
-  // with a grid edge (edge-flush tiling): an end lane that holds x = 0 or x = nx-1 keeps its
-  // own value in the cross-lane move, and the outermost wave of a window flush with row 0 or
-  // ny-1 takes its own edge row as the halo row, which is exactly the clamp.
+  // with an x edge of the grid (edge-flush tiling): an end lane that holds x = 0 or x = nx-1
+  // keeps its own value in the cross-lane move, which is exactly the clamp.  A window flush
+  // with row 0 or ny-1 needs nothing here: its outermost wave reads its own edge row as the
+  // halo row (hn_off, hs_off).  The transposed step also takes EA for y-flush windows, where
+  // the flush rows swap the weight of the leaving direction.
   template <bool XE, bool YE, bool ZE, bool EA>
   __device__ __forceinline__ void partial(const float (&Pl)[R][V], const float (&Cl)[R][V], float (&o)[R][V],
                                           int lev_in, int rbuf, int j) const {
@@ -140,22 +148,13 @@ struct Tb3dTile {
 
     float hn[V], hs[V];
     {
-      const int wn = wave > 0 ? wave - 1 : 0;
-      const int wsn = wave < NW - 1 ? wave + 1 : NW - 1;
-      const float* pn = hrow(rbuf, lev_in, wn, 1) + lane * V;
-      const float* ps = hrow(rbuf, lev_in, wsn, 0) + lane * V;
+      const float* lev = hrow(rbuf, lev_in, 0, 0) + lane * V;
+      const float* pn = lev + hn_off;
+      const float* ps = lev + hs_off;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         hn[v] = pn[v];
         hs[v] = ps[v];
-      }
-      if constexpr (EA) {
-        const bool top = topA && wave == 0, bot = botA && wave == NW - 1;  // wave-uniform
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          hn[v] = top ? Cl[0][v] : hn[v];
-          hs[v] = bot ? Cl[R - 1][v] : hs[v];
-        }
       }
     }
     const bool zlo = ZE && (j == 0);
@@ -482,6 +481,12 @@ struct Tb3dTile {
     const bool xa = a.ax && (tx == 0 || tx == a.ntx - 1);
     topA = a.ay && ty == 0;
     botA = a.ay && ty == a.nty - 1;
+    {
+      const int wn = (wave == 0) ? 0 : wave - 1, which_n = (wave == 0 && topA) ? 0 : 1;
+      const int ws_ = (wave == NW - 1) ? NW - 1 : wave + 1, which_s = (wave == NW - 1 && botA) ? 1 : 0;
+      hn_off = (wn * 2 + which_n) * WX;
+      hs_off = (ws_ * 2 + which_s) * WX;
+    }
     z0 = zs;
     z1 = ze;
     const bool xe = !a.aligned || (xw < 0) || (xw + WX > a.nx);
@@ -512,7 +517,10 @@ struct Tb3dTile {
       if (gy) run<true, true, false>(); else run<true, false, false>();
     } else if (gy) {
       run<false, true, false>();
-    } else if (xa || topA || botA) {
+    } else if (xa || (ADJ && (topA || botA))) {
+      // x-flush windows take the own-value cross-lane moves; a window flush only in y runs the
+      // edge-free body (its halo rows come from the LDS sources above), except in the
+      // transposed step, whose flush rows also swap a weight
       run<false, false, true>();
     } else {
       run<false, false, false>();
