@@ -85,6 +85,9 @@ def _load():
                 st = getattr(lib, "oracle_star2d_" + suf)
                 st.restype = ctypes.c_int
                 st.argtypes = [ctypes.c_int] * 3 + [ctypes.POINTER(ctypes.c_float), p, ctypes.c_int]
+                st3 = getattr(lib, "oracle_star3d_" + suf)
+                st3.restype = ctypes.c_int
+                st3.argtypes = [ctypes.c_int] * 4 + [ctypes.POINTER(ctypes.c_float), p, ctypes.c_int]
             lib.oracle_num_threads.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -183,6 +186,28 @@ def star2d(x0, weights, T, dtype=np.float64):
     rc = fn(rad, g.shape[1], g.shape[0], _ptr(w, ctypes.c_float), _ptr(g, ct), int(T))
     if rc != 0:
         raise ValueError("oracle_star2d rejected its arguments")
+    return g
+
+
+def star3d(x0, weights, T, dtype=np.float64):
+    """T clamped Jacobi steps of the radius-r 3D star stencil (diffusion form) on ``x0`` of
+    shape (nz, ny, nx).  ``weights`` has 1 + 6r entries: cc, then w_d, e_d for d = 1..r, then
+    s_1..s_r (y+d), n_1..n_r (y-d), b_1..b_r (z-d), a_1..a_r (z+d) (FP32 values; the FP64 run
+    promotes them exactly)."""
+    lib = _load()
+    dtype = np.dtype(dtype)
+    ct = ctypes.c_double if dtype == np.float64 else ctypes.c_float
+    fn = lib.oracle_star3d_f64 if dtype == np.float64 else lib.oracle_star3d_f32
+    g = _prep(x0, dtype)
+    if g.ndim != 3:
+        raise ValueError("the 3D radius-r stencil takes (nz, ny, nx) grids")
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    if w.size < 7 or (w.size - 1) % 6:
+        raise ValueError("weights must have 1 + 6r entries")
+    rad = (w.size - 1) // 6
+    rc = fn(rad, g.shape[2], g.shape[1], g.shape[0], _ptr(w, ctypes.c_float), _ptr(g, ct), int(T))
+    if rc != 0:
+        raise ValueError("oracle_star3d rejected its arguments")
     return g
 
 

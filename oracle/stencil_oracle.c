@@ -254,3 +254,57 @@ ORACLE_DEFINE(float, f32, fmaf)
 
 ORACLE_STAR_DEFINE(double, f64, fma)
 ORACLE_STAR_DEFINE(float, f32, fmaf)
+
+/*
+ * Radius-r star stencil in 3D, diffusion form (Eq. 1 and Eq. 2 are written for a general rad
+ * in both 2D and 3D; the 3D shift register of Eq. 1 spans 2*rad planes).  Each cell is updated
+ * from itself and the cells at distance d = 1..rad along each of the three axes:
+ *   out = cc*c + sum_d (w_d*[x-d] + e_d*[x+d]) + sum_d s_d*[y+d] + sum_d n_d*[y-d]
+ *               + sum_d b_d*[z-d] + sum_d a_d*[z+d]
+ * with the clamp of Section 5.1 at every distance (an index beyond the grid is replaced by the
+ * nearest boundary index).
+ * Weight layout (1 + 6*rad floats), which is also the evaluation order of the FMA chain:
+ *   wts[0] = cc; for d = 1..rad: wts[2d-1] = w_d, wts[2d] = e_d;
+ *   wts[2rad+d] = s_d; wts[3rad+d] = n_d; wts[4rad+d] = b_d; wts[5rad+d] = a_d (d = 1..rad).
+ * With rad = 1 this is the chain c, w, e, s, n, b, a of the radius-1 3D forward above.
+ */
+#define ORACLE_STAR3_DEFINE(REAL, SUF, FMA)                                                      \
+  int oracle_star3d_##SUF(int rad, int nx, int ny, int nz, const float* wts, REAL* grid, int T) { \
+    if (rad < 1 || nx < 1 || ny < 1 || nz < 1 || T < 0) return -1;                             \
+    const long n = (long)nx * ny * nz;                                                         \
+    REAL* buf = (REAL*)malloc(sizeof(REAL) * (size_t)n);                                       \
+    if (!buf) return -1;                                                                       \
+    REAL* v = grid;                                                                            \
+    REAL* o = buf;                                                                             \
+    for (int t = 0; t < T; ++t) {                                                              \
+      _Pragma("omp parallel for collapse(2) schedule(static)")                                 \
+      for (long z = 0; z < nz; ++z) {                                                          \
+        for (long y = 0; y < ny; ++y) {                                                        \
+          const REAL* row = v + (z * ny + y) * nx;                                             \
+          for (long x = 0; x < nx; ++x) {                                                      \
+            REAL acc = (REAL)wts[0] * row[x];                                                  \
+            for (int d = 1; d <= rad; ++d) {                                                   \
+              acc = FMA((REAL)wts[2 * d - 1], row[clampl(x - d, 0, nx - 1)], acc);             \
+              acc = FMA((REAL)wts[2 * d], row[clampl(x + d, 0, nx - 1)], acc);                 \
+            }                                                                                  \
+            for (int d = 1; d <= rad; ++d)                                                     \
+              acc = FMA((REAL)wts[2 * rad + d], v[(z * ny + clampl(y + d, 0, ny - 1)) * nx + x], acc); \
+            for (int d = 1; d <= rad; ++d)                                                     \
+              acc = FMA((REAL)wts[3 * rad + d], v[(z * ny + clampl(y - d, 0, ny - 1)) * nx + x], acc); \
+            for (int d = 1; d <= rad; ++d)                                                     \
+              acc = FMA((REAL)wts[4 * rad + d], v[(clampl(z - d, 0, nz - 1) * ny + y) * nx + x], acc); \
+            for (int d = 1; d <= rad; ++d)                                                     \
+              acc = FMA((REAL)wts[5 * rad + d], v[(clampl(z + d, 0, nz - 1) * ny + y) * nx + x], acc); \
+            o[(z * ny + y) * nx + x] = acc;                                                    \
+          }                                                                                    \
+        }                                                                                      \
+      }                                                                                        \
+      REAL* tmp = v; v = o; o = tmp;                                                           \
+    }                                                                                          \
+    if (v != grid) memcpy(grid, v, sizeof(REAL) * (size_t)n);                                  \
+    free(buf);                                                                                 \
+    return 0;                                                                                  \
+  }
+
+ORACLE_STAR3_DEFINE(double, f64, fma)
+ORACLE_STAR3_DEFINE(float, f32, fmaf)

@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import SETS, STAR_SETS, DIFFUSION, HOTSPOT, HOTSPOT_PHYS, phys_coeffs, uniform
+from workloads import SETS, STAR_SETS, STAR3_SETS, DIFFUSION, HOTSPOT, HOTSPOT_PHYS, phys_coeffs, uniform
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -628,3 +628,108 @@ def test_star_rejects_bad_arguments():
         oracle.star2d(np.zeros((2, 3, 3)), STAR[2], 1)
     with pytest.raises(ValueError):
         oracle.star2d(np.zeros((3, 3)), STAR[2], -1)
+
+
+# ---------------------------------------------------------------- radius-r star stencil, 3D
+
+STAR3 = STAR3_SETS
+
+
+def dense_star3(shape, wts):
+    """Dense operator of the radius-r 3D star stencil: row i gets every directional weight at
+    the clamped index of that neighbour (Section 5.1 at every distance)."""
+    nz, ny, nx = shape
+    r = (len(wts) - 1) // 6
+    n = nx * ny * nz
+    A = np.zeros((n, n))
+    idx = lambda z, y, x: (z * ny + y) * nx + x
+    for z, y, x in itertools.product(range(nz), range(ny), range(nx)):
+        i = idx(z, y, x)
+        A[i, i] += float(wts[0])
+        for d in range(1, r + 1):
+            A[i, idx(z, y, max(x - d, 0))] += float(wts[2 * d - 1])
+            A[i, idx(z, y, min(x + d, nx - 1))] += float(wts[2 * d])
+            A[i, idx(z, min(y + d, ny - 1), x)] += float(wts[2 * r + d])
+            A[i, idx(z, max(y - d, 0), x)] += float(wts[3 * r + d])
+            A[i, idx(max(z - d, 0), y, x)] += float(wts[4 * r + d])
+            A[i, idx(min(z + d, nz - 1), y, x)] += float(wts[5 * r + d])
+    return A
+
+
+def test_star3d_radius_one_is_the_3d_diffusion_stencil():
+    w = STAR3[1]  # cc, w, e, s, n, b, a
+    cf = np.array([w[0], w[1], w[2], w[4], w[3], w[5], w[6], 0, 0, 0], dtype=np.float32)
+    x0 = uniform((11, 17, 23), 0.0, 1.0, 161)
+    for dt in (np.float64, np.float32):
+        assert np.array_equal(oracle.star3d(x0, w, 13, dtype=dt), oracle.forward(x0, cf, 13, dtype=dt))
+
+
+@pytest.mark.parametrize("shape", [(6, 6, 6), (5, 4, 3), (1, 5, 7), (7, 1, 2), (2, 3, 1), (1, 1, 1), (4, 2, 6)])
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_star3d_equals_dense_matrix_power(shape, r):
+    w = STAR3[r]
+    A = dense_star3(shape, w)
+    x0 = uniform(shape, 0.0, 1.0, 162 + r)
+    for T in (0, 1, 2, 3, 6):
+        ref = (np.linalg.matrix_power(A, T) @ x0.astype(np.float64).ravel()).reshape(shape)
+        assert relerr(oracle.star3d(x0, w, T), ref) < 1e-13, (shape, r, T)
+        assert relerr(oracle.star3d(x0, w, T, dtype=np.float32), ref) < 2e-6, (shape, r, T)
+
+
+@pytest.mark.parametrize("r,T", [(2, 3), (3, 2), (4, 2)])
+def test_star3d_green_function_exact(r, T):
+    """Away from the edges the impulse response is the T-fold convolution of the stencil, here
+    in exact integers (weights scaled by their common denominator); the FP64 oracle must
+    reproduce it exactly."""
+    w = STAR3[r]
+    scale = 128
+    iw = [int(round(float(v) * scale)) for v in w]
+    assert all(a == float(v) * scale for a, v in zip(iw, w))
+    n = 2 * r * T + 3
+    c = n // 2
+    ex = {(c, c, c): 1}
+    for _ in range(T):
+        nxt = {}
+        for (z, y, x), v in ex.items():
+            # scatter: the value at a cell feeds the cells that read it as a neighbour: the
+            # cell at x+d reads it as its x-d neighbour (weight w_d), and so on
+            terms = [((z, y, x), iw[0])]
+            for d in range(1, r + 1):
+                terms += [((z, y, x + d), iw[2 * d - 1]), ((z, y, x - d), iw[2 * d]),
+                          ((z, y - d, x), iw[2 * r + d]), ((z, y + d, x), iw[3 * r + d]),
+                          ((z + d, y, x), iw[4 * r + d]), ((z - d, y, x), iw[5 * r + d])]
+            for k, wv in terms:
+                nxt[k] = nxt.get(k, 0) + wv * v
+        ex = nxt
+    x0 = np.zeros((n, n, n))
+    x0[c, c, c] = 1.0
+    out = oracle.star3d(x0, w, T)
+    ref = np.zeros((n, n, n))
+    for k, v in ex.items():
+        ref[k] = Fraction(v, scale ** T)
+    assert np.array_equal(out, ref)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_star3d_constant_field_and_axis_permutation(r):
+    w = STAR3[r]
+    x0 = np.full((9, 11, 13), 0.625, dtype=np.float32)
+    assert np.all(oracle.star3d(x0, w, 20, dtype=np.float32) == 0.625)
+    # exchanging the x and z axes together with (w_d, e_d) <-> (b_d, a_d) permutes the result
+    sw = w.copy()
+    for d in range(1, r + 1):
+        sw[2 * d - 1], sw[2 * d] = w[4 * r + d], w[5 * r + d]
+        sw[4 * r + d], sw[5 * r + d] = w[2 * d - 1], w[2 * d]
+    x1 = uniform((7, 10, 12), 0.0, 1.0, 170 + r)
+    a = oracle.star3d(x1, w, 5)
+    b = oracle.star3d(np.ascontiguousarray(x1.transpose(2, 1, 0)), sw, 5)
+    assert relerr(b.transpose(2, 1, 0), a) < 1e-14
+
+
+def test_star3d_rejects_bad_arguments():
+    with pytest.raises(ValueError):
+        oracle.star3d(np.zeros((3, 3, 3)), np.zeros(8, np.float32), 1)
+    with pytest.raises(ValueError):
+        oracle.star3d(np.zeros((3, 3)), STAR3[2], 1)
+    with pytest.raises(ValueError):
+        oracle.star3d(np.zeros((3, 3, 3)), STAR3[2], -1)

@@ -88,6 +88,32 @@ STAR_SETS = {
 }
 
 
+def star3_weights(cc, xw, xe, ys, yn, zb, za):
+    """Pack the weights of a radius-r 3D star stencil: cc; w_d, e_d for d = 1..r (x-d, x+d);
+    s_1..s_r (y+d); n_1..n_r (y-d); b_1..b_r (z-d); a_1..a_r (z+d).  The order is also the
+    stencil's evaluation order."""
+    r = len(xw)
+    out = [cc]
+    for d in range(r):
+        out += [xw[d], xe[d]]
+    return np.array(out + list(ys) + list(yn) + list(zb) + list(za), dtype=np.float32)
+
+
+def _star3_from_ints(den, cc, xw, xe, ys, yn, zb, za):
+    f = lambda v: [x / den for x in v]
+    return star3_weights(cc / den, f(xw), f(xe), f(ys), f(yn), f(zb), f(za))
+
+
+# Radius-r 3D weights: dyadic, asymmetric, summing to exactly 1 (r = 1 is set A3's pattern).
+STAR3_SETS = {
+    1: _star3_from_ints(64, 16, [4], [12], [12], [8], [4], [8]),
+    2: _star3_from_ints(64, 16, [4, 2], [6, 3], [5, 2], [6, 2], [4, 3], [7, 4]),
+    3: _star3_from_ints(128, 36, [6, 4, 2], [9, 5, 3], [8, 4, 2], [9, 5, 1], [7, 4, 3], [11, 6, 3]),
+    4: _star3_from_ints(128, 27, [6, 4, 2, 1], [9, 5, 3, 2], [8, 4, 2, 1], [9, 5, 1, 2], [7, 4, 3, 2],
+                        [11, 6, 3, 1]),
+}
+
+
 def rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
