@@ -73,9 +73,14 @@ typedef struct {
  *   vec      FP32 cells per lane along x (par_vec of Section 3.1)
  *   bsize_x  spatial block width in cells (64*vec for the temporal-blocked kernels)
  *   bsize_y  3D: spatial block height in cells
- *   seg_len  cells of the streamed axis (y in 2D, z in 3D) handled by one tile pass */
+ *   seg_len  cells of the streamed axis (y in 2D, z in 3D) handled by one tile pass
+ *   nwork    3D: workgroups of the balanced launch, where each workgroup streams an equal share
+ *            of all x-y columns' planes (reported: 0 means the tile launch, one workgroup per
+ *            tile of seg_len planes).  As input, nwork > 0 selects the balanced launch with that
+ *            many workgroups; 0 leaves the choice to the tuner (or, with seg_len > 0, to the tile
+ *            launch). */
 typedef struct {
-  int variant, k, vec, bsize_x, bsize_y, seg_len;
+  int variant, k, vec, bsize_x, bsize_y, seg_len, nwork;
 } stencil_tuning_t;
 
 typedef struct stencil_plan_s* stencil_plan_t;
@@ -200,6 +205,11 @@ stencil_status_t stencil_run_batched_noalloc(int n, const stencil_batch_item_t* 
 
 /* Report the blocking the plan resolved to (after auto-tuning). */
 stencil_status_t stencil_get_tuning(stencil_plan_t plan, stencil_tuning_t* out);
+
+/* The blocking of the plan's transposed (adjoint) passes, which the tuner chooses and times on
+ * their own (they also read and write grad_p): k, seg_len, nwork and the window as in
+ * stencil_get_tuning.  UNSUPPORTED for star plans. */
+stencil_status_t stencil_get_adjoint_tuning(stencil_plan_t plan, stencil_tuning_t* out);
 
 /* The library's own time model for T steps of the plan's resolved blocking, the model the
  * tuner ranks candidates with: the paper's external-memory count (Section 4, Eq. 6-8, with

@@ -29,7 +29,7 @@ EXPORTED = ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoin
             "stencil_batch_destroy", "stencil_get_tuning", "stencil_destroy", "stencil_status_string",
             "stencil_last_error", "stencil_model_estimate", "stencil_plan_model", "stencil_create_star",
             "stencil_run_star", "stencil_batch_sync", "stencil_run_batched_noalloc",
-            "stencil_run_slab")
+            "stencil_run_slab", "stencil_get_adjoint_tuning")
 
 
 class StencilError(RuntimeError):
@@ -43,7 +43,7 @@ class Coeffs(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int) for n in ("variant", "k", "vec", "bsize_x", "bsize_y", "seg_len")]
+    _fields_ = [(n, ctypes.c_int) for n in ("variant", "k", "vec", "bsize_x", "bsize_y", "seg_len", "nwork")]
 
 
 class BatchItem(ctypes.Structure):
@@ -101,6 +101,7 @@ def lib():
             L.stencil_batch_destroy.argtypes = [vp]
             L.stencil_batch_destroy.restype = None
             L.stencil_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+            L.stencil_get_adjoint_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
             L.stencil_destroy.argtypes = [vp]
             L.stencil_destroy.restype = None
             L.stencil_status_string.argtypes = [i]
@@ -114,7 +115,7 @@ def lib():
             for name in ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoint",
                          "stencil_run_batched", "stencil_get_tuning", "stencil_model_estimate",
                          "stencil_plan_model", "stencil_create_star", "stencil_run_star", "stencil_batch_sync",
-                         "stencil_run_batched_noalloc", "stencil_run_slab"):
+                         "stencil_run_batched_noalloc", "stencil_run_slab", "stencil_get_adjoint_tuning"):
                 getattr(L, name).restype = i
             _lib = L
     return _lib
@@ -236,6 +237,12 @@ def stencil_get_tuning(plan) -> dict:
     return {k: getattr(t, k) for k, _ in Tuning._fields_}
 
 
+def stencil_get_adjoint_tuning(plan) -> dict:
+    t = Tuning()
+    _check(lib().stencil_get_adjoint_tuning(plan, ctypes.byref(t)))
+    return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+
 def stencil_plan_model(plan, T) -> dict:
     """The library's time model of T steps on the plan's resolved blocking."""
     m = PlanModel()
@@ -350,6 +357,10 @@ class Plan:
     @property
     def tuning(self):
         return stencil_get_tuning(self.handle)
+
+    @property
+    def adjoint_tuning(self):
+        return stencil_get_adjoint_tuning(self.handle)
 
     def model(self, T):
         return stencil_plan_model(self.handle, T)

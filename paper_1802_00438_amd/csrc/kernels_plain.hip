@@ -71,21 +71,21 @@ hipError_t launch_tb3d(int K, KMode m, bool full, const Tb3dArgs& a, hipStream_t
 hipError_t launch_plain(KMode m, const PlainArgs& a, hipStream_t s) {
   const int nb = plain_blocks(a);
   switch (m) {
-    case KM_DIFF: hipLaunchKernelGGL((plain_kernel<false, false, false>), dim3(nb), dim3(256), 0, s, a); break;
-    case KM_HOT: hipLaunchKernelGGL((plain_kernel<true, false, false>), dim3(nb), dim3(256), 0, s, a); break;
-    case KM_ADJ: hipLaunchKernelGGL((plain_kernel<false, true, false>), dim3(nb), dim3(256), 0, s, a); break;
-    case KM_ADJ_ACC: hipLaunchKernelGGL((plain_kernel<false, true, true>), dim3(nb), dim3(256), 0, s, a); break;
+    case KM_DIFF: hipLaunchKernelGGL((plain_kernel<false, false, false>), dim3(nb), dim3(64), 0, s, a); break;
+    case KM_HOT: hipLaunchKernelGGL((plain_kernel<true, false, false>), dim3(nb), dim3(64), 0, s, a); break;
+    case KM_ADJ: hipLaunchKernelGGL((plain_kernel<false, true, false>), dim3(nb), dim3(64), 0, s, a); break;
+    case KM_ADJ_ACC: hipLaunchKernelGGL((plain_kernel<false, true, true>), dim3(nb), dim3(64), 0, s, a); break;
     case KM_PHYS:
       if (a.ndim != 2) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((plain_kernel<true, false, false, true>), dim3(nb), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((plain_kernel<true, false, false, true>), dim3(nb), dim3(64), 0, s, a);
       break;
     case KM_PHYS_ADJ:
       if (a.ndim != 2) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((plain_kernel<false, true, false, true>), dim3(nb), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((plain_kernel<false, true, false, true>), dim3(nb), dim3(64), 0, s, a);
       break;
     case KM_PHYS_ADJ_ACC:
       if (a.ndim != 2) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((plain_kernel<false, true, true, true>), dim3(nb), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((plain_kernel<false, true, true, true>), dim3(nb), dim3(64), 0, s, a);
       break;
     case KM_STAR: return hipErrorInvalidValue;
   }

@@ -5,11 +5,18 @@
 // ceiling is HBM bandwidth divided by the bytes per cell update of Table 2 (8 B diffusion,
 // 12 B hotspot).
 //
-// Each thread owns four consecutive x cells (one 16-byte access) and marches kPlainMR rows
-// (2D) or planes (3D) along the slowest axis, keeping the previous/current/next row of that
-// axis in registers, so every value along the streamed axis is fetched once per step; the
-// in-plane y neighbours of the 3D stencil and the two x neighbours beyond the four cells
-// come from the L1/L2 copies of rows that other threads stream.
+// One wave per workgroup; lane l owns four consecutive x cells (one 16-byte access) of a
+// 256-column chunk and marches kPlainMR rows (2D) or planes (3D) along the slowest axis,
+// keeping the previous, current and next row (plane) in registers and loading the one after
+// next an iteration ahead, so every value along the marched axis is fetched once per step (plus
+// two per strip).  The x neighbours beyond a lane's four cells come from the neighbouring lanes
+// through DPP; only the first and last lane of a wave read theirs from memory.  In 3D the
+// in-plane y neighbours are the rows that the waves of the adjacent rows stream, read at the
+// current plane (by which time those waves have brought them into L2): workgroups are ordered
+// chunk, then row, then strip, and mapped so that each XCD runs a contiguous range of them, so
+// a row is fetched from HBM once and read by its neighbours from the XCD's L2.  (Streaming
+// several rows per wave, with the neighbour rows loaded either with the plane ahead or at the
+// current plane, measured 8-35% slower on the 512^3 grid.)
 #pragma once
 #include "device_common.hpp"
 
@@ -19,12 +26,12 @@ struct PlainArgs {
   const float* power;  // forward hotspot
   float* gp;           // adjoint hotspot accumulator (grad_p += cp * src), or null
   int nx, ny, nz, ndim;
-  int chunks;          // 1024-column chunks per row
+  int chunks;          // 256-column chunks per row
   int vec;             // 1: nx % 4 == 0 and 16-byte aligned buffers
   DevCoef cf;
 };
 
-constexpr int kPlainMR = 8;  // rows (2D) / planes (3D) marched per thread
+constexpr int kPlainMR = 16;  // rows (2D) / planes (3D) marched per wave
 
 // four consecutive cells starting at x0 of row r (clamped beyond nx on the scalar path)
 __device__ __forceinline__ void plain_ld4(const float* r, int x0, int nx, bool vec, float (&o)[4]) {
@@ -37,20 +44,22 @@ __device__ __forceinline__ void plain_ld4(const float* r, int x0, int nx, bool v
   }
 }
 
-// PHYS (2D only): Table 2's physical Hotspot 2D formula in its printed order (see DevCoef
-// for where its parameters travel); with ADJ, its symmetric linear part (no power, TEMP_AMB
-// = 0) as the transposed step.
+// PHYS (2D only): Table 2's physical Hotspot 2D formula in its printed order (see DevCoef for
+// where its parameters travel); with ADJ, its symmetric linear part (no power, TEMP_AMB = 0)
+// as the transposed step.
 template <bool HOT, bool ADJ, bool ACC, bool PHYS = false>
-__global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
+__global__ __launch_bounds__(64) void plain_kernel(PlainArgs a) {
   static_assert(!PHYS || (HOT && !ADJ && !ACC) || (!HOT && ADJ), "physical form: forward hotspot or transposed step");
-  const int chunk = blockIdx.x % a.chunks;
-  const int strip = blockIdx.x / a.chunks;  // y-strips (2D) or (y, z-strip) pairs (3D)
-  const int x0 = chunk * 1024 + threadIdx.x * 4;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int chunk = b % a.chunks;
+  const int strip = b / a.chunks;  // y-strips (2D) or (row y, z-strip) pairs (3D)
+  const int lane = threadIdx.x;
+  const int x0 = chunk * 256 + lane * 4;
   if (x0 >= a.nx) return;
   const bool vec = a.vec != 0;
   const int cnt = min(4, a.nx - x0);
   const size_t plane = (size_t)a.ny * a.nx;
-  // streamed axis: y (2D) or z (3D); the fixed in-plane row of a 3D thread is y
+  // marched axis: y (2D) or z (3D); the fixed in-plane row of a 3D wave is y
   int y = 0, s0, ns;
   if (a.ndim == 2) {
     s0 = strip * kPlainMR;
@@ -61,18 +70,27 @@ __global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
     ns = a.nz;
   }
   const int s1 = min(s0 + kPlainMR, ns);
-  const size_t stride = a.ndim == 2 ? (size_t)a.nx : plane;  // distance between streamed rows
+  const size_t stride = a.ndim == 2 ? (size_t)a.nx : plane;  // distance between marched rows
   const float* sbase = a.src + (a.ndim == 2 ? 0 : (size_t)y * a.nx);
   const int ym = y > 0 ? y - 1 : 0, yp = y < a.ny - 1 ? y + 1 : a.ny - 1;
   const bool top = (a.ndim == 3) && (y == 0), bot = (a.ndim == 3) && (y == a.ny - 1);
-  float prv[4], cur[4], nxt[4];
+  float prv[4], cur[4], nxt[4], nn[4];
   plain_ld4(sbase + (size_t)max(s0 - 1, 0) * stride, x0, a.nx, vec, prv);
   plain_ld4(sbase + (size_t)s0 * stride, x0, a.nx, vec, cur);
+  plain_ld4(sbase + (size_t)min(s0 + 1, ns - 1) * stride, x0, a.nx, vec, nxt);
   for (int s = s0; s < s1; ++s) {
-    plain_ld4(sbase + (size_t)min(s + 1, ns - 1) * stride, x0, a.nx, vec, nxt);
+    plain_ld4(sbase + (size_t)min(s + 2, ns - 1) * stride, x0, a.nx, vec, nn);  // one ahead
     const float* cr = sbase + (size_t)s * stride;
-    const float left = (x0 > 0) ? cr[x0 - 1] : cur[0];
-    const float right = (x0 + 4 < a.nx) ? cr[x0 + 4] : cur[cnt - 1];
+    // x neighbours: the neighbouring lanes' cells; a wave's first and last lane read theirs
+    float left = from_lower(cur[3]);
+    float right = from_upper(cur[0]);
+    if (lane == 0) left = (x0 > 0) ? cr[x0 - 1] : cur[0];
+    if (lane == 63 || x0 + 4 >= a.nx) {
+      // the row's last cell when it falls inside this lane (a select chain, not an indexed
+      // register array, which would live in scratch memory)
+      const float last = cnt == 1 ? cur[0] : (cnt == 2 ? cur[1] : (cnt == 3 ? cur[2] : cur[3]));
+      right = (x0 + 4 < a.nx) ? cr[x0 + 4] : last;
+    }
     float yn[4], ys[4], p4[4], g4[4];
     if (a.ndim == 3) {
       const float* pl = a.src + (size_t)s * plane;
@@ -82,7 +100,7 @@ __global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
     const size_t off = (size_t)s * stride + (a.ndim == 2 ? 0 : (size_t)y * a.nx);
     if constexpr (HOT && !ADJ) plain_ld4(a.power + off, x0, a.nx, vec, p4);
     if constexpr (ACC) plain_ld4(a.gp + off, x0, a.nx, vec, g4);
-    const bool slo = (s == 0), shi = (s == ns - 1);  // streamed-axis edges (uniform per row)
+    const bool slo = (s == 0), shi = (s == ns - 1);  // marched-axis edges (uniform per row)
     float o[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -100,16 +118,16 @@ __global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
       float q = 0.0f;
       if constexpr (HOT && !ADJ && !PHYS) q = __builtin_fmaf(a.cf.cp, p4[v], a.cf.kamb);
       if constexpr (PHYS) {
-        const float yn = slo ? c : prv[v], ys = shi ? c : nxt[v];
-        const float dy = __builtin_fmaf(-2.0f, c, yn + ys);  // (n + s) - 2c, one rounding each
-        const float dx = __builtin_fmaf(-2.0f, c, xp + xm);  // (e + w) - 2c
-        const float dz = a.cf.kamb - c;                      // TEMP_AMB - c
+        const float yn2 = slo ? c : prv[v], ys2 = shi ? c : nxt[v];
+        const float dy = __builtin_fmaf(-2.0f, c, yn2 + ys2);  // (n + s) - 2c, one rounding each
+        const float dx = __builtin_fmaf(-2.0f, c, xp + xm);    // (e + w) - 2c
+        const float dz = a.cf.kamb - c;                        // TEMP_AMB - c
         acc = __builtin_fmaf(dy, a.cf.wy_m, (HOT && !ADJ) ? p4[v] : 0.0f);
         acc = __builtin_fmaf(dx, a.cf.wx_m, acc);
         acc = __builtin_fmaf(dz, a.cf.wz_m, acc);
         acc = __builtin_fmaf(a.cf.cp, acc, c);
       } else if (a.ndim == 2) {
-        // streamed axis is y: prv = row y-1, nxt = row y+1
+        // marched axis is y: prv = row y-1, nxt = row y+1
         float cym = a.cf.wy_m, cyp = a.cf.wy_p;
         if constexpr (ADJ) {
           if (slo) cym = a.cf.wy_p;
@@ -147,11 +165,12 @@ __global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
     for (int v = 0; v < 4; ++v) {
       prv[v] = cur[v];
       cur[v] = nxt[v];
+      nxt[v] = nn[v];
     }
   }
 }
 
-// Workgroups of one plain launch: (1024-column chunks) x (strips along the streamed axis).
+// Workgroups of one plain launch: (256-column chunks) x (strips along the marched axis).
 inline int plain_blocks(const PlainArgs& a) {
   if (a.ndim == 2) return a.chunks * ((a.ny + kPlainMR - 1) / kPlainMR);
   return a.chunks * a.ny * ((a.nz + kPlainMR - 1) / kPlainMR);

@@ -428,7 +428,7 @@ hipError_t run_plain_step(const stencil_plan_s* p, KMode m, const float* src, fl
   PlainArgs a;
   a.src = src; a.dst = dst; a.power = power; a.gp = gp;
   a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.ndim = p->ndim;
-  a.chunks = (p->nx + 1023) / 1024;
+  a.chunks = (p->nx + 255) / 256;
   a.vec = ((p->nx & 3) == 0) && aligned16(src) && aligned16(dst) && (!power || aligned16(power)) &&
           (!gp || aligned16(gp)) ? 1 : 0;
   a.cf = cf;
@@ -512,11 +512,48 @@ struct TuneResult {
 };
 std::map<TuneKey, TuneResult> g_tune_cache;
 
+// Tuning results persist across processes when STENCIL_TUNE_CACHE names a file: it is read
+// once, before the first tuning, and every new result is appended to it, one line per shape
+// ("form ndim nx ny nz : variant k vec bsize_x bsize_y seg_len nwork adj_k adj_seg adj_nwork").
+// A profiler run can then reuse exactly the blockings a timed run chose.
+const char* tune_cache_path() {
+  const char* v = std::getenv("STENCIL_TUNE_CACHE");
+  return (v && *v) ? v : nullptr;
+}
+void load_tune_cache_file() {
+  static bool loaded = false;
+  if (loaded) return;
+  loaded = true;
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  int form, ndim, nx, ny, nz;
+  TuneResult r{};
+  while (std::fscanf(f, "%d %d %d %d %d : %d %d %d %d %d %d %d %d %d %d", &form, &ndim, &nx, &ny, &nz, &r.t.variant,
+                     &r.t.k, &r.t.vec, &r.t.bsize_x, &r.t.bsize_y, &r.t.seg_len, &r.nwork, &r.adj_k, &r.adj_seg,
+                     &r.adj_nwork) == 15) {
+    r.t.nwork = r.nwork;
+    g_tune_cache[TuneKey{form, ndim, nx, ny, nz}] = r;
+  }
+  std::fclose(f);
+}
+void save_tune_result(const TuneKey& k, const TuneResult& r) {
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%d %d %d %d %d : %d %d %d %d %d %d %d %d %d %d\n", k.form, k.ndim, k.nx, k.ny, k.nz, r.t.variant,
+               r.t.k, r.t.vec, r.t.bsize_x, r.t.bsize_y, r.t.seg_len, r.nwork, r.adj_k, r.adj_seg, r.adj_nwork);
+  std::fclose(f);
+}
+
 // Model-ranked candidates, the best few timed on scratch memory.
 stencil_status_t autotune(stencil_plan_s* p, TuneResult* out) {
   const TuneKey key{p->form, p->ndim, p->nx, p->ny, p->nz};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache_file();
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
       *out = it->second;
@@ -743,6 +780,7 @@ stencil_status_t autotune(stencil_plan_s* p, TuneResult* out) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = TuneResult{best, best_nwork, adj_k, adj_seg, adj_nwork};
+    save_tune_result(key, g_tune_cache[key]);
   }
   *out = TuneResult{best, best_nwork, adj_k, adj_seg, adj_nwork};
   return STENCIL_OK;
@@ -953,8 +991,10 @@ stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int nd
   if ((long)nx * ny > 0x7fffffffL && ndim == 3) return fail(STENCIL_ERR_UNSUPPORTED, "plane larger than 2^31 cells");
   if (tuning) {
     if (tuning->variant < 0 || tuning->variant > 2 || tuning->k < 0 || tuning->vec < 0 || tuning->bsize_x < 0 ||
-        tuning->bsize_y < 0 || tuning->seg_len < 0)
+        tuning->bsize_y < 0 || tuning->seg_len < 0 || tuning->nwork < 0)
       return fail(STENCIL_ERR_INVALID_ARG, "tuning fields must be >= 0 (variant 0..2)");
+    if (tuning->nwork > 0 && ndim != 3)
+      return fail(STENCIL_ERR_INVALID_ARG, "nwork selects the balanced launch of 3D grids");
     if (tuning->vec != 0 && tuning->vec != (ndim == 2 ? kTb2dV : kTb3dV))
       return fail(STENCIL_ERR_UNSUPPORTED, "vec is fixed by the kernel instantiation (2D: 4, 3D: 2)");
   }
@@ -1004,8 +1044,9 @@ stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int nd
       if (ndim == 2) {
         tuned.seg_len = pick_seg2d(K, nx, ny, 8);
       } else {
-        // balanced launch, one workgroup per CU; seg_len reports the planes of one share
-        p->nwork3d = balanced_nwork3d(K, false, nx, ny, nz, 1);
+        // balanced launch, one workgroup per CU unless given; seg_len reports the planes of one
+        // share
+        p->nwork3d = t.nwork > 0 ? t.nwork : balanced_nwork3d(K, false, nx, ny, nz, 1);
         const Geom3D g = geom3d(K, false, nx, ny, nz, nz);
         tuned.seg_len = (int)ceil_div((long)g.ntx * g.nty * nz, p->nwork3d);
       }
@@ -1030,12 +1071,14 @@ stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int nd
         p->adj_seg = t.seg_len;
         p->adj_nwork = 0;
       }
+      if (t.nwork > 0) p->nwork3d = t.nwork;  // an explicit balanced launch
     }
     p->tuning = tuned;
     p->tuning.variant = 2;
   } else {
     p->tuning.variant = 2;
     p->tuning.k = std::min(t.k, tb_max_k(ndim, m));
+    if (ndim == 3 && t.nwork > 0) p->nwork3d = t.nwork;
   }
   // A caller-fixed k (or the plain variant) also fixes the adjoint's blocking: same k and
   // segment length, tile launch.
@@ -1050,6 +1093,7 @@ stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int nd
   p->tuning.vec = ndim == 2 ? kTb2dV : kTb3dV;
   p->tuning.bsize_x = 64 * p->tuning.vec;
   p->tuning.bsize_y = ndim == 2 ? 0 : kTb3dWY;
+  p->tuning.nwork = p->nwork3d;
   *out = p;
   return STENCIL_OK;
 }
@@ -1057,6 +1101,22 @@ stencil_status_t stencil_create(stencil_plan_t* out, stencil_form_t form, int nd
 stencil_status_t stencil_get_tuning(stencil_plan_t plan, stencil_tuning_t* out) {
   if (!plan || !out) return fail(STENCIL_ERR_INVALID_ARG, "NULL argument");
   *out = plan->tuning;
+  return STENCIL_OK;
+}
+
+stencil_status_t stencil_get_adjoint_tuning(stencil_plan_t p, stencil_tuning_t* out) {
+  if (!p || !out) return fail(STENCIL_ERR_INVALID_ARG, "NULL argument");
+  if (p->star) return fail(STENCIL_ERR_UNSUPPORTED, "no adjoint for radius-r star plans");
+  stencil_tuning_t t = p->tuning;
+  if (t.variant != 1) {
+    const KMode m = p->form == STENCIL_HOTSPOT_PHYS ? KM_PHYS_ADJ_ACC : KM_ADJ_ACC;
+    const int kreq = p->adj_k > 0 ? p->adj_k : std::max(1, p->tuning.k);
+    t.k = std::min(kreq, tb_max_k(p->ndim, m));
+    t.seg_len = p->adj_seg > 0 ? p->adj_seg : p->tuning.seg_len;
+    t.nwork = p->adj_nwork;
+    if (p->ndim == 3) t.bsize_y = kTb3dAdjWY;
+  }
+  *out = t;
   return STENCIL_OK;
 }
 
@@ -1336,11 +1396,12 @@ stencil_status_t stencil_create_star(stencil_plan_t* out, int ndim, int rad, int
   if (rad > kStarMaxR) return fail(STENCIL_ERR_UNSUPPORTED, "rad is at most 4 (the x-neighbours of a lane's 4 cells)");
   stencil_tuning_t t{};
   if (tuning) t = *tuning;
-  if (t.variant < 0 || t.variant > 2 || t.k < 0 || t.vec < 0 || t.bsize_x < 0 || t.bsize_y < 0 || t.seg_len < 0)
-    return fail(STENCIL_ERR_INVALID_ARG, "tuning fields must be >= 0 (variant 0..2)");
+  if (t.variant < 0 || t.variant > 2 || t.k < 0 || t.vec < 0 || t.bsize_x < 0 || t.bsize_y < 0 || t.seg_len < 0 ||
+      t.nwork != 0)
+    return fail(STENCIL_ERR_INVALID_ARG, "tuning fields must be >= 0 (variant 0..2), nwork 0");
   if (t.vec != 0 && t.vec != kTb2dV) return fail(STENCIL_ERR_UNSUPPORTED, "vec is fixed at 4");
   // the plan itself (scratch, streams) without the radius-1 tuner: its blocking is set below
-  stencil_tuning_t fixed{2, 1, 0, 0, 0, 1};
+  stencil_tuning_t fixed{2, 1, 0, 0, 0, 1, 0};
   stencil_status_t st = stencil_create(out, STENCIL_DIFFUSION, ndim, nx, ny, nz, &fixed, hip_stream);
   if (st != STENCIL_OK) return st;
   stencil_plan_s* p = *out;
@@ -1361,6 +1422,7 @@ stencil_status_t stencil_create_star(stencil_plan_t* out, int ndim, int rad, int
   }
   p->tuning.vec = kTb2dV;
   p->tuning.bsize_x = 64 * kTb2dV;
+  p->tuning.nwork = 0;
   if (log_enabled())
     std::fprintf(stderr, "[stencil] star plan r=%d %dx%d -> k=%d seg=%d\n", rad, nx, ny, p->tuning.k, p->tuning.seg_len);
   return STENCIL_OK;

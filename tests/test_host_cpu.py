@@ -33,16 +33,41 @@ def test_interior_rectangle_is_edge_free():
         assert (s in ys) == (r0 - K > 0 and r1 + K < ny)
 
 
-def test_run_roofline_of_radius_one_matches_the_pass_count():
-    """run_roofline sums one pass per k steps plus a shorter last one; for radius 1 its bytes
-    equal tb2d_bytes_flops over all tiles, pass by pass."""
-    ms = 100.0
-    r = bench.run_roofline(16384, 16384, 1000, 12, bench.smallest_at_least([4, 8, 12, 16]), 192, 1, 2, 10, ms)
-    b12, f12 = bench.tb2d_bytes_flops(16384, 16384, 12, 12, 192, hot=True)
-    b4, f4 = bench.tb2d_bytes_flops(16384, 16384, 4, 4, 192, hot=True)
-    total_b = 83 * b12 + b4
-    assert abs(r["frac_hbm"] - total_b / (ms * 1e-3) / 1e9 / bench.HBM_PEAK_GBS) < 1e-4
-    assert r["bound"] in ("alu", "hbm")
+def test_tb2d_pass_counts_window_rows_and_outputs():
+    """Bytes of one pass: every tile reads its 256-column window over seg + 2k rows per field and
+    writes its output cells once; the interior part is a subset of the whole pass."""
+    b, f = bench.tb2d_pass(16384, 16384, 12, 12, 192, 2, 10)
+    W, kr, cs, ntx, sg, nseg = bench.tb2d_geometry(16384, 16384, 12, 192)
+    assert b == ntx * nseg * (192 + 24) * 256 * 4 * 2 + 16384 * 16384 * 4
+    assert f == ntx * nseg * 256 * (192 + 12) * 12 * 10
+    bi, fi = bench.tb2d_pass(16384, 16384, 12, 12, 192, 2, 10, interior_only=True)
+    assert bi < b and fi < f and bi == 69 * 84 * 216 * 256 * 8 + 69 * cs * 84 * 192 * 4
+    assert bench.tb2d_split(16384, 16384, 12, 12, 192) and not bench.tb2d_split(256, 256, 4, 4, 256)
+
+
+def test_tb3d_geometry_and_segments():
+    # 512^3 at k = 4 in 128 x 48 windows: 5 x 13 edge-flush tiles; 256^3 at k = 3: 3 x 6
+    assert bench.tb3d_geometry(4, 512, 512) == (5, 13)
+    assert bench.tb3d_geometry(3, 256, 256) == (3, 6)
+    assert bench.tb3d_geometry(2, 100, 40) == (1, 1)  # narrower than a window: uniform tiling
+    for nwork, segz in ((256, 0), (0, 64), (0, 1000)):
+        segs = bench.tb3d_segments(65, 512, nwork, segz)
+        assert sum(ze - zs for zs, ze in segs) == 65 * 512  # every (column, plane) unit once
+        assert all(0 <= zs < ze <= 512 for zs, ze in segs)
+    segs = bench.tb3d_segments(10, 72, 7, 0, zlo=4, zhi=68)
+    assert sum(ze - zs for zs, ze in segs) == 10 * 64 and all(4 <= zs < ze <= 68 for zs, ze in segs)
+    tun = {"bsize_x": 128, "bsize_y": 48, "nwork": 256, "seg_len": 130}
+    b, f = bench.tb3d_pass(512, 512, 512, 4, 4, tun, 1, 4, 13)
+    assert 512 ** 3 * 4 * 1.5 < b < 512 ** 3 * 4 * 3.2  # reads 1.5-2x the grid, writes it once
+    assert f > 512 ** 3 * 4 * 13
+
+
+def test_roofline_record_picks_the_larger_fraction():
+    r = bench.roofline("k", "plain", {}, 1.0, 4.0e9, 1.0e9, 5000.0)
+    assert r["bound"] == "hbm" and abs(r["frac"] - 0.5) < 1e-9 and abs(r["frac_copy_bw"] - 0.8) < 1e-9
+    assert r["traffic"] is None
+    r = bench.roofline("k", "plain", {}, 1.0, 1.0e9, 70.0e9, 5000.0)
+    assert r["bound"] == "alu" and abs(r["achieved"] - 70.0) < 1e-6
     assert bench.smallest_at_least([1, 2, 4, 8])(3) == 4 and bench.smallest_at_least([1, 2, 4])(7) == 4
 
 
