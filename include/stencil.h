@@ -234,24 +234,29 @@ const char* stencil_status_string(stencil_status_t status);
 const char* stencil_last_error(void); /* thread-local; "" if none */
 
 /* ---------------------------------------------------------------- radius-r star stencils
- * Eq. 1 and Eq. 2 are written for a general radius rad; Table 2's stencils are rad = 1.  A
- * radius-r 2D star stencil (diffusion form) updates each cell from itself and the cells at
- * distance d = 1..r along x and y:
+ * Eq. 1 and Eq. 2 are written for a general radius rad in 2D and 3D; Table 2's stencils are
+ * rad = 1.  A radius-r star stencil (diffusion form) updates each cell from itself and the
+ * cells at distance d = 1..r along each axis:
  *     out = cc*c + sum_d (w_d*[x-d] + e_d*[x+d]) + sum_d s_d*[y+d] + sum_d n_d*[y-d]
+ *                [ + sum_d b_d*[z-d] + sum_d a_d*[z+d] ]                       (3D)
  * An index beyond the grid is replaced by the nearest boundary index at every distance and
- * every step (Section 5.1).  Tiles overlap by a halo of r*k cells per side.
+ * every step (Section 5.1).  Tiles overlap by a halo of r*k cells per side: 2D tiles are
+ * 256-column windows streamed along y, 3D tiles 64 x 64 x-y windows streamed along z.
  *
- * stencil_create_star: a plan for an nx*ny grid (ndim must be 2 and nz 1; ndim 3 returns
- * UNSUPPORTED), 1 <= rad <= 4 (larger rad returns UNSUPPORTED).  tuning as for
- * stencil_create; with k == 0 the fused step count is chosen by timing each instantiated k
- * on plan scratch (rad 1, 2: k <= 8; rad 3, 4: k <= 4).  The plan serves stencil_run_star,
+ * stencil_create_star: a plan for an nx*ny grid (ndim 2, nz 1) or an nx*ny*nz grid (ndim 3),
+ * 1 <= rad <= 4 (larger rad returns UNSUPPORTED).  tuning as for stencil_create (seg_len is
+ * the rows per tile in 2D, the planes per tile in 3D); with k == 0 the fused step count is
+ * chosen by timing each instantiated k on plan scratch.  Instantiated k: 2D rad 1: 1, 2, 4, 8;
+ * rad 2: 1, 2, 4, 5, 8; rad 3, 4: 1, 2, 4.  3D rad 1: 1, 2, 3; rad 2, 3: 1, 2; rad 4: 1.  A
+ * larger k is lowered to the largest instantiated one.  The plan serves stencil_run_star,
  * stencil_get_tuning, stencil_plan_model (its passes priced with a halo of rad*k) and
  * stencil_destroy; stencil_run, stencil_run_ckpt and stencil_adjoint reject it.
  *
- * stencil_run_star: exactly T >= 0 steps in place on grid (device, nx*ny FP32).  weights is a
- * HOST array of 1 + 4*rad finite floats, in the stencil's FMA evaluation order: cc; then w_d,
- * e_d for d = 1..rad; then s_1..s_rad; then n_1..n_rad (rad = 1 gives the chain c, w, e, s, n
- * of stencil_run).  Asynchronous on the plan's stream. */
+ * stencil_run_star: exactly T >= 0 steps in place on grid (device, FP32, the plan's shape).
+ * weights is a HOST array of finite floats in the stencil's FMA evaluation order: cc; then
+ * w_d, e_d for d = 1..rad; then s_1..s_rad; then n_1..n_rad; in 3D then b_1..b_rad and
+ * a_1..a_rad.  That is 1 + 4*rad floats in 2D and 1 + 6*rad in 3D (rad = 1 gives the chain c,
+ * w, e, s, n[, b, a] of stencil_run).  Asynchronous on the plan's stream. */
 stencil_status_t stencil_create_star(stencil_plan_t* out, int ndim, int rad, int nx, int ny, int nz,
                                      const stencil_tuning_t* tuning, void* hip_stream);
 stencil_status_t stencil_run_star(stencil_plan_t plan, float* grid, const float* weights, int T);

@@ -378,22 +378,30 @@ class Plan:
 
 
 class StarPlan:
-    """A plan for the radius-r 2D star stencil of a (ny, nx) grid (stencil_create_star)."""
+    """A plan for the radius-r star stencil of a (ny, nx) or (nz, ny, nx) grid
+    (stencil_create_star)."""
 
     def __init__(self, rad, shape, tuning=None, stream=None):
-        if len(shape) != 2:
-            raise ValueError("the radius-r star stencil takes (ny, nx) grids")
+        if len(shape) not in (2, 3):
+            raise ValueError("the radius-r star stencil takes (ny, nx) or (nz, ny, nx) grids")
         self.rad = int(rad)
-        self.shape = (int(shape[0]), int(shape[1]))
+        self.shape = tuple(int(v) for v in shape)
+        self.ndim = len(self.shape)
         self.device = _current_device()
         self.handle = None
-        self.handle = stencil_create_star(2, self.rad, self.shape[1], self.shape[0], 1, tuning, stream)
+        nz = self.shape[0] if self.ndim == 3 else 1
+        self.handle = stencil_create_star(self.ndim, self.rad, self.shape[-1], self.shape[-2], nz, tuning, stream)
+
+    @property
+    def n_weights(self):
+        return 1 + (6 if self.ndim == 3 else 4) * self.rad
 
     def run(self, grid, weights, T):
-        """weights: 1 + 4*rad values, cc; w_d, e_d (d = 1..rad); s_1..s_rad; n_1..n_rad."""
+        """weights: cc; w_d, e_d (d = 1..rad); s_1..s_rad; n_1..n_rad; in 3D then b_1..b_rad
+        (z-d) and a_1..a_rad (z+d): 1 + 4*rad values in 2D, 1 + 6*rad in 3D."""
         _check_tensor(grid, "grid", self.shape, self.device)
-        if len(weights) != 1 + 4 * self.rad:
-            raise ValueError("weights must have 1 + 4*rad entries")
+        if len(weights) != self.n_weights:
+            raise ValueError("weights must have 1 + %d*rad entries" % (6 if self.ndim == 3 else 4))
         stencil_run_star(self.handle, grid, weights, T)
         return grid
 

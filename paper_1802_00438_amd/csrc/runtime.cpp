@@ -79,6 +79,18 @@ Geom2D geom_star(int R, int K, int nx, int ny, int seg) {
   return g;
 }
 
+Geom3D geom_star3(int R, int K, int nx, int ny, int nz, int segz) {
+  Geom3D g;
+  g.K = K;
+  g.krx = g.kry = R * K;
+  g.csx = g.csy = kStar3W - 2 * R * K;
+  g.ntx = ceil_div(nx, g.csx);
+  g.nty = ceil_div(ny, g.csy);
+  g.segz = std::max(1, std::min(segz, nz));
+  g.nsegz = ceil_div(nz, g.segz);
+  return g;
+}
+
 Geom3D geom3d(int K, bool adj, int nx, int ny, int nz, int segz) {
   Geom3D g;
   g.K = K;
@@ -152,6 +164,25 @@ double model_time_star(const Geom2D& g, int R, int nx, int ny, long T, ModelPart
   const double quant = tiles / (rounds * slots);
   const double tm = bytes / (d.hbm_gbs * 1e9 * d.achievable_frac);
   const double ta = ops / (d.valu_lane_ops * 0.8) / quant;
+  if (parts) *parts = ModelParts{passes * tm, passes * ta};
+  return passes * (std::max(tm, ta) + 4e-6);
+}
+
+// Radius-R 3D star passes: every workgroup reads its 64 x 64 window over segz + 2RK planes and
+// computes 6R+1 FMAs per window cell and level over segz + K(2R+1) pipeline iterations; one
+// workgroup per CU.
+double model_time_star3(const Geom3D& g, int R, int nx, int ny, int nz, long T, ModelParts* parts) {
+  const DeviceInfo& d = device_info();
+  const double W2 = (double)kStar3W * kStar3W;
+  const long passes = (T + g.K - 1) / g.K;
+  const double tiles = (double)g.ntx * g.nty * g.nsegz;
+  const double bytes = tiles * (g.segz + 2.0 * R * g.K) * W2 * 4.0 + (double)nx * ny * nz * 4.0;
+  const double iters = g.segz + (double)g.K * (2 * R + 1);
+  const double ops = tiles * W2 * iters * g.K * (6.0 * R + 1.0 + 2.0 * R);
+  const double rounds = std::ceil(tiles / d.cus);
+  const double quant = tiles / (rounds * d.cus);
+  const double tm = bytes / (d.hbm_gbs * 1e9 * d.achievable_frac);
+  const double ta = ops / (d.valu_lane_ops * 0.6) / quant;
   if (parts) *parts = ModelParts{passes * tm, passes * ta};
   return passes * (std::max(tm, ta) + 4e-6);
 }
@@ -310,10 +341,14 @@ KMode form_mode(stencil_form_t f) {
 }
 KMode fwd_mode(const stencil_plan_s* p) { return form_mode(p->form); }
 
+int star_inst(int ndim, int R, const int** ks) {
+  return ndim == 3 ? star3_instantiated(R, ks) : star_instantiated(R, ks);
+}
+
 // Smallest instantiated K >= k of the radius-R star kernels (the largest if none is).
-int star_k_for(int R, int k) {
+int star_k_for(int ndim, int R, int k) {
   const int* ks;
-  const int n = star_instantiated(R, &ks);
+  const int n = star_inst(ndim, R, &ks);
   for (int i = 0; i < n; ++i)
     if (ks[i] >= k) return ks[i];
   return ks[n - 1];
@@ -349,6 +384,15 @@ void interior_rect2d(const Geom2D& g, int nx, int ny, int keff, int ylo, int yhi
 
 // One pass of keff fused steps from src to dst.
 hipError_t run_star_pass(const stencil_plan_s* p, int K, int keff, const float* src, float* dst) {
+  if (p->ndim == 3) {
+    const Geom3D g = geom_star3(p->rad, K, p->nx, p->ny, p->nz, p->tuning.seg_len);
+    Star3dArgs a;
+    a.src = src; a.dst = dst;
+    a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.keff = keff;
+    a.cs = g.csx; a.ntx = g.ntx; a.nty = g.nty; a.segz = g.segz; a.nsegz = g.nsegz;
+    a.cf = p->star3_cf;
+    return launch_star3d(p->rad, K, a, p->stream);
+  }
   const Geom2D g = geom_star(p->rad, K, p->nx, p->ny, p->tuning.seg_len);
   Star2dArgs a;
   a.src = src; a.dst = dst;
@@ -479,7 +523,7 @@ stencil_status_t run_sequence(stencil_plan_s* p, KMode m, bool plain, int K, con
     } else {
       // a pass that fuses fewer steps than K runs on the smallest instantiation that holds
       // them: surplus levels would only forward their input at the full pass's cost
-      const int Ki = steps[i] < K ? (m == KM_STAR ? star_k_for(p->rad, steps[i]) : inst_k_for(p->ndim, m, steps[i]))
+      const int Ki = steps[i] < K ? (m == KM_STAR ? star_k_for(p->ndim, p->rad, steps[i]) : inst_k_for(p->ndim, m, steps[i]))
                                   : K;
       e = run_pass(p, m, Ki, steps[i], src, dst, power, gp, cf);
     }
@@ -812,12 +856,37 @@ int pick_seg_star(int R, int K, int nx, int ny) {
   return best_seg;
 }
 
+// Segment length (planes) of a radius-R 3D star pass: whole rounds of one workgroup per CU,
+// each workgroup paying K(2R+1) pipeline-fill iterations on top of its planes.
+int pick_segz_star3(int R, int K, int nx, int ny, int nz) {
+  const DeviceInfo& d = device_info();
+  const Geom3D g0 = geom_star3(R, K, nx, ny, nz, nz);
+  const double tiles_xy = (double)g0.ntx * g0.nty;
+  int best_seg = nz;
+  double best = 1e300;
+  for (int nseg = 1; nseg <= nz; ++nseg) {
+    const int seg = ceil_div(nz, nseg);
+    const double wg = tiles_xy * ceil_div(nz, seg);
+    const double cost = std::ceil(wg / d.cus) * (seg + (double)K * (2 * R + 1) + 2.0 * R * K);
+    if (cost < best * 0.999) {
+      best = cost;
+      best_seg = seg;
+    }
+    if (wg > 32.0 * d.cus) break;
+  }
+  return best_seg;
+}
+
+int pick_seg_star_nd(const stencil_plan_s* p, int K) {
+  return p->ndim == 3 ? pick_segz_star3(p->rad, K, p->nx, p->ny, p->nz) : pick_seg_star(p->rad, K, p->nx, p->ny);
+}
+
 // Blocking of a radius-R star plan: every instantiated K, each on its own segment length, is
 // timed on scratch memory (three rounds of at least ~12 ms after a warm-up) and the fastest
 // kept; grids below 2^16 cells take K = 4 untimed.
 void star_tune(stencil_plan_s* p) {
   const int* ks;
-  const int nk = star_instantiated(p->rad, &ks);
+  const int nk = star_inst(p->ndim, p->rad, &ks);
   int bestK = ks[std::min(2, nk - 1)];
   const bool timed = !env_flag("STENCIL_MODEL_ONLY") && p->cells >= (size_t)1 << 16;
   float* tmp = nullptr;
@@ -828,13 +897,17 @@ void star_tune(stencil_plan_s* p) {
     c.c0 = 0.5f;
     for (int d = 0; d < p->rad; ++d) c.w[d] = c.e[d] = c.s[d] = c.n[d] = 0.125f / p->rad;
     p->star_cf = c;
+    Star3Coef c3{};
+    c3.c0 = 0.5f;
+    for (int d = 0; d < p->rad; ++d) c3.w[d] = c3.e[d] = c3.s[d] = c3.n[d] = c3.b[d] = c3.a[d] = 0.25f / (3 * p->rad);
+    p->star3_cf = c3;
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     auto time_k = [&](int K) -> double {
       stencil_plan_s q = *p;
       q.tuning.k = K;
-      q.tuning.seg_len = pick_seg_star(p->rad, K, p->nx, p->ny);
+      q.tuning.seg_len = pick_seg_star_nd(p, K);
       const double per_pass = (double)K * (double)p->cells;
       const int reps = std::max(2, std::min(192, (int)std::ceil(2.0e10 / per_pass)));
       run_star_pass(&q, K, K, tmp, p->scratch);
@@ -870,7 +943,7 @@ void star_tune(stencil_plan_s* p) {
   hipGetLastError();
   p->tuning.variant = 2;
   p->tuning.k = bestK;
-  p->tuning.seg_len = pick_seg_star(p->rad, bestK, p->nx, p->ny);
+  p->tuning.seg_len = pick_seg_star_nd(p, bestK);
 }
 
 stencil_status_t set_device(const stencil_plan_s* p) {
@@ -1124,13 +1197,19 @@ stencil_status_t stencil_plan_model(stencil_plan_t p, int T, stencil_plan_model_
   if (!p || !out) return fail(STENCIL_ERR_INVALID_ARG, "NULL argument");
   if (T < 0) return fail(STENCIL_ERR_INVALID_ARG, "T must be >= 0");
   if (p->star) {
-    const int K = star_k_for(p->rad, std::max(1, p->tuning.k));
+    const int K = star_k_for(p->ndim, p->rad, std::max(1, p->tuning.k));
     const int kpass = std::min(K, std::max(1, p->tuning.k));
-    Geom2D g = geom_star(p->rad, K, p->nx, p->ny, p->tuning.seg_len);
-    g.K = kpass;
     ModelParts mp;
     stencil_plan_model_t r{};
-    r.seconds = model_time_star(g, p->rad, p->nx, p->ny, T, &mp);
+    if (p->ndim == 3) {
+      Geom3D g = geom_star3(p->rad, K, p->nx, p->ny, p->nz, p->tuning.seg_len);
+      g.K = kpass;
+      r.seconds = model_time_star3(g, p->rad, p->nx, p->ny, p->nz, T, &mp);
+    } else {
+      Geom2D g = geom_star(p->rad, K, p->nx, p->ny, p->tuning.seg_len);
+      g.K = kpass;
+      r.seconds = model_time_star(g, p->rad, p->nx, p->ny, T, &mp);
+    }
     r.mem_seconds = mp.mem;
     r.alu_seconds = mp.alu;
     r.passes = (T + kpass - 1) / kpass;
@@ -1390,8 +1469,7 @@ stencil_status_t stencil_create_star(stencil_plan_t* out, int ndim, int rad, int
                                      const stencil_tuning_t* tuning, void* hip_stream) {
   if (!out) return fail(STENCIL_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  if (ndim != 2) return fail(ndim == 3 ? STENCIL_ERR_UNSUPPORTED : STENCIL_ERR_INVALID_ARG,
-                             "radius-r star stencils are offered in 2D");
+  if (ndim != 2 && ndim != 3) return fail(STENCIL_ERR_INVALID_ARG, "ndim must be 2 or 3");
   if (rad < 1) return fail(STENCIL_ERR_INVALID_ARG, "rad must be >= 1");
   if (rad > kStarMaxR) return fail(STENCIL_ERR_UNSUPPORTED, "rad is at most 4 (the x-neighbours of a lane's 4 cells)");
   stencil_tuning_t t{};
@@ -1408,23 +1486,30 @@ stencil_status_t stencil_create_star(stencil_plan_t* out, int ndim, int rad, int
   p->star = true;
   p->rad = rad;
   const int* ks;
-  const int nk = star_instantiated(rad, &ks);
+  const int nk = star_inst(ndim, rad, &ks);
   p->tuning = t;
   if (t.variant == 1) {
     p->tuning.k = 1;
-    p->tuning.seg_len = t.seg_len > 0 ? t.seg_len : pick_seg_star(rad, 1, nx, ny);
+    p->tuning.seg_len = t.seg_len > 0 ? t.seg_len : pick_seg_star_nd(p, 1);
   } else if (t.k > 0) {
     p->tuning.variant = 2;
     p->tuning.k = std::min(t.k, ks[nk - 1]);
-    p->tuning.seg_len = t.seg_len > 0 ? t.seg_len : pick_seg_star(rad, star_k_for(rad, p->tuning.k), nx, ny);
+    p->tuning.seg_len = t.seg_len > 0 ? t.seg_len : pick_seg_star_nd(p, star_k_for(ndim, rad, p->tuning.k));
   } else {
     star_tune(p);
   }
-  p->tuning.vec = kTb2dV;
-  p->tuning.bsize_x = 64 * kTb2dV;
+  if (ndim == 3) {
+    p->tuning.vec = 1;
+    p->tuning.bsize_x = p->tuning.bsize_y = kStar3W;
+  } else {
+    p->tuning.vec = kTb2dV;
+    p->tuning.bsize_x = 64 * kTb2dV;
+    p->tuning.bsize_y = 0;
+  }
   p->tuning.nwork = 0;
   if (log_enabled())
-    std::fprintf(stderr, "[stencil] star plan r=%d %dx%d -> k=%d seg=%d\n", rad, nx, ny, p->tuning.k, p->tuning.seg_len);
+    std::fprintf(stderr, "[stencil] star plan r=%d %dx%dx%d -> k=%d seg=%d\n", rad, nx, ny, nz, p->tuning.k,
+                 p->tuning.seg_len);
   return STENCIL_OK;
 }
 
@@ -1436,21 +1521,36 @@ stencil_status_t stencil_run_star(stencil_plan_t p, float* grid, const float* we
   if (T < 0) return fail(STENCIL_ERR_INVALID_ARG, "T must be >= 0");
   if (reinterpret_cast<uintptr_t>(grid) & 3) return fail(STENCIL_ERR_INVALID_ARG, "grid must be 4-byte aligned");
   const int R = p->rad;
-  for (int i = 0; i < 1 + 4 * R; ++i)
+  const int nw = 1 + (p->ndim == 3 ? 6 : 4) * R;
+  for (int i = 0; i < nw; ++i)
     if (!std::isfinite(weights[i])) return fail(STENCIL_ERR_INVALID_ARG, "weights must be finite");
-  StarCoef c{};
-  c.c0 = weights[0];
-  for (int d = 1; d <= R; ++d) {
-    c.w[d - 1] = weights[2 * d - 1];
-    c.e[d - 1] = weights[2 * d];
-    c.s[d - 1] = weights[2 * R + d];
-    c.n[d - 1] = weights[3 * R + d];
+  if (p->ndim == 3) {
+    Star3Coef c{};
+    c.c0 = weights[0];
+    for (int d = 1; d <= R; ++d) {
+      c.w[d - 1] = weights[2 * d - 1];
+      c.e[d - 1] = weights[2 * d];
+      c.s[d - 1] = weights[2 * R + d];
+      c.n[d - 1] = weights[3 * R + d];
+      c.b[d - 1] = weights[4 * R + d];
+      c.a[d - 1] = weights[5 * R + d];
+    }
+    p->star3_cf = c;
+  } else {
+    StarCoef c{};
+    c.c0 = weights[0];
+    for (int d = 1; d <= R; ++d) {
+      c.w[d - 1] = weights[2 * d - 1];
+      c.e[d - 1] = weights[2 * d];
+      c.s[d - 1] = weights[2 * R + d];
+      c.n[d - 1] = weights[3 * R + d];
+    }
+    p->star_cf = c;
   }
-  p->star_cf = c;
   st = set_device(p);
   if (st != STENCIL_OK) return st;
   if (hipError_t e = poison_scratch(p); e != hipSuccess) return hip_fail(e, "poison fill");
-  const int K = star_k_for(R, std::max(1, p->tuning.k));
+  const int K = star_k_for(p->ndim, R, std::max(1, p->tuning.k));
   const int kpass = std::min(K, std::max(1, p->tuning.k));
   int counter = 0;
   return run_sequence(p, KM_STAR, false, K, split_steps(T, kpass), grid, grid, p->scratch, nullptr, nullptr, DevCoef{},

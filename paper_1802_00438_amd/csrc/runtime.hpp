@@ -35,6 +35,9 @@ struct Geom3D {
 Geom2D geom2d(int K, int nx, int ny, int seg);
 // Geometry of a radius-R star pass: halo R*K per side (left halo rounded up to 4).
 Geom2D geom_star(int R, int K, int nx, int ny, int seg);
+// Geometry of a radius-R 3D star pass: 64 x 64 windows with a halo of R*K per side (csx = csy
+// output cells per tile), streamed along z in segments of segz planes.
+Geom3D geom_star3(int R, int K, int nx, int ny, int nz, int segz);
 // Memory and arithmetic parts of a modelled time, summed over the passes (seconds).
 struct ModelParts {
   double mem = 0.0, alu = 0.0;
@@ -45,6 +48,7 @@ double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj
                      ModelParts* parts = nullptr);
 double model_time_3d(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj, ModelParts* parts = nullptr);
 double model_time_star(const Geom2D& g, int R, int nx, int ny, long T, ModelParts* parts = nullptr);
+double model_time_star3(const Geom3D& g, int R, int nx, int ny, int nz, long T, ModelParts* parts = nullptr);
 // The same for the balanced 3D launch of nwork workgroups (equal shares of column planes).
 double model_time_3d_bal(const Geom3D& g, int nx, int ny, int nz, long T, bool hot, bool adj, int nwork,
                          ModelParts* parts = nullptr);
@@ -65,7 +69,8 @@ struct stencil_plan_s {
   int ndim, nx, ny, nz;
   int rad = 1;           // > 0 with star = true: a radius-rad star plan (stencil_create_star)
   bool star = false;
-  StarCoef star_cf{};    // weights of the current stencil_run_star call
+  StarCoef star_cf{};    // weights of the current stencil_run_star call (2D)
+  Star3Coef star3_cf{};  // the same for a 3D plan
   size_t cells;
   hipStream_t stream;
   int device;

@@ -173,8 +173,9 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
 def test_create_star_rejects_bad_arguments_before_device_work():
     L = S.lib()
     h = ctypes.c_void_p(1234)
-    assert L.stencil_create_star(ctypes.byref(h), 3, 2, 8, 8, 8, None, None) == -2  # 3D: unsupported
+    assert L.stencil_create_star(ctypes.byref(h), 4, 2, 8, 8, 8, None, None) == -1  # ndim 2 or 3
     assert h.value is None
+    assert L.stencil_create_star(ctypes.byref(h), 3, 5, 8, 8, 8, None, None) == -2  # 3D rad > 4
     assert L.stencil_create_star(ctypes.byref(h), 2, 0, 8, 8, 1, None, None) == -1  # rad < 1
     assert L.stencil_create_star(ctypes.byref(h), 2, 5, 8, 8, 1, None, None) == -2  # rad > 4
     t = S.Tuning(variant=3)

@@ -201,6 +201,15 @@ def star_field(wl=STAR_WORKLOAD) -> np.ndarray:
     return uniform((wl["ny"], wl["nx"]), 0.0, 1.0, wl["seed"])
 
 
+# The 3D radius-2 workload: the 512^3 grid of the 3D diffusion workload with the weights of
+# STAR3_SETS[2].
+STAR3_WORKLOAD = {"name": "star3d_r2_512", "rad": 2, "nx": 512, "ny": 512, "nz": 512, "T": 100, "seed": 7100}
+
+
+def star3_field(wl=STAR3_WORKLOAD) -> np.ndarray:
+    return uniform((wl["nz"], wl["ny"], wl["nx"]), 0.0, 1.0, wl["seed"])
+
+
 @dataclass
 class BatchGrid:
     ndim: int
