@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # are built without packed FP32, so the 157.3 TFLOP/s packed figure is out of their reach
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 
-SECONDARY = ["plain_hotspot2d_16384", "hotspot2d_phys_16384", "star2d_r2_16384", "diffusion3d_512",
+SECONDARY = ["plain_hotspot2d_16384", "hotspot2d_phys_16384", "star2d_r2_16384", "star3d_r2_512", "diffusion3d_512",
              "diffusion2d_256", "hotspot3d_256", "batched_64", "slab3d_512x512x64"]
 
 
@@ -155,6 +155,34 @@ def tb3d_pass(nx, ny, nz, K, keff, tun, nread, out_bytes_per_cell, flops_per, zl
     return bytes_, flops
 
 
+def star3d_pass(nx, ny, nz, R, K, segz):
+    """Algorithmic HBM bytes and executed FLOPs of one radius-R 3D star pass fusing K steps:
+    every tile reads its 64 x 64 window (inside the grid) over the planes within R*K of its
+    output planes (inside the grid) once, and writes its output cells once; every lane computes
+    K levels of its window cells for each pipeline iteration (output planes + K(2R+1), rounded
+    up to a multiple of 3), at 12R + 1 FLOP per cell and level (a multiply and 6R FMAs)."""
+    W, H = 64, R * K
+    cs = W - 2 * H
+    ntx, nty = math.ceil(nx / cs), math.ceil(ny / cs)
+    segz = max(1, min(segz, nz))
+    nsegz = math.ceil(nz / segz)
+    cols = 0
+    for tx in range(ntx):
+        xw = tx * cs - H
+        wx = min(xw + W, nx) - max(xw, 0)
+        for ty in range(nty):
+            yw = ty * cs - H
+            cols += wx * (min(yw + W, ny) - max(yw, 0))
+    iters = 0
+    for sz in range(nsegz):
+        z0, z1 = sz * segz, min(sz * segz + segz, nz)
+        iters += ((z1 - z0) + K * (2 * R + 1) + 2) // 3 * 3
+    bytes_ = sum(cols * (min(min(sz * segz + segz, nz) + H, nz) - max(sz * segz - H, 0)) for sz in range(nsegz)) * 4
+    bytes_ += nx * ny * nz * 4
+    flops = iters * ntx * nty * W * W * K * (12 * R + 1)
+    return bytes_, flops
+
+
 # ------------------------------------------------------------------ measured traffic records
 
 def source_hash(files):
@@ -170,6 +198,7 @@ KERNEL_SOURCES = {
     "tb2d_diff": ["tb2d.hpp", "device_common.hpp", "k_tb2d_diff.hip"],
     "tb2d_phys": ["tb2d.hpp", "device_common.hpp", "k_tb2d_phys.hip"],
     "star2d": ["star2d.hpp", "device_common.hpp", "k_star2d.hip", "k_star2d_r12.hip"],
+    "star3d": ["star3d.hpp", "star2d.hpp", "device_common.hpp", "k_star3d.hip"],
     "tb3d_diff": ["tb3d.hpp", "device_common.hpp", "k_tb3d_diff.hip"],
     "tb3d_hot": ["tb3d.hpp", "device_common.hpp", "k_tb3d_hot.hip"],
     "tb3d_adj": ["tb3d.hpp", "device_common.hpp", "k_tb3d_adj.hip"],
@@ -502,6 +531,37 @@ def star2d(S, args, dev, stream, copy_gbs):
             "roofline": roof}, study
 
 
+def star3d(S, dev, stream, copy_gbs):
+    import torch
+    from workloads import STAR3_WORKLOAD, STAR3_SETS, star3_field
+    w = STAR3_WORKLOAD
+    x = torch.from_numpy(star3_field(w)).to(dev)
+    shape = (w["nz"], w["ny"], w["nx"])
+    R, T = w["rad"], w["T"]
+    pl = S.StarPlan(R, shape)
+    wt = STAR3_SETS[R]
+    pl.run(x, wt, 4)
+    ms = time_call(lambda: pl.run(x, wt, T), stream, 2)
+    cells = w["nx"] * w["ny"] * w["nz"]
+    g = cells * T / (ms * 1e-3) / 1e9
+    t = pl.tuning
+    K, seg = t["k"], t["seg_len"]
+    lms = time_call(lambda: pl.run(x, wt, 8 * K), stream, 2) / 8
+    b, f = star3d_pass(w["nx"], w["ny"], w["nz"], R, K, seg)
+    roof = roofline("star3d_kernel<%d, %d>" % (R, K), "star3d", {"k": K, "seg_len": seg, "rad": R}, lms, b, f,
+                    copy_gbs)
+    pp = S.StarPlan(R, shape, {"variant": 1})
+    pp.run(x, wt, 2)
+    msp = time_call(lambda: pp.run(x, wt, 20), stream, 1)
+    gp = cells * 20 / (msp * 1e-3) / 1e9
+    study = model_row(S, pl, T, ms, 3, 1, (w["nx"], w["ny"], w["nz"]), (64, 64), rad=R)
+    pl.close()
+    pp.close()
+    return {"gcells": round(g, 1), "ms_per_run": round(ms, 2), "k": K, "seg_len": seg,
+            "gcells_one_step": round(gp, 1), "speedup_vs_one_step": round(g / gp, 2),
+            "pct_single_pass_roofline": round(100 * g / (HBM_PEAK_GBS / 8), 1), "roofline": roof}, study
+
+
 def diffusion3d(S, dev, stream, copy_gbs):
     import torch
     from workloads import WORKLOADS, DIFFUSION
@@ -745,6 +805,7 @@ def main():
     torch.cuda.empty_cache()
     runners = [("hotspot2d_phys_16384", lambda: phys2d(S, dev, stream, copy_gbs)),
                ("star2d_r2_16384", lambda: star2d(S, args, dev, stream, copy_gbs)),
+               ("star3d_r2_512", lambda: star3d(S, dev, stream, copy_gbs)),
                ("diffusion3d_512", lambda: diffusion3d(S, dev, stream, copy_gbs)),
                ("diffusion2d_256", lambda: diffusion2d_small(S, dev, stream, copy_gbs)),
                ("hotspot3d_256", lambda: hotspot3d(S, dev, stream, copy_gbs)),

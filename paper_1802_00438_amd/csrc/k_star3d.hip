@@ -4,6 +4,8 @@
 
 // Instantiated fused-step counts per radius: the K levels' held planes and partial sums (2R+1
 // values per lane cell and level) must fit 128 VGPRs (16 waves per workgroup) without spills.
+// Every count from 1 to the largest is instantiated: a pass runs on the kernel whose K is the
+// number of steps it fuses.
 static const int kStar3K1[] = {1, 2, 3};
 static const int kStar3K23[] = {1, 2};
 static const int kStar3K4[] = {1};
@@ -23,7 +25,7 @@ int star3_instantiated(int R, const int** ks) {
 
 hipError_t launch_star3d(int R, int K, const Star3dArgs& a, hipStream_t s) {
   const long nbl = (long)a.ntx * a.nty * a.nsegz;
-  if (nbl <= 0 || nbl > 0x7fffffffL || a.keff < 1 || a.keff > K || a.cs != kStar3W - 2 * R * K)
+  if (nbl <= 0 || nbl > 0x7fffffffL || a.keff != K || a.cs != kStar3W - 2 * R * K)
     return hipErrorInvalidValue;
   const unsigned nb = (unsigned)nbl;
   switch (R) {

@@ -17,17 +17,21 @@
 //     order c, (w_d, e_d), s_d, n_d, b_d, a_d of the evaluation chain, and the R partial sums
 //     take the place of the R planes ahead that a window of 2R+1 planes would hold.
 //   * In-plane neighbours come from LDS: every level publishes its newest plane into a padded
-//     (64+2R)^2 LDS plane, double-buffered by plane parity, so one barrier per plane serves
-//     every level; level s consumes the plane that level s-1 published in the previous
-//     iteration, so it runs R+1 planes behind level s-1.  y neighbours within a lane's own
-//     four rows come from its registers.  Reads past the window edge land in the padding; they
-//     feed only halo cells whose results are never stored.
+//     (64+2R)^2 LDS plane, in one of three buffers taken in turn, so one barrier per plane
+//     serves every level; level s consumes the plane that level s-1 published in the previous
+//     iteration, so it runs R+1 planes behind level s-1.  Input planes land in three register
+//     slots, loaded two planes ahead; the loop is unrolled by three so that every slot and LDS
+//     buffer is a fixed register set or address and no load result is copied (a copy would
+//     wait for the load at once).  y neighbours within a lane's own four rows come from its
+//     registers.  Reads past the window edge land in the padding; they feed only halo cells
+//     whose results are never stored.
 //   * Clamp (Section 5.1, at every distance and every step): in tiles whose window reaches
 //     past an x or y edge of the grid, the neighbour at distance d is replaced by the one at
 //     distance d-1 where x-d (x+d, y-d, y+d) leaves the grid, which makes it the nearest
 //     boundary cell.  Along z, a level sets every held plane to plane 0 when plane 0 arrives,
 //     and takes its last held plane (plane nz-1) in place of planes past the top.
-//   * A pass that fuses keff < K steps turns the levels past keff into delay lines of R planes.
+//   * Every step count from 1 to the largest k is instantiated, so a pass always runs on the
+//     kernel whose K equals the steps it fuses.
 #pragma once
 #include "device_common.hpp"
 #include "star2d.hpp"
@@ -41,7 +45,7 @@ struct Star3dArgs {
   const float* src;
   float* dst;
   int nx, ny, nz;
-  int keff;         // steps fused in this pass, 1..K
+  int keff;         // steps fused in this pass (equal to K)
   int cs;           // output cells per tile in x and y (64 - 2*R*K)
   int ntx, nty;     // tiles along x and y
   int segz, nsegz;  // output planes per tile, tiles along z
@@ -53,8 +57,10 @@ constexpr int kStar3RY = 4;         // rows per lane
 constexpr int kStar3Threads = 1024;  // 16 waves
 
 constexpr int star3_lw(int R) { return kStar3W + 2 * R; }
-// LDS floats of a (R, K) kernel: two parities x K levels x one padded plane
-constexpr int star3_lds_floats(int R, int K) { return 2 * K * star3_lw(R) * star3_lw(R); }
+constexpr int star3_gcd(int a, int b) { return b == 0 ? a : star3_gcd(b, a % b); }
+constexpr int star3_lcm(int a, int b) { return a / star3_gcd(a, b) * b; }
+// LDS floats of a (R, K) kernel: three buffers x K levels x one padded plane
+constexpr int star3_lds_floats(int R, int K) { return 3 * K * star3_lw(R) * star3_lw(R); }
 
 template <int R, int K>
 struct Star3dTile {
@@ -66,24 +72,32 @@ struct Star3dTile {
   const Star3dArgs& a;
   float* lds;
   int gx, gy0, ox0, ox1, oy0, oy1, z0, z1, i0;
-  int goff[RY];  // in-plane offsets of the lane's cells (clamped to the grid)
+  unsigned goff[RY];  // in-plane byte offsets of the lane's cells (clamped to the grid)
   int lidx;      // LDS index of the lane's first cell within one plane
-  float hist[K][R][RY];  // level s: planes q-1 .. q-R of level s-1
-  float pend[K][R][RY];  // level s: partial sums of its planes q-1 .. q-R (newest first)
-  float out[K][RY];      // out[0]: the input plane; out[s]: level s's newest plane
-  float lb[2][RY];       // input planes loaded two iterations ahead
+  // Rings addressed by the iteration phase u (it mod U, a compile-time constant):
+  //   hist[s-1][(u - d) mod HS]: plane q-d of level s-1 (d = 1..R); plane q goes to slot u mod HS
+  //   pend[s-1][(u - j) mod PS]: level s's partial sum of plane q-j (j = 0..R); the sum of
+  //   plane q-R completes in iteration u and stays in its slot through iteration u+1, where
+  //   level s+1 takes it as its input plane (so PS = R+1 when a level above reads it).
+  static constexpr int HS = R;
+  static constexpr int PS = K > 1 ? R + 1 : R;
+  static constexpr int U = star3_lcm(3, star3_lcm(HS, PS));
+  float hist[K][HS][RY];
+  float pend[K][PS][RY];
+  float lb[3][RY];  // input planes i-1, i, i+1 (plane i0 + it in slot it mod 3)
 
   __device__ __forceinline__ Star3dTile(const Star3dArgs& args, float* l) : a(args), lds(l) {}
 
+  // (a uniform plane base plus 32-bit lane offsets: the loads take the scalar-base form)
   __device__ __forceinline__ void load_plane(int z, float (&dstv)[RY]) const {
-    const float* pl = a.src + (size_t)clampi(z, 0, a.nz - 1) * a.nx * a.ny;
+    const char* pl = reinterpret_cast<const char*>(a.src + (size_t)clampi(z, 0, a.nz - 1) * a.nx * a.ny);
 #pragma unroll
-    for (int j = 0; j < RY; ++j) dstv[j] = pl[goff[j]];
+    for (int j = 0; j < RY; ++j) dstv[j] = *reinterpret_cast<const float*>(pl + goff[j]);
   }
 
   // New partial sum of plane q at level s from Q (level s-1's plane q, own cells), the
   // neighbours of that plane in LDS plane rp, and the held planes.
-  template <bool EDGE>
+  template <int u, bool EDGE>
   __device__ __forceinline__ void open_sum(int s, const float (&Q)[RY], const float* rp, float (&nw)[RY]) const {
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
@@ -125,103 +139,105 @@ struct Star3dTile {
         acc = __builtin_fmaf(a.cf.n[d - 1], yn, acc);
       }
 #pragma unroll
-      for (int d = 1; d <= R; ++d) acc = __builtin_fmaf(a.cf.b[d - 1], hist[s - 1][d - 1][j], acc);
+      for (int d = 1; d <= R; ++d) acc = __builtin_fmaf(a.cf.b[d - 1], hist[s - 1][(u - d + 4 * HS) % HS][j], acc);
       nw[j] = acc;
     }
   }
 
-  // Iteration it (input plane i = i0 + it arrives); P = it % 2 selects the LDS parity and the
-  // load slot.
-  template <int P, bool EDGE>
+  // Iteration it (input plane i = i0 + it arrives) at phase u = it mod U; P = u mod 3 selects
+  // the LDS buffer written and the load slot of plane i.  TOP: some level may be past the top
+  // plane (q >= nz), which only the last iterations of a tile can be.
+  template <int u, bool EDGE, bool TOP>
   __device__ __forceinline__ void iter(int it) {
+    constexpr int P = u % 3, PP = (P + 2) % 3;  // PP: the previous iteration's buffer, plane i-1's slot
+    constexpr int SH = u % HS, SP = u % PS;
     const int i = i0 + it;
-    const float* rd = lds + (P ^ 1) * K * PL;  // planes published in the previous iteration
+    const float* rd = lds + PP * K * PL;  // planes published in the previous iteration
     float* wr = lds + P * K * PL;
     const size_t plane = (size_t)a.nx * a.ny;
-    // top level first: level s reads out[s-1] before level s-1 replaces it
+    // top level first: level s takes level s-1's plane completed in the previous iteration
+    // before level s-1 runs
 #pragma unroll
     for (int s = K; s >= 1; --s) {
       const int q = i - 1 - (s - 1) * (R + 1);  // plane of level s-1 that level s takes now
       if (q < 0) continue;                       // uniform: the pipeline is still filling
-      const bool act = s <= a.keff;
-      const bool past = q >= a.nz;
+      const bool past = TOP && q >= a.nz;
       float Q[RY];
 #pragma unroll
-      for (int j = 0; j < RY; ++j) Q[j] = past ? hist[s - 1][0][j] : out[s - 1][j];
-      if (act) {
-#pragma unroll
-        for (int u = 0; u < R; ++u)
-#pragma unroll
-          for (int j = 0; j < RY; ++j) pend[s - 1][u][j] = __builtin_fmaf(a.cf.a[u], Q[j], pend[s - 1][u][j]);
-      }
-      float done[RY];
-#pragma unroll
-      for (int j = 0; j < RY; ++j) done[j] = pend[s - 1][R - 1][j];
-      float nw[RY];
-      if (!past) {
-        if (q == 0) {
-#pragma unroll
-          for (int d = 0; d < R; ++d)
-#pragma unroll
-            for (int j = 0; j < RY; ++j) hist[s - 1][d][j] = Q[j];
-        }
-        if (act) {
-          open_sum<EDGE>(s, Q, rd + (s - 1) * PL, nw);
-        } else {
-#pragma unroll
-          for (int j = 0; j < RY; ++j) nw[j] = Q[j];
-        }
-#pragma unroll
-        for (int d = R - 1; d >= 1; --d)
-#pragma unroll
-          for (int j = 0; j < RY; ++j) hist[s - 1][d][j] = hist[s - 1][d - 1][j];
-#pragma unroll
-        for (int j = 0; j < RY; ++j) hist[s - 1][0][j] = Q[j];
-      } else {
-#pragma unroll
-        for (int j = 0; j < RY; ++j) nw[j] = Q[j];
+      for (int j = 0; j < RY; ++j) {
+        // level s-1's plane completed in iteration it-1: its slot (u-1-R) mod PS = u mod PS
+        const float v = s == 1 ? lb[PP][j] : pend[s > 1 ? s - 2 : 0][SP][j];
+        Q[j] = past ? hist[s - 1][(u - 1 + HS) % HS][j] : v;  // past the top: plane nz-1
       }
 #pragma unroll
-      for (int u = R - 1; u >= 1; --u)
-#pragma unroll
-        for (int j = 0; j < RY; ++j) pend[s - 1][u][j] = pend[s - 1][u - 1][j];
-#pragma unroll
-      for (int j = 0; j < RY; ++j) pend[s - 1][0][j] = nw[j];
-      if (s < K) {
+      for (int t = 0; t < R; ++t)  // plane q is z+1+t of the sum of plane q-1-t
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
-          out[s][j] = done[j];
-          wr[s * PL + lidx + j * LW] = done[j];
+          float& ps = pend[s - 1][(u - 1 - t + 4 * PS) % PS][j];
+          ps = __builtin_fmaf(a.cf.a[t], Q[j], ps);
         }
-      } else {
-        const int p = q - R;  // the plane level K completes now
+      constexpr int SD = (u - R + 4 * PS) % PS;  // the sum of plane q-R, complete now
+      if (s == K) {
+        const int p = q - R;
         if (p >= z0 && p < z1 && gx >= ox0 && gx < ox1) {
-          float* dp = a.dst + (size_t)p * plane;
+          // an output cell is inside the grid, where goff is its unclamped offset
+          char* dp = reinterpret_cast<char*>(a.dst + (size_t)p * plane);
 #pragma unroll
           for (int j = 0; j < RY; ++j) {
             const int gy = gy0 + j;
-            if (gy >= oy0 && gy < oy1) dp[(size_t)gy * a.nx + gx] = done[j];
+            if (gy >= oy0 && gy < oy1) *reinterpret_cast<float*>(dp + goff[j]) = pend[s - 1][SD][j];
           }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < RY; ++j) wr[s * PL + lidx + j * LW] = pend[s - 1][SD][j];
+      }
+      if (!past) {
+        if (q == 0) {
+#pragma unroll
+          for (int d = 0; d < HS; ++d)
+#pragma unroll
+            for (int j = 0; j < RY; ++j) hist[s - 1][d][j] = Q[j];
+        }
+        float nw[RY];
+        open_sum<u, EDGE>(s, Q, rd + (s - 1) * PL, nw);
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+          pend[s - 1][SP][j] = nw[j];
+          hist[s - 1][SH][j] = Q[j];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+          pend[s - 1][SP][j] = Q[j];
+          hist[s - 1][SH][j] = Q[j];  // the newest slot keeps plane nz-1
         }
       }
     }
-    // level 0: publish input plane i, load plane i + 2 into the freed slot
+    // level 0: publish input plane i; plane i+2 goes to the slot of plane i-1, which level 1
+    // has just consumed
 #pragma unroll
-    for (int j = 0; j < RY; ++j) {
-      out[0][j] = lb[P][j];
-      wr[lidx + j * LW] = lb[P][j];
-    }
-    load_plane(i + 2, lb[P]);
+    for (int j = 0; j < RY; ++j) wr[lidx + j * LW] = lb[P][j];
+    load_plane(i + 2, lb[PP]);
     __syncthreads();
+  }
+
+  template <int u, bool EDGE, bool TOP>
+  __device__ __forceinline__ void iters(int it) {
+    if constexpr (u < U) {
+      iter<u, EDGE, TOP>(it + u);
+      iters<u + 1, EDGE, TOP>(it);
+    }
   }
 
   template <bool EDGE>
   __device__ __forceinline__ void run() {
     const int nit = (z1 - z0) + K * (2 * R + 1);
-    for (int it = 0; it < nit; it += 2) {
-      iter<0, EDGE>(it);
-      iter<1, EDGE>(it + 1);  // one surplus iteration when nit is odd: it stores nothing
-    }
+    // iterations it with i0 + it - 1 < nz have every level below the top plane
+    const int nlow = min(nit, a.nz + 1 - i0);
+    int it = 0;
+    for (; it + U <= nlow; it += U) iters<0, EDGE, false>(it);
+    for (; it < nit; it += U) iters<0, EDGE, true>(it);  // surplus iterations store nothing
   }
 
   __device__ __forceinline__ void process(int tile) {
@@ -242,20 +258,21 @@ struct Star3dTile {
     i0 = z0 - R * K;
     lidx = (wave * RY + R) * LW + lane + R;
 #pragma unroll
-    for (int j = 0; j < RY; ++j) goff[j] = clampi(gy0 + j, 0, a.ny - 1) * a.nx + clampi(gx, 0, a.nx - 1);
+    for (int j = 0; j < RY; ++j)
+      goff[j] = 4u * (unsigned)(clampi(gy0 + j, 0, a.ny - 1) * a.nx + clampi(gx, 0, a.nx - 1));
 #pragma unroll
     for (int s = 0; s < K; ++s)
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
-        out[s][j] = 0.0f;
 #pragma unroll
-        for (int d = 0; d < R; ++d) {
-          hist[s][d][j] = 0.0f;
-          pend[s][d][j] = 0.0f;
-        }
+        for (int d = 0; d < HS; ++d) hist[s][d][j] = 0.0f;
+#pragma unroll
+        for (int d = 0; d < PS; ++d) pend[s][d][j] = 0.0f;
       }
     load_plane(i0, lb[0]);
     load_plane(i0 + 1, lb[1]);
+#pragma unroll
+    for (int j = 0; j < RY; ++j) lb[2][j] = 0.0f;  // "plane i0-1": level 1 takes nothing before i0
     const bool edge = (xw < 0) || (xw + kStar3W > a.nx) || (yw < 0) || (yw + kStar3W > a.ny);
     if (edge) run<true>();
     else run<false>();

@@ -95,3 +95,17 @@ def test_binding_rejects_host_tensors_before_any_library_call():
         S.run(x, SETS["D2"], 1)
     with pytest.raises(ValueError):
         S._check_tensor(torch.zeros(8, 8, dtype=torch.float64), "x")
+
+
+def test_star3d_pass_counts_windows_and_pipeline():
+    """A grid inside one window and one segment is read once and written once; the 512^3
+    radius-2 pass reads each cell about (64/56)^2 x (103+8)/103 times."""
+    b, f = bench.star3d_pass(9, 7, 5, 1, 1, 100)
+    assert b == 9 * 7 * 5 * 4 * 2
+    assert f == ((5 + 3 + 2) // 3 * 3) * 64 * 64 * 13
+    b, f = bench.star3d_pass(512, 512, 512, 2, 2, 103)
+    cs = 64 - 8
+    ntx = math.ceil(512 / cs)
+    reads = b / (512 ** 3 * 4) - 1.0
+    assert (64 / cs) ** 2 < reads < (64 / cs) ** 2 * (103 + 8) / 103 * 1.01
+    assert f == sum(((min(z + 103, 512) - z) + 10 + 2) // 3 * 3 for z in range(0, 512, 103)) * ntx * ntx * 4096 * 2 * 25
