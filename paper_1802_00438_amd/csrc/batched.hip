@@ -13,7 +13,9 @@
 //
 // Each grid uses an even number of passes (the steps spread over them), so its result ends in
 // the caller's buffer.  The flag reset and both persistent kernels are captured once in a HIP
-// graph and replayed; the reset is a fill kernel, not a memset node.
+// graph and replayed; the reset is a fill kernel, not a memset node.  In the graph the 2D and
+// 3D kernels are parallel branches on a split of the CUs (see plan_batch); the no-allocation
+// path runs them one after the other on the whole device.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -215,6 +217,8 @@ struct BPlan {
   std::vector<BItem> it2, it3;
   int nflags = 0;
   int g2 = 1, g3 = 1;  // persistent workgroups of the 2D and 3D launches
+  bool concurrent = false;  // the two launches run side by side on disjoint CUs
+  double w2 = 0.0, w3 = 0.0;  // modelled work of the two halves (item work units, summed)
   std::vector<int> passes, ntiles, seg;
 };
 
@@ -264,13 +268,28 @@ int spin_limit() {
   return 1 << 25;
 }
 
-// Enqueue the reset and the two persistent kernels on stream s.
-hipError_t enqueue_launch(const BPlan& P, const BLayout& L, unsigned char* base, int clear_err, hipStream_t s) {
+// Enqueue the reset and the two persistent kernels on stream s.  With a second stream s3 (and
+// two events), the 3D kernel runs on s3 concurrently with the 2D kernel on s, forked after the
+// reset and joined back into s.
+hipError_t enqueue_launch(const BPlan& P, const BLayout& L, unsigned char* base, int clear_err, hipStream_t s,
+                          hipStream_t s3 = nullptr, hipEvent_t fork = nullptr, hipEvent_t join = nullptr) {
   BLaunch a2, a3;
   launch_args(P, L, base, spin_limit(), &a2, &a3);
   const int nr = std::max(P.nflags, 3);
   hipLaunchKernelGGL(reset_kernel, dim3((nr + 255) / 256), dim3(256), 0, s, a2.flags, P.nflags,
                      reinterpret_cast<int*>(base + L.counters), clear_err);
+  const bool both = !P.it2.empty() && !P.it3.empty() && s3 && fork && join;
+  if (both) {
+    hipError_t e = hipEventRecord(fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s3, fork, 0);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batched3d_kernel, dim3(P.g3), dim3(64 * kBatchNW3), 0, s3, a3);
+    hipLaunchKernelGGL(batched2d_kernel, dim3(P.g2), dim3(64), 0, s, a2);
+    e = hipEventRecord(join, s3);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+  }
   if (!P.it2.empty()) hipLaunchKernelGGL(batched2d_kernel, dim3(P.g2), dim3(64), 0, s, a2);
   if (!P.it3.empty()) hipLaunchKernelGGL(batched3d_kernel, dim3(P.g3), dim3(64 * kBatchNW3), 0, s, a3);
   return hipGetLastError();
@@ -401,7 +420,8 @@ std::vector<int> choose_segments(const std::vector<int>& idx, const std::vector<
 
 // Plan a batch: per-grid pass split and tiling, the flag offsets and the two work lists in
 // claim order.  partners[i] is grid i's ping-pong partner (device, same size as the grid).
-BPlan plan_batch(int n, const stencil_batch_item_t* items, float* const* partners) {
+// concurrent: the launch may run the two halves side by side (the graph path).
+BPlan plan_batch(int n, const stencil_batch_item_t* items, float* const* partners, bool concurrent) {
   BPlan P;
   P.grids.resize(n);
   std::vector<std::vector<int>> steps(n);
@@ -500,16 +520,37 @@ BPlan plan_batch(int n, const stencil_batch_item_t* items, float* const* partner
   std::stable_sort(k3.begin(), k3.end(), order);
   for (const Keyed& x : k2) P.it2.push_back(x.it);
   for (const Keyed& x : k3) P.it3.push_back(x.it);
-  // persistent grid sizes: resident capacity of the device
+  for (const BItem& it : P.it2) P.w2 += t_item[it.g];
+  for (const BItem& it : P.it3) P.w3 += t_item[it.g];
+  // Persistent grid sizes: the resident capacity of the device.  With both dimensionalities
+  // and `concurrent`, the two launches run side by side on a split of the CUs (a 3D
+  // workgroup takes a whole CU's registers, so the halves cannot share a CU): the 3D half
+  // gets the share kappa*w3 / (w2 + kappa*w3) of the CUs, clamped to [1/8, 7/8].  kappa = 2.4,
+  // the cost of a 3D item-work unit relative to a 2D one per CU, is the ratio at which the
+  // split met the measured optimum on the 64-grid batch (160 of 256 CUs: 39.8 ms, against
+  // 41.8 / 40.7 / 44.4 / 45.6 ms at 144 / 152 / 168 / 176 CUs and 45.1 ms back to back).
+  // STENCIL_BATCH_SPLIT sets the 3D CUs instead (0: back to back).
   P.g2 = std::max(1, std::min((int)P.it2.size(), slots2));
   P.g3 = std::max(1, std::min((int)P.it3.size(), slots3));
+  if (concurrent && !P.it2.empty() && !P.it3.empty()) {
+    constexpr double kappa = 2.4;
+    int c3 = (int)std::lround(d.cus * kappa * P.w3 / (P.w2 + kappa * P.w3));
+    c3 = std::max(d.cus / 8, std::min(d.cus - d.cus / 8, c3));
+    const char* sp = std::getenv("STENCIL_BATCH_SPLIT");
+    if (sp && *sp) c3 = std::max(0, std::min(d.cus - 1, std::atoi(sp)));
+    if (c3 > 0) {
+      P.g3 = std::max(1, std::min((int)P.it3.size(), c3 * std::max(1, occ3)));
+      P.g2 = std::max(1, std::min((int)P.it2.size(), (d.cus - c3) * std::max(1, occ2)));
+      P.concurrent = true;
+    }
+  }
   return P;
 }
 
 void log_plan(int n, const stencil_batch_item_t* items, const BPlan& P, const char* how) {
   if (!log_enabled()) return;
-  std::fprintf(stderr, "[stencil] batch (%s): %d grids, %zu 2D items (%d WGs), %zu 3D items (%d WGs)\n", how, n,
-               P.it2.size(), P.g2, P.it3.size(), P.g3);
+  std::fprintf(stderr, "[stencil] batch (%s): %d grids, %zu 2D items (%d WGs), %zu 3D items (%d WGs), work %.4g / %.4g%s\n",
+               how, n, P.it2.size(), P.g2, P.it3.size(), P.g3, P.w2, P.w3, P.concurrent ? ", concurrent" : "");
   for (int i = 0; i < n; ++i)
     std::fprintf(stderr, "[stencil]   grid %d: %dD %dx%dx%d T=%d passes=%d tiles=%d seg=%d\n", i, items[i].ndim,
                  items[i].nx, items[i].ny, items[i].nz, items[i].T, P.passes[i], P.ntiles[i], P.seg[i]);
@@ -532,7 +573,7 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
     }
     b->scratch.push_back(s);
   }
-  const BPlan P = plan_batch(n, items, b->scratch.data());
+  const BPlan P = plan_batch(n, items, b->scratch.data(), true);
   const BLayout L = layout_of(P);
   b->n2 = (int)P.it2.size();
   b->n3 = (int)P.it3.size();
@@ -554,15 +595,24 @@ stencil_status_t build(int n, const stencil_batch_item_t* items, hipStream_t str
   }
   if (b->err_host) *b->err_host = 0;
   // capture: reset flags/counters, then the two persistent kernels
-  hipStream_t cs = nullptr;
+  hipStream_t cs = nullptr, cs3 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess && P.concurrent) {
+    e = hipStreamCreateWithFlags(&cs3, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+  }
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    const hipError_t le = enqueue_launch(P, L, base, 0, cs);
+    const hipError_t le = enqueue_launch(P, L, base, 0, cs, cs3, fork, join);
     e = hipStreamEndCapture(cs, &b->graph);
     if (e == hipSuccess) e = le;
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (fork) hipEventDestroy(fork);
+  if (join) hipEventDestroy(join);
+  if (cs3) hipStreamDestroy(cs3);
   if (cs) hipStreamDestroy(cs);
   if (e != hipSuccess) {
     stencil_status_t st = hip_fail(e, "graph capture");
@@ -706,7 +756,7 @@ stencil_status_t stencil_run_batched_noalloc(int n, const stencil_batch_item_t* 
   }
   if (n == 0) return STENCIL_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-  const BPlan P = plan_batch(n, items, partners);
+  const BPlan P = plan_batch(n, items, partners, false);
   const BLayout L = layout_of(P);
   if (L.total > kNoAllocScratchBytes)
     return fail(STENCIL_ERR_INVALID_ARG, "the batch needs " + std::to_string(L.total) +
