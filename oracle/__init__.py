@@ -88,6 +88,13 @@ def _load():
                 st3 = getattr(lib, "oracle_star3d_" + suf)
                 st3.restype = ctypes.c_int
                 st3.argtypes = [ctypes.c_int] * 4 + [ctypes.POINTER(ctypes.c_float), p, ctypes.c_int]
+                fp = ctypes.POINTER(ctypes.c_float)
+                ss = getattr(lib, "oracle_star2d_src_" + suf)
+                ss.restype = ctypes.c_int
+                ss.argtypes = [ctypes.c_int] * 3 + [fp, fp, p, p, ctypes.c_int]
+                ss3 = getattr(lib, "oracle_star3d_src_" + suf)
+                ss3.restype = ctypes.c_int
+                ss3.argtypes = [ctypes.c_int] * 4 + [fp, fp, p, p, ctypes.c_int]
             lib.oracle_num_threads.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -168,14 +175,28 @@ def adjoint(cot, coeffs, T, form=DIFFUSION, dtype=np.float64, want_grad_p=None):
     return gx, gp
 
 
-def star2d(x0, weights, T, dtype=np.float64):
-    """T clamped Jacobi steps of the radius-r 2D star stencil (diffusion form) on ``x0`` of
-    shape (ny, nx).  ``weights`` has 1 + 4r entries: cc, then w_d, e_d for d = 1..r, then
-    s_1..s_r, then n_1..n_r (FP32 values; the FP64 run promotes them exactly)."""
+def _star_source(power, src, shape, dtype):
+    """The hotspot-form arguments of the radius-r oracles: the power map in the working
+    precision and src = (cp, c_amb, t_amb) as FP32 values, or (None, None)."""
+    if power is None:
+        return None, None
+    if src is None or len(src) != 3:
+        raise ValueError("the hotspot form needs src = (cp, c_amb, t_amb)")
+    pw = _prep(power, dtype)
+    if pw.shape != tuple(shape):
+        raise ValueError("power must have the grid's shape")
+    return pw, np.ascontiguousarray(src, dtype=np.float32)
+
+
+def star2d(x0, weights, T, dtype=np.float64, power=None, src=None):
+    """T clamped Jacobi steps of the radius-r 2D star stencil on ``x0`` of shape (ny, nx).
+    ``weights`` has 1 + 4r entries: cc, then w_d, e_d for d = 1..r, then s_1..s_r, then
+    n_1..n_r (FP32 values; the FP64 run promotes them exactly).  Diffusion form by default; with
+    ``power`` (same shape) and ``src`` = (cp, c_amb, t_amb) the hotspot form, whose chain starts
+    from fma(cc, c, q) with q = fma(cp, p, c_amb*t_amb) as for radius 1."""
     lib = _load()
     dtype = np.dtype(dtype)
     ct = ctypes.c_double if dtype == np.float64 else ctypes.c_float
-    fn = lib.oracle_star2d_f64 if dtype == np.float64 else lib.oracle_star2d_f32
     g = _prep(x0, dtype)
     if g.ndim != 2:
         raise ValueError("the radius-r stencil is 2D: shape (ny, nx)")
@@ -183,21 +204,27 @@ def star2d(x0, weights, T, dtype=np.float64):
     if w.size < 5 or (w.size - 1) % 4:
         raise ValueError("weights must have 1 + 4r entries")
     rad = (w.size - 1) // 4
-    rc = fn(rad, g.shape[1], g.shape[0], _ptr(w, ctypes.c_float), _ptr(g, ct), int(T))
+    pw, sv = _star_source(power, src, g.shape, dtype)
+    if pw is None:
+        fn = lib.oracle_star2d_f64 if dtype == np.float64 else lib.oracle_star2d_f32
+        rc = fn(rad, g.shape[1], g.shape[0], _ptr(w, ctypes.c_float), _ptr(g, ct), int(T))
+    else:
+        fn = lib.oracle_star2d_src_f64 if dtype == np.float64 else lib.oracle_star2d_src_f32
+        rc = fn(rad, g.shape[1], g.shape[0], _ptr(w, ctypes.c_float), _ptr(sv, ctypes.c_float), _ptr(pw, ct),
+                _ptr(g, ct), int(T))
     if rc != 0:
         raise ValueError("oracle_star2d rejected its arguments")
     return g
 
 
-def star3d(x0, weights, T, dtype=np.float64):
-    """T clamped Jacobi steps of the radius-r 3D star stencil (diffusion form) on ``x0`` of
-    shape (nz, ny, nx).  ``weights`` has 1 + 6r entries: cc, then w_d, e_d for d = 1..r, then
-    s_1..s_r (y+d), n_1..n_r (y-d), b_1..b_r (z-d), a_1..a_r (z+d) (FP32 values; the FP64 run
-    promotes them exactly)."""
+def star3d(x0, weights, T, dtype=np.float64, power=None, src=None):
+    """T clamped Jacobi steps of the radius-r 3D star stencil on ``x0`` of shape (nz, ny, nx).
+    ``weights`` has 1 + 6r entries: cc, then w_d, e_d for d = 1..r, then s_1..s_r (y+d),
+    n_1..n_r (y-d), b_1..b_r (z-d), a_1..a_r (z+d) (FP32 values; the FP64 run promotes them
+    exactly).  ``power`` and ``src`` as for star2d."""
     lib = _load()
     dtype = np.dtype(dtype)
     ct = ctypes.c_double if dtype == np.float64 else ctypes.c_float
-    fn = lib.oracle_star3d_f64 if dtype == np.float64 else lib.oracle_star3d_f32
     g = _prep(x0, dtype)
     if g.ndim != 3:
         raise ValueError("the 3D radius-r stencil takes (nz, ny, nx) grids")
@@ -205,7 +232,14 @@ def star3d(x0, weights, T, dtype=np.float64):
     if w.size < 7 or (w.size - 1) % 6:
         raise ValueError("weights must have 1 + 6r entries")
     rad = (w.size - 1) // 6
-    rc = fn(rad, g.shape[2], g.shape[1], g.shape[0], _ptr(w, ctypes.c_float), _ptr(g, ct), int(T))
+    pw, sv = _star_source(power, src, g.shape, dtype)
+    if pw is None:
+        fn = lib.oracle_star3d_f64 if dtype == np.float64 else lib.oracle_star3d_f32
+        rc = fn(rad, g.shape[2], g.shape[1], g.shape[0], _ptr(w, ctypes.c_float), _ptr(g, ct), int(T))
+    else:
+        fn = lib.oracle_star3d_src_f64 if dtype == np.float64 else lib.oracle_star3d_src_f32
+        rc = fn(rad, g.shape[2], g.shape[1], g.shape[0], _ptr(w, ctypes.c_float), _ptr(sv, ctypes.c_float),
+                _ptr(pw, ct), _ptr(g, ct), int(T))
     if rc != 0:
         raise ValueError("oracle_star3d rejected its arguments")
     return g

@@ -219,13 +219,23 @@ ORACLE_DEFINE(float, f32, fmaf)
  *   wts[0] = cc; for d = 1..rad: wts[2d-1] = w_d, wts[2d] = e_d;
  *   wts[2rad+d] = s_d (d = 1..rad); wts[3rad+d] = n_d (d = 1..rad).
  * With rad = 1 this is the chain c, w, e, s, n of the radius-1 diffusion forward above.
+ * Hotspot form (oracle_star2d_src_*, power non-NULL): the radius-1 hotspot source carried over
+ * to radius r, q = fma(cp, p, c_amb*t_amb) per cell (src = {cp, c_amb, t_amb}, c_amb*t_amb
+ * rounded once in the working precision) and the chain starts from fma(cc, c, q), as the
+ * radius-1 hotspot forward does; power NULL is the diffusion form.
  */
 #define ORACLE_STAR_DEFINE(REAL, SUF, FMA)                                                       \
-  int oracle_star2d_##SUF(int rad, int nx, int ny, const float* wts, REAL* grid, int T) {       \
+  int oracle_star2d_src_##SUF(int rad, int nx, int ny, const float* wts, const float* src,      \
+                              const REAL* power, REAL* grid, int T) {                          \
     if (rad < 1 || nx < 1 || ny < 1 || T < 0) return -1;                                       \
     const long n = (long)nx * ny;                                                              \
     REAL* buf = (REAL*)malloc(sizeof(REAL) * (size_t)n);                                       \
-    if (!buf) return -1;                                                                       \
+    REAL* q = power ? (REAL*)malloc(sizeof(REAL) * (size_t)n) : NULL;                          \
+    if (!buf || (power && !q)) { free(buf); free(q); return -1; }                              \
+    if (power) {                                                                               \
+      const REAL kamb = (REAL)src[1] * (REAL)src[2];                                           \
+      for (long i = 0; i < n; ++i) q[i] = FMA((REAL)src[0], power[i], kamb);                   \
+    }                                                                                          \
     REAL* v = grid;                                                                            \
     REAL* o = buf;                                                                             \
     for (int t = 0; t < T; ++t) {                                                              \
@@ -233,7 +243,7 @@ ORACLE_DEFINE(float, f32, fmaf)
       for (long y = 0; y < ny; ++y) {                                                          \
         const REAL* row = v + y * nx;                                                          \
         for (long x = 0; x < nx; ++x) {                                                        \
-          REAL acc = (REAL)wts[0] * row[x];                                                    \
+          REAL acc = q ? FMA((REAL)wts[0], row[x], q[y * nx + x]) : (REAL)wts[0] * row[x];     \
           for (int d = 1; d <= rad; ++d) {                                                     \
             acc = FMA((REAL)wts[2 * d - 1], row[clampl(x - d, 0, nx - 1)], acc);               \
             acc = FMA((REAL)wts[2 * d], row[clampl(x + d, 0, nx - 1)], acc);                   \
@@ -249,7 +259,11 @@ ORACLE_DEFINE(float, f32, fmaf)
     }                                                                                          \
     if (v != grid) memcpy(grid, v, sizeof(REAL) * (size_t)n);                                  \
     free(buf);                                                                                 \
+    free(q);                                                                                   \
     return 0;                                                                                  \
+  }                                                                                            \
+  int oracle_star2d_##SUF(int rad, int nx, int ny, const float* wts, REAL* grid, int T) {       \
+    return oracle_star2d_src_##SUF(rad, nx, ny, wts, NULL, NULL, grid, T);                     \
   }
 
 ORACLE_STAR_DEFINE(double, f64, fma)
@@ -267,13 +281,20 @@ ORACLE_STAR_DEFINE(float, f32, fmaf)
  *   wts[0] = cc; for d = 1..rad: wts[2d-1] = w_d, wts[2d] = e_d;
  *   wts[2rad+d] = s_d; wts[3rad+d] = n_d; wts[4rad+d] = b_d; wts[5rad+d] = a_d (d = 1..rad).
  * With rad = 1 this is the chain c, w, e, s, n, b, a of the radius-1 3D forward above.
+ * Hotspot form (oracle_star3d_src_*): as for 2D, the chain starts from fma(cc, c, q).
  */
 #define ORACLE_STAR3_DEFINE(REAL, SUF, FMA)                                                      \
-  int oracle_star3d_##SUF(int rad, int nx, int ny, int nz, const float* wts, REAL* grid, int T) { \
+  int oracle_star3d_src_##SUF(int rad, int nx, int ny, int nz, const float* wts, const float* src, \
+                              const REAL* power, REAL* grid, int T) {                          \
     if (rad < 1 || nx < 1 || ny < 1 || nz < 1 || T < 0) return -1;                             \
     const long n = (long)nx * ny * nz;                                                         \
     REAL* buf = (REAL*)malloc(sizeof(REAL) * (size_t)n);                                       \
-    if (!buf) return -1;                                                                       \
+    REAL* q = power ? (REAL*)malloc(sizeof(REAL) * (size_t)n) : NULL;                          \
+    if (!buf || (power && !q)) { free(buf); free(q); return -1; }                              \
+    if (power) {                                                                               \
+      const REAL kamb = (REAL)src[1] * (REAL)src[2];                                           \
+      for (long i = 0; i < n; ++i) q[i] = FMA((REAL)src[0], power[i], kamb);                   \
+    }                                                                                          \
     REAL* v = grid;                                                                            \
     REAL* o = buf;                                                                             \
     for (int t = 0; t < T; ++t) {                                                              \
@@ -282,7 +303,8 @@ ORACLE_STAR_DEFINE(float, f32, fmaf)
         for (long y = 0; y < ny; ++y) {                                                        \
           const REAL* row = v + (z * ny + y) * nx;                                             \
           for (long x = 0; x < nx; ++x) {                                                      \
-            REAL acc = (REAL)wts[0] * row[x];                                                  \
+            const long ic = (z * ny + y) * nx + x;                                             \
+            REAL acc = q ? FMA((REAL)wts[0], row[x], q[ic]) : (REAL)wts[0] * row[x];           \
             for (int d = 1; d <= rad; ++d) {                                                   \
               acc = FMA((REAL)wts[2 * d - 1], row[clampl(x - d, 0, nx - 1)], acc);             \
               acc = FMA((REAL)wts[2 * d], row[clampl(x + d, 0, nx - 1)], acc);                 \
@@ -295,7 +317,7 @@ ORACLE_STAR_DEFINE(float, f32, fmaf)
               acc = FMA((REAL)wts[4 * rad + d], v[(clampl(z - d, 0, nz - 1) * ny + y) * nx + x], acc); \
             for (int d = 1; d <= rad; ++d)                                                     \
               acc = FMA((REAL)wts[5 * rad + d], v[(clampl(z + d, 0, nz - 1) * ny + y) * nx + x], acc); \
-            o[(z * ny + y) * nx + x] = acc;                                                    \
+            o[ic] = acc;                                                                       \
           }                                                                                    \
         }                                                                                      \
       }                                                                                        \
@@ -303,7 +325,11 @@ ORACLE_STAR_DEFINE(float, f32, fmaf)
     }                                                                                          \
     if (v != grid) memcpy(grid, v, sizeof(REAL) * (size_t)n);                                  \
     free(buf);                                                                                 \
+    free(q);                                                                                   \
     return 0;                                                                                  \
+  }                                                                                            \
+  int oracle_star3d_##SUF(int rad, int nx, int ny, int nz, const float* wts, REAL* grid, int T) { \
+    return oracle_star3d_src_##SUF(rad, nx, ny, nz, wts, NULL, NULL, grid, T);                 \
   }
 
 ORACLE_STAR3_DEFINE(double, f64, fma)

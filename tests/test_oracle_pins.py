@@ -733,3 +733,94 @@ def test_star3d_rejects_bad_arguments():
         oracle.star3d(np.zeros((3, 3)), STAR3[2], 1)
     with pytest.raises(ValueError):
         oracle.star3d(np.zeros((3, 3, 3)), STAR3[2], -1)
+
+
+# ---------------------------------------------------------------- radius-r hotspot form
+
+SRC = (0.125, 0.25, 64.0)  # cp, c_amb, t_amb (dyadic, so the source q is exact in FP32)
+
+
+def test_star_src_radius_one_is_the_hotspot_stencil():
+    """Radius 1 with a source: the radius-1 hotspot forward (its own chain fma(cc, c, q)), bit
+    for bit in FP64 and FP32, in 2D and 3D."""
+    cf = SETS["AH2"]  # cc, cw, ce, cn, cs, cb, ca, cp, c_amb, t_amb
+    w = np.array([cf[0], cf[1], cf[2], cf[4], cf[3]], dtype=np.float32)
+    src = (cf[7], cf[8], cf[9])
+    x0 = uniform((29, 41), 300.0, 350.0, 171)
+    p = uniform((29, 41), 0.0, 1e-3, 172)
+    for dt in (np.float64, np.float32):
+        assert np.array_equal(oracle.star2d(x0, w, 15, dtype=dt, power=p, src=src),
+                              oracle.forward(x0, cf, 15, power=p, dtype=dt))
+    cf3 = SETS["H3"]
+    w3 = np.array([cf3[0], cf3[1], cf3[2], cf3[4], cf3[3], cf3[5], cf3[6]], dtype=np.float32)
+    src3 = (cf3[7], cf3[8], cf3[9])
+    x3 = uniform((9, 13, 17), 300.0, 350.0, 173)
+    p3 = uniform((9, 13, 17), 0.0, 1e-3, 174)
+    for dt in (np.float64, np.float32):
+        assert np.array_equal(oracle.star3d(x3, w3, 11, dtype=dt, power=p3, src=src3),
+                              oracle.forward(x3, cf3, 11, power=p3, dtype=dt))
+
+
+def affine_reference(A, x0, q, T):
+    """x_T = A^T x_0 + sum_{t < T} A^t q, in FP64 from the dense operator."""
+    x = x0.astype(np.float64).ravel()
+    acc = np.zeros_like(x)
+    Ak = np.eye(A.shape[0])
+    for _ in range(T):
+        acc += Ak @ q
+        Ak = A @ Ak
+    return Ak @ x + acc
+
+
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_star_src_is_the_affine_map_of_the_dense_operator(r):
+    """The hotspot form is x_{t+1} = A x_t + q with A the clamped radius-r operator and
+    q = cp*p + c_amb*t_amb: its T-step result is A^T x_0 + sum_{t<T} A^t q."""
+    shape = (6, 5)
+    w = STAR[r]
+    A = dense_star(shape, w)
+    x0 = uniform(shape, 0.0, 1.0, 181 + r)
+    p = uniform(shape, 0.0, 1.0, 185 + r)
+    q = SRC[0] * p.astype(np.float64).ravel() + SRC[1] * SRC[2]
+    for T in (0, 1, 2, 5):
+        ref = affine_reference(A, x0, q, T).reshape(shape)
+        assert relerr(oracle.star2d(x0, w, T, power=p, src=SRC), ref) < 1e-13, (r, T)
+        assert relerr(oracle.star2d(x0, w, T, dtype=np.float32, power=p, src=SRC), ref) < 2e-6, (r, T)
+    shape3 = (3, 4, 5)
+    w3 = STAR3[r]
+    A3 = dense_star3(shape3, w3)
+    x3 = uniform(shape3, 0.0, 1.0, 191 + r)
+    p3 = uniform(shape3, 0.0, 1.0, 195 + r)
+    q3 = SRC[0] * p3.astype(np.float64).ravel() + SRC[1] * SRC[2]
+    for T in (0, 1, 3):
+        ref = affine_reference(A3, x3, q3, T).reshape(shape3)
+        assert relerr(oracle.star3d(x3, w3, T, power=p3, src=SRC), ref) < 1e-13, (r, T)
+        assert relerr(oracle.star3d(x3, w3, T, dtype=np.float32, power=p3, src=SRC), ref) < 2e-6, (r, T)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_star_src_exact_fixed_point(r):
+    """Weights summing to 3/4 and q = 20 everywhere (p = 32: 0.125*32 + 0.25*64): the field 80
+    is a fixed point, (3/4)*80 + 20 = 80, exactly in FP32 at every step (dyadic values)."""
+    a2 = SETS["A2"]
+    base2 = np.array([a2[0], a2[1], a2[2], a2[4], a2[3]], np.float32) if r == 1 else STAR[r]
+    w2 = (base2.astype(np.float64) * 0.75).astype(np.float32)
+    w3 = (STAR3[r].astype(np.float64) * 0.75).astype(np.float32)
+    assert float(w2.astype(np.float64).sum()) == 0.75 and float(w3.astype(np.float64).sum()) == 0.75
+    x2 = np.full((7, 9), 80.0, np.float32)
+    x3 = np.full((4, 5, 6), 80.0, np.float32)
+    for dt in (np.float32, np.float64):
+        assert np.all(oracle.star2d(x2, w2, 25, dtype=dt, power=np.full(x2.shape, 32.0), src=SRC) == 80.0)
+        assert np.all(oracle.star3d(x3, w3, 25, dtype=dt, power=np.full(x3.shape, 32.0), src=SRC) == 80.0)
+    # one step from 0 with uniform power is q everywhere
+    z = oracle.star2d(np.zeros((4, 4)), w2, 1, power=np.full((4, 4), 32.0), src=SRC)
+    assert np.all(z == 20.0)
+
+
+def test_star_src_rejects_bad_arguments():
+    with pytest.raises(ValueError):
+        oracle.star2d(np.zeros((3, 3)), STAR[2], 1, power=np.zeros((3, 3)))  # no src
+    with pytest.raises(ValueError):
+        oracle.star2d(np.zeros((3, 3)), STAR[2], 1, power=np.zeros((3, 4)), src=SRC)
+    with pytest.raises(ValueError):
+        oracle.star3d(np.zeros((3, 3, 3)), STAR3[2], 1, power=np.zeros((3, 3)), src=SRC)
