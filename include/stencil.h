@@ -261,6 +261,18 @@ stencil_status_t stencil_create_star(stencil_plan_t* out, int ndim, int rad, int
                                      const stencil_tuning_t* tuning, void* hip_stream);
 stencil_status_t stencil_run_star(stencil_plan_t plan, float* grid, const float* weights, int T);
 
+/* stencil_run_star_hotspot: the hotspot form of the radius-r star stencil on a star plan (2D or
+ * 3D): Table 2's Hotspot source carried over to radius r, i.e. every step is
+ *     out = q + (the weighted sum of stencil_run_star),  q = cp*p + c_amb*t_amb,
+ * evaluated as the chain fma(cc, c, q), then the neighbour terms in stencil_run_star's order,
+ * with q = fma(cp, p, k_amb) and k_amb = c_amb*t_amb rounded once in FP32 (as stencil_run's
+ * hotspot form).  power: device, the grid's shape, FP32, 4-byte aligned, not aliasing grid;
+ * read only.  src: HOST array {cp, c_amb, t_amb}, finite.  weights, T, grid and the stream as
+ * for stencil_run_star; the plan's tuning (k, seg_len) serves both forms.  INVALID_ARG for a
+ * NULL power or src, non-finite values or a non-star plan. */
+stencil_status_t stencil_run_star_hotspot(stencil_plan_t plan, float* grid, const float* power, const float* weights,
+                                          const float* src, int T);
+
 /* ---------------------------------------------------------------- performance model
  * The paper's external-memory model (Section 4, Eq. 3-9), as used to prune the tuning
  * space (Section 5.3).  Pure host arithmetic; needs no device.  rad = 1 for the evaluated

@@ -29,7 +29,7 @@ EXPORTED = ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoin
             "stencil_batch_destroy", "stencil_get_tuning", "stencil_destroy", "stencil_status_string",
             "stencil_last_error", "stencil_model_estimate", "stencil_plan_model", "stencil_create_star",
             "stencil_run_star", "stencil_batch_sync", "stencil_run_batched_noalloc",
-            "stencil_run_slab", "stencil_get_adjoint_tuning")
+            "stencil_run_slab", "stencil_get_adjoint_tuning", "stencil_run_star_hotspot")
 
 
 class StencilError(RuntimeError):
@@ -112,10 +112,13 @@ def lib():
             L.stencil_plan_model.argtypes = [vp, i, ctypes.POINTER(PlanModel)]
             L.stencil_create_star.argtypes = [ctypes.POINTER(vp), i, i, i, i, i, ctypes.POINTER(Tuning), vp]
             L.stencil_run_star.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float), i]
+            L.stencil_run_star_hotspot.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_float),
+                                                   ctypes.POINTER(ctypes.c_float), i]
             for name in ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoint",
                          "stencil_run_batched", "stencil_get_tuning", "stencil_model_estimate",
                          "stencil_plan_model", "stencil_create_star", "stencil_run_star", "stencil_batch_sync",
-                         "stencil_run_batched_noalloc", "stencil_run_slab", "stencil_get_adjoint_tuning"):
+                         "stencil_run_batched_noalloc", "stencil_run_slab", "stencil_get_adjoint_tuning",
+                         "stencil_run_star_hotspot"):
                 getattr(L, name).restype = i
             _lib = L
     return _lib
@@ -179,6 +182,17 @@ def stencil_run_star(plan, grid, weights, T):
     import numpy as np
     w = np.ascontiguousarray(weights, dtype=np.float32)
     _check(lib().stencil_run_star(plan, _ptr(grid), w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(T)))
+
+
+def stencil_run_star_hotspot(plan, grid, power, weights, src, T):
+    import numpy as np
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    sv = np.ascontiguousarray(src, dtype=np.float32)
+    if sv.size != 3:
+        raise ValueError("src must be (cp, c_amb, t_amb)")
+    fp = ctypes.POINTER(ctypes.c_float)
+    _check(lib().stencil_run_star_hotspot(plan, _ptr(grid), _ptr(power), w.ctypes.data_as(fp), sv.ctypes.data_as(fp),
+                                          int(T)))
 
 
 def stencil_run(plan, grid, power, coeffs, T):
@@ -396,13 +410,22 @@ class StarPlan:
     def n_weights(self):
         return 1 + (6 if self.ndim == 3 else 4) * self.rad
 
-    def run(self, grid, weights, T):
+    def run(self, grid, weights, T, power=None, src=None):
         """weights: cc; w_d, e_d (d = 1..rad); s_1..s_rad; n_1..n_rad; in 3D then b_1..b_rad
-        (z-d) and a_1..a_rad (z+d): 1 + 4*rad values in 2D, 1 + 6*rad in 3D."""
+        (z-d) and a_1..a_rad (z+d): 1 + 4*rad values in 2D, 1 + 6*rad in 3D.  With power (a
+        device tensor of the grid's shape) and src = (cp, c_amb, t_amb): the hotspot form."""
         _check_tensor(grid, "grid", self.shape, self.device)
         if len(weights) != self.n_weights:
             raise ValueError("weights must have 1 + %d*rad entries" % (6 if self.ndim == 3 else 4))
-        stencil_run_star(self.handle, grid, weights, T)
+        if power is None:
+            if src is not None:
+                raise ValueError("src without power")
+            stencil_run_star(self.handle, grid, weights, T)
+        else:
+            _check_tensor(power, "power", self.shape, self.device)
+            if src is None or len(src) != 3:
+                raise ValueError("the hotspot form needs src = (cp, c_amb, t_amb)")
+            stencil_run_star_hotspot(self.handle, grid, power, weights, src, T)
         return grid
 
     @property

@@ -3,8 +3,13 @@
 
 #define SL(R, K)                                                                                                \
   case K:                                                                                                       \
-    if (a.keff == K) hipLaunchKernelGGL((star2d_kernel<R, K, true>), dim3(a.ntx * a.nseg), dim3(64), 0, s, a);  \
-    else hipLaunchKernelGGL((star2d_kernel<R, K, false>), dim3(a.ntx * a.nseg), dim3(64), 0, s, a);             \
+    if (a.power) {                                                                                              \
+      if (a.keff == K) hipLaunchKernelGGL((star2d_kernel<R, K, true, true>), dim3(a.ntx * a.nseg), dim3(64), 0, s, a); \
+      else hipLaunchKernelGGL((star2d_kernel<R, K, false, true>), dim3(a.ntx * a.nseg), dim3(64), 0, s, a);    \
+    } else {                                                                                                    \
+      if (a.keff == K) hipLaunchKernelGGL((star2d_kernel<R, K, true, false>), dim3(a.ntx * a.nseg), dim3(64), 0, s, a); \
+      else hipLaunchKernelGGL((star2d_kernel<R, K, false, false>), dim3(a.ntx * a.nseg), dim3(64), 0, s, a);   \
+    }                                                                                                           \
     break;
 
 hipError_t launch_star2d_r34(int R, int K, const Star2dArgs& a, hipStream_t s) {

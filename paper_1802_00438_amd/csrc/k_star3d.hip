@@ -20,7 +20,8 @@ int star3_instantiated(int R, const int** ks) {
 
 #define S3(R, K)                                                                                        \
   case K:                                                                                               \
-    hipLaunchKernelGGL((star3d_kernel<R, K>), dim3(nb), dim3(kStar3Threads), 0, s, a);                  \
+    if (a.power) hipLaunchKernelGGL((star3d_kernel<R, K, true>), dim3(nb), dim3(kStar3Threads), 0, s, a); \
+    else hipLaunchKernelGGL((star3d_kernel<R, K, false>), dim3(nb), dim3(kStar3Threads), 0, s, a);       \
     break;
 
 hipError_t launch_star3d(int R, int K, const Star3dArgs& a, hipStream_t s) {

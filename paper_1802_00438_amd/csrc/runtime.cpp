@@ -390,6 +390,7 @@ hipError_t run_star_pass(const stencil_plan_s* p, int K, int keff, const float* 
     a.src = src; a.dst = dst;
     a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.keff = keff;
     a.cs = g.csx; a.ntx = g.ntx; a.nty = g.nty; a.segz = g.segz; a.nsegz = g.nsegz;
+    a.power = p->star_power;
     a.cf = p->star3_cf;
     return launch_star3d(p->rad, K, a, p->stream);
   }
@@ -398,7 +399,9 @@ hipError_t run_star_pass(const stencil_plan_s* p, int K, int keff, const float* 
   a.src = src; a.dst = dst;
   a.nx = p->nx; a.ny = p->ny; a.keff = keff;
   a.cs = g.cs; a.kr = g.kr; a.ntx = g.ntx; a.seg = g.seg; a.nseg = g.nseg;
-  a.aligned = ((p->nx & 3) == 0) && aligned16(src) && aligned16(dst) ? 1 : 0;
+  a.aligned = ((p->nx & 3) == 0) && aligned16(src) && aligned16(dst) &&
+                      (!p->star_power || aligned16(p->star_power)) ? 1 : 0;
+  a.power = p->star_power;
   a.cf = p->star_cf;
   return launch_star2d(p->rad, K, a, p->stream);
 }
@@ -1513,7 +1516,10 @@ stencil_status_t stencil_create_star(stencil_plan_t* out, int ndim, int rad, int
   return STENCIL_OK;
 }
 
-stencil_status_t stencil_run_star(stencil_plan_t p, float* grid, const float* weights, int T) {
+// A radius-r star run of either form: power == nullptr is the diffusion form; otherwise the
+// hotspot form with src = {cp, c_amb, t_amb}.
+static stencil_status_t run_star(stencil_plan_t p, float* grid, const float* power, const float* weights, const float* src,
+                          int T) {
   stencil_status_t st = check_plan(p);
   if (st != STENCIL_OK) return st;
   if (!p->star) return fail(STENCIL_ERR_INVALID_ARG, "not a radius-r star plan (stencil_create_star)");
@@ -1524,6 +1530,16 @@ stencil_status_t stencil_run_star(stencil_plan_t p, float* grid, const float* we
   const int nw = 1 + (p->ndim == 3 ? 6 : 4) * R;
   for (int i = 0; i < nw; ++i)
     if (!std::isfinite(weights[i])) return fail(STENCIL_ERR_INVALID_ARG, "weights must be finite");
+  float cp = 0.0f, kamb = 0.0f;
+  if (power) {
+    if (!src) return fail(STENCIL_ERR_INVALID_ARG, "the hotspot form needs src = {cp, c_amb, t_amb}");
+    for (int i = 0; i < 3; ++i)
+      if (!std::isfinite(src[i])) return fail(STENCIL_ERR_INVALID_ARG, "src must be finite");
+    if (reinterpret_cast<uintptr_t>(power) & 3) return fail(STENCIL_ERR_INVALID_ARG, "power must be 4-byte aligned");
+    if (power == grid) return fail(STENCIL_ERR_INVALID_ARG, "power must not alias grid");
+    cp = src[0];
+    kamb = src[1] * src[2];  // rounded once in FP32
+  }
   if (p->ndim == 3) {
     Star3Coef c{};
     c.c0 = weights[0];
@@ -1535,6 +1551,8 @@ stencil_status_t stencil_run_star(stencil_plan_t p, float* grid, const float* we
       c.b[d - 1] = weights[4 * R + d];
       c.a[d - 1] = weights[5 * R + d];
     }
+    c.cp = cp;
+    c.kamb = kamb;
     p->star3_cf = c;
   } else {
     StarCoef c{};
@@ -1545,6 +1563,8 @@ stencil_status_t stencil_run_star(stencil_plan_t p, float* grid, const float* we
       c.s[d - 1] = weights[2 * R + d];
       c.n[d - 1] = weights[3 * R + d];
     }
+    c.cp = cp;
+    c.kamb = kamb;
     p->star_cf = c;
   }
   st = set_device(p);
@@ -1553,8 +1573,21 @@ stencil_status_t stencil_run_star(stencil_plan_t p, float* grid, const float* we
   const int K = star_k_for(p->ndim, R, std::max(1, p->tuning.k));
   const int kpass = std::min(K, std::max(1, p->tuning.k));
   int counter = 0;
-  return run_sequence(p, KM_STAR, false, K, split_steps(T, kpass), grid, grid, p->scratch, nullptr, nullptr, DevCoef{},
-                      &counter);
+  p->star_power = power;
+  st = run_sequence(p, KM_STAR, false, K, split_steps(T, kpass), grid, grid, p->scratch, nullptr, nullptr, DevCoef{},
+                    &counter);
+  p->star_power = nullptr;
+  return st;
+}
+
+stencil_status_t stencil_run_star(stencil_plan_t p, float* grid, const float* weights, int T) {
+  return run_star(p, grid, nullptr, weights, nullptr, T);
+}
+
+stencil_status_t stencil_run_star_hotspot(stencil_plan_t p, float* grid, const float* power, const float* weights,
+                                          const float* src, int T) {
+  if (!power) return fail(STENCIL_ERR_INVALID_ARG, "power is required");
+  return run_star(p, grid, power, weights, src, T);
 }
 
 }  // extern "C"

@@ -71,6 +71,7 @@ struct stencil_plan_s {
   bool star = false;
   StarCoef star_cf{};    // weights of the current stencil_run_star call (2D)
   Star3Coef star3_cf{};  // the same for a 3D plan
+  const float* star_power = nullptr;  // power map of the current hotspot-form star run, or null
   size_t cells;
   hipStream_t stream;
   int device;

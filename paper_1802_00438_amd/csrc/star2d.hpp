@@ -1,4 +1,5 @@
-// star2d.hpp -- temporal-blocked radius-r 2D star stencil (diffusion form), one wave per tile.
+// star2d.hpp -- temporal-blocked radius-r 2D star stencil (diffusion and hotspot forms), one
+// wave per tile.
 //
 // Method (paper Eq. 1 and Eq. 2 with a general radius rad = R; Sections 3.1, 3.2): a cell is
 // updated from itself and the cells at distance 1..R along x and y.  Tiles overlap by a halo
@@ -27,6 +28,9 @@
 //   * Evaluation order, the same FMA chain as the oracle: acc = cc*c; for d = 1..R:
 //     acc = fma(w_d, x-d, acc), acc = fma(e_d, x+d, acc); then fma(s_d, y+d) for d = 1..R,
 //     then fma(n_d, y-d) for d = 1..R.
+//   * Hotspot form (HOT): the chain starts from fma(cc, c, q), q = fma(cp, p, kamb) of the
+//     cell, as the radius-1 hotspot does.  Each level reads the power row of the row it makes
+//     (the rows of the K levels are K*R rows apart, so all but the first read hit L2).
 #pragma once
 #include "device_common.hpp"
 
@@ -35,11 +39,13 @@ constexpr int kStarMaxR = 4;
 struct StarCoef {
   float c0;
   float w[kStarMaxR], e[kStarMaxR], s[kStarMaxR], n[kStarMaxR];
+  float cp, kamb;  // hotspot form: q = fma(cp, p, kamb), kamb = c_amb * t_amb rounded in FP32
 };
 
 struct Star2dArgs {
   const float* src;
   float* dst;
+  const float* power;  // hotspot form: the power map (grid shape); diffusion: unused
   int nx, ny;
   int keff;  // steps fused in this pass, 1..K
   int cs;    // output columns per tile (multiple of 4)
@@ -53,7 +59,7 @@ struct Star2dArgs {
 
 // FULL: the pass fuses all K steps (keff == K), so no level needs the run-time keff test that
 // would split the unrolled step into one basic block per level.
-template <int R, int K, bool FULL>
+template <int R, int K, bool FULL, bool HOT = false>
 struct Star2dTile {
   static_assert(R >= 1 && R <= kStarMaxR, "radius");
   static constexpr int V = 4;
@@ -96,13 +102,32 @@ struct Star2dTile {
     }
   }
 
+  // q = fma(cp, p, kamb) of the lane's cells of row j (clamped, so a halo row outside the grid
+  // reads a valid address; its results are never stored)
+  template <bool XE, bool VEC>
+  __device__ __forceinline__ void source_row(int j, float (&q)[V]) const {
+    const float* rowp = a.power + (size_t)clampi(j, 0, a.ny - 1) * a.nx;
+    const int x0 = ws + lane * V;
+    if constexpr (VEC && !XE) {
+      const float4 t = *reinterpret_cast<const float4*>(rowp + x0);
+      q[0] = t.x; q[1] = t.y; q[2] = t.z; q[3] = t.w;
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) q[v] = rowp[clampi(x0 + v, 0, a.nx - 1)];
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) q[v] = __builtin_fmaf(a.cf.cp, q[v], a.cf.kamb);
+  }
+
   // Row j of level s from the window P of level s-1, whose newest row (slot NW) is row j - R.
   // The row that arrived u steps ago sits in slot (NW - u) mod NR and is row j - R + u.  With
   // LAST = false the final term (n_R times the newest row) is left out.
-  template <bool XE, bool YE, int NW, bool LAST = true>
+  template <bool XE, bool YE, int NW, bool LAST = true, bool VEC = false>
   __device__ __forceinline__ void level_row(const float (&P)[NR][V], int j, float (&o)[V]) const {
     constexpr int CS = (NW - R + 2 * NR) % NR;  // centre slot (u = R)
     const float(&C)[V] = P[CS];
+    float q[V];
+    if constexpr (HOT) source_row<XE, VEC>(j, q);
     // x-neighbours: xm[d][v] is the value at distance d to the left of cell v, xp to the right
     float xm[R + 1][V], xp[R + 1][V];
     float lo[R], up[R];
@@ -152,7 +177,7 @@ struct Star2dTile {
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      float acc = a.cf.c0 * C[v];
+      float acc = HOT ? __builtin_fmaf(a.cf.c0, C[v], q[v]) : a.cf.c0 * C[v];
 #pragma unroll
       for (int d = 1; d <= R; ++d) {
         const int im = v - d, ip = v + d;
@@ -190,7 +215,7 @@ struct Star2dTile {
       for (int s = K; s >= 1; --s) {
         float o[V];
         if (FULL || s <= a.keff) {
-          level_row<XE, false, T, false>(win[s - 1], r + s * R, o);
+          level_row<XE, false, T, false, VEC>(win[s - 1], r + s * R, o);
         } else {
 #pragma unroll
           for (int v = 0; v < V; ++v) o[v] = 0.0f;  // surplus level: set in phase 2
@@ -228,7 +253,7 @@ struct Star2dTile {
       const int j = r + s * R;
       float o[V];
       if (FULL || s <= a.keff) {
-        level_row<XE, YE, T>(win[s - 1], j, o);
+        level_row<XE, YE, T, true, VEC>(win[s - 1], j, o);
       } else {
         // levels past keff forward their input row (the centre of the window below)
         constexpr int CS = (T - R + 2 * NR) % NR;
@@ -293,13 +318,15 @@ struct Star2dTile {
 };
 
 // Radius 2 with five fused steps sits a few registers above the three-waves-per-SIMD limit
-// (168); it is held to that limit.  Everything else takes what the compiler allocates.
-constexpr int star_min_waves(int R, int K) { return (R == 2 && K == 5) ? 3 : 1; }
+// (168); the diffusion form is held to that limit (a 12-byte spill).  The hotspot form needs
+// more (the power row in flight), and held to 168 it would spill 356 bytes, so it is not.
+// Everything else takes what the compiler allocates.
+constexpr int star_min_waves(int R, int K, bool HOT) { return (!HOT && R == 2 && K == 5) ? 3 : 1; }
 
-template <int R, int K, bool FULL>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(star_min_waves(R, K))))
+template <int R, int K, bool FULL, bool HOT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(star_min_waves(R, K, HOT))))
 void star2d_kernel(Star2dArgs a) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  Star2dTile<R, K, FULL> t(a, threadIdx.x);
+  Star2dTile<R, K, FULL, HOT> t(a, threadIdx.x);
   t.process(tile);
 }

@@ -32,6 +32,10 @@
 //     and takes its last held plane (plane nz-1) in place of planes past the top.
 //   * Every step count from 1 to the largest k is instantiated, so a pass always runs on the
 //     kernel whose K equals the steps it fuses.
+//   * Hotspot form (HOT): a new sum starts from fma(cc, c, q) with q = fma(cp, p, kamb) of its
+//     own plane and cell, as the radius-1 hotspot does; each level reads the power plane of the
+//     plane it opens (the same plane for every level, one iteration apart, so an L2 hit after
+//     the first).
 #pragma once
 #include "device_common.hpp"
 #include "star2d.hpp"
@@ -39,11 +43,13 @@
 struct Star3Coef {
   float c0;
   float w[kStarMaxR], e[kStarMaxR], s[kStarMaxR], n[kStarMaxR], b[kStarMaxR], a[kStarMaxR];
+  float cp, kamb;  // hotspot form: q = fma(cp, p, kamb), kamb = c_amb * t_amb rounded in FP32
 };
 
 struct Star3dArgs {
   const float* src;
   float* dst;
+  const float* power;  // hotspot form: the power map (grid shape); diffusion: unused
   int nx, ny, nz;
   int keff;         // steps fused in this pass (equal to K)
   int cs;           // output cells per tile in x and y (64 - 2*R*K)
@@ -62,7 +68,7 @@ constexpr int star3_lcm(int a, int b) { return a / star3_gcd(a, b) * b; }
 // LDS floats of a (R, K) kernel: three buffers x K levels x one padded plane
 constexpr int star3_lds_floats(int R, int K) { return 3 * K * star3_lw(R) * star3_lw(R); }
 
-template <int R, int K>
+template <int R, int K, bool HOT>
 struct Star3dTile {
   static_assert(R >= 1 && R <= kStarMaxR, "radius");
   static constexpr int RY = kStar3RY;
@@ -98,13 +104,21 @@ struct Star3dTile {
   // New partial sum of plane q at level s from Q (level s-1's plane q, own cells), the
   // neighbours of that plane in LDS plane rp, and the held planes.
   template <int u, bool EDGE>
-  __device__ __forceinline__ void open_sum(int s, const float (&Q)[RY], const float* rp, float (&nw)[RY]) const {
+  __device__ __forceinline__ void open_sum(int s, int qz, const float (&Q)[RY], const float* rp,
+                                           float (&nw)[RY]) const {
+    float src[RY];
+    if constexpr (HOT) {
+      const char* pp = reinterpret_cast<const char*>(a.power + (size_t)qz * a.nx * a.ny);
+#pragma unroll
+      for (int j = 0; j < RY; ++j)
+        src[j] = __builtin_fmaf(a.cf.cp, *reinterpret_cast<const float*>(pp + goff[j]), a.cf.kamb);
+    }
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
       const float* cp = rp + lidx + j * LW;
       const float c = Q[j];
       const int gy = gy0 + j;
-      float acc = a.cf.c0 * c;
+      float acc = HOT ? __builtin_fmaf(a.cf.c0, c, src[j]) : a.cf.c0 * c;
       float vm = c, vp = c;
 #pragma unroll
       for (int d = 1; d <= R; ++d) {
@@ -200,7 +214,7 @@ struct Star3dTile {
             for (int j = 0; j < RY; ++j) hist[s - 1][d][j] = Q[j];
         }
         float nw[RY];
-        open_sum<u, EDGE>(s, Q, rd + (s - 1) * PL, nw);
+        open_sum<u, EDGE>(s, q, Q, rd + (s - 1) * PL, nw);
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
           pend[s - 1][SP][j] = nw[j];
@@ -279,10 +293,10 @@ struct Star3dTile {
   }
 };
 
-template <int R, int K>
+template <int R, int K, bool HOT>
 __global__ __launch_bounds__(kStar3Threads) void star3d_kernel(Star3dArgs a) {
   __shared__ float lds[star3_lds_floats(R, K)];
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  Star3dTile<R, K> t(a, lds);
+  Star3dTile<R, K, HOT> t(a, lds);
   t.process(tile);
 }

@@ -198,3 +198,11 @@ def test_noalloc_batch_rejects_bad_arguments_before_device_work():
     bad = (S.BatchItem * 1)(S.BatchItem(S.HOTSPOT, 2, 8, 8, 1, 4096, None, S.make_coeffs([0.5]), 3))
     assert L.stencil_run_batched_noalloc(1, bad, (ctypes.c_void_p * 1)(65536), None) == -2  # hotspot
     assert L.stencil_run_batched_noalloc(-1, None, None, None) == -1
+
+
+def test_star_hotspot_rejects_bad_arguments_before_device_work():
+    L = S.lib()
+    w = (ctypes.c_float * 9)(*([0.2] * 9))
+    src = (ctypes.c_float * 3)(0.125, 0.25, 64.0)
+    assert L.stencil_run_star_hotspot(None, None, None, w, src, 1) == -1  # no plan
+    assert L.stencil_run_star_hotspot(None, None, None, None, None, 1) == -1

@@ -170,3 +170,70 @@ def test_star_run_captured_in_a_graph():
     finally:
         plan.close()
         ref_plan.close()
+
+
+SRC = (0.125, 2.0 ** -8, 80.0)  # cp, c_amb, t_amb
+
+
+def check_hot(x0, p, r, T, tuning=None, weights=None):
+    w = weights if weights is not None else weights_for(r)
+    x = dev(x0)
+    plan = S.StarPlan(r, x0.shape, tuning)
+    try:
+        plan.run(x, w, T, power=dev(p), src=SRC)
+        torch.cuda.synchronize()
+        used = plan.tuning
+    finally:
+        plan.close()
+    got = x.cpu().numpy()
+    ref = oracle.star2d(x0, w, T, dtype=np.float32, power=p, src=SRC)
+    assert np.array_equal(got, ref), (x0.shape, r, T, tuning, used, maxrel(got, ref))
+
+
+def weights_for(r):
+    """Radius-r weights scaled to sum 7/8, so the source keeps the field bounded."""
+    return (weights(r).astype(np.float64) * 0.875).astype(np.float32)
+
+
+@pytest.mark.parametrize("shape", [(131, 257), (1, 33), (29, 1), (5, 7), (97, 1001)])
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_star_hotspot_form_all_k(shape, r):
+    """The hotspot form (stencil_run_star_hotspot) bit for bit against the FP32 oracle."""
+    x0 = uniform(shape, 300.0, 350.0, 7800 + 10 * r)
+    p = uniform(shape, 0.0, 1.0, 7801 + 10 * r)
+    for k in KS[r]:
+        for T in sorted({1, k, 2 * k + 3}):
+            check_hot(x0, p, r, T, {"variant": 2, "k": k, "seg_len": 37})
+
+
+def test_star_hotspot_form_tuned_plan_and_rejections():
+    x0 = uniform((300, 412), 300.0, 350.0, 7850)
+    p = uniform((300, 412), 0.0, 1.0, 7851)
+    check_hot(x0, p, 2, 13)  # timed tuner
+    # a power map 4 bytes off 16-byte alignment takes the scalar path, same bits
+    buf = torch.empty(p.size + 1, device="cuda")
+    pv = buf[1:].view(p.shape)
+    pv.copy_(dev(p))
+    xa = dev(x0)
+    pa = S.StarPlan(2, x0.shape, {"variant": 2, "k": 4, "seg_len": 64})
+    try:
+        pa.run(xa, weights_for(2), 9, power=pv, src=SRC)
+        torch.cuda.synchronize()
+    finally:
+        pa.close()
+    assert np.array_equal(xa.cpu().numpy(), oracle.star2d(x0, weights_for(2), 9, dtype=np.float32, power=p, src=SRC))
+    g = dev(x0)
+    plan = S.StarPlan(2, x0.shape, {"variant": 2, "k": 2, "seg_len": 32})
+    try:
+        with pytest.raises(ValueError):
+            plan.run(g, weights_for(2), 1, power=dev(p))  # no src
+        with pytest.raises(ValueError):
+            plan.run(g, weights_for(2), 1, power=dev(p[:10]), src=SRC)  # wrong shape
+        with pytest.raises(S.StencilError) as e:
+            plan.run(g, weights_for(2), 1, power=dev(p), src=(0.1, float("nan"), 80.0))
+        assert e.value.status == -1
+        with pytest.raises(S.StencilError) as e:
+            S.stencil_run_star_hotspot(plan.handle, g, g, weights_for(2), SRC, 1)  # power aliases grid
+        assert e.value.status == -1
+    finally:
+        plan.close()

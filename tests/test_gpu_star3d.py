@@ -176,3 +176,68 @@ def test_star3d_r2_512_full_size_samples():
         assert got[idx] == rv, (idx, got[idx], rv)
     # convex weights: the field stays within the bounds of the initial data
     assert got.min() >= x0.min() and got.max() <= x0.max()
+
+
+SRC = (0.125, 2.0 ** -8, 80.0)  # cp, c_amb, t_amb
+
+
+def w3_hot(r):
+    """Radius-r 3D weights scaled to sum 7/8, so the source keeps the field bounded."""
+    return (STAR3_SETS[r].astype(np.float64) * 0.875).astype(np.float32)
+
+
+def check_hot3(x0, p, r, T, tuning=None):
+    w = w3_hot(r)
+    x = dev(x0)
+    plan = S.StarPlan(r, x0.shape, tuning)
+    try:
+        plan.run(x, w, T, power=dev(p), src=SRC)
+        torch.cuda.synchronize()
+        used = plan.tuning
+    finally:
+        plan.close()
+    got = x.cpu().numpy()
+    ref = oracle.star3d(x0, w, T, dtype=np.float32, power=p, src=SRC)
+    if not np.array_equal(got, ref):
+        d = np.abs(got.astype(np.float64) - ref)
+        raise AssertionError((x0.shape, r, T, tuning, used, float(d.max()), np.argwhere(d > 0)[:4].tolist()))
+
+
+@pytest.mark.parametrize("shape", [(9, 70, 130), (20, 1, 33), (1, 40, 37), (2, 3, 1), (12, 129, 61)])
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_star3d_hotspot_form_all_k(shape, r):
+    """The 3D hotspot form bit for bit against the FP32 oracle, every radius and k."""
+    x0 = uniform(shape, 300.0, 350.0, 7900 + 10 * r)
+    p = uniform(shape, 0.0, 1.0, 7901 + 10 * r)
+    for k in KS3[r]:
+        for T in sorted({1, k, 2 * k + 1}):
+            check_hot3(x0, p, r, T, {"variant": 2, "k": k, "seg_len": 5})
+
+
+def test_star3d_hotspot_form_tuned_plan_and_a_graph():
+    x0 = uniform((40, 100, 90), 300.0, 350.0, 7950)
+    p = uniform((40, 100, 90), 0.0, 1.0, 7951)
+    check_hot3(x0, p, 2, 7)  # timed tuner
+    # a captured hotspot-form run replays like the eager one
+    s = torch.cuda.Stream()
+    w = w3_hot(2)
+    with torch.cuda.stream(s):
+        plan = S.StarPlan(2, x0.shape, {"variant": 2, "k": 2, "seg_len": 8})
+    try:
+        x, y, pd = dev(x0), dev(x0), dev(p)
+        with torch.cuda.stream(s):
+            plan.run(x, w, 5, power=pd, src=SRC)
+            plan.run(y, w, 5, power=pd, src=SRC)
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            plan.run(x, w, 5, power=pd, src=SRC)
+        for _ in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                plan.run(y, w, 5, power=pd, src=SRC)
+            s.synchronize()
+            assert torch.equal(x, y)
+    finally:
+        plan.close()
