@@ -95,6 +95,9 @@ def _load():
                 ss3 = getattr(lib, "oracle_star3d_src_" + suf)
                 ss3.restype = ctypes.c_int
                 ss3.argtypes = [ctypes.c_int] * 4 + [fp, fp, p, p, ctypes.c_int]
+                sa = getattr(lib, "oracle_star_adjoint_" + suf)
+                sa.restype = ctypes.c_int
+                sa.argtypes = [ctypes.c_int] * 5 + [fp, ctypes.c_float, p, ctypes.c_int, p]
             lib.oracle_num_threads.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -243,6 +246,32 @@ def star3d(x0, weights, T, dtype=np.float64, power=None, src=None):
     if rc != 0:
         raise ValueError("oracle_star3d rejected its arguments")
     return g
+
+
+def star_adjoint(cotangent, weights, T, cp=None, dtype=np.float64):
+    """Adjoint of T steps of the radius-r star stencil (2D or 3D by the cotangent's shape;
+    weights as for star2d / star3d).  Returns (grad_x0, grad_p), grad_p = cp * sum_{t=1..T}
+    lambda_t when cp is given (the hotspot form), else None."""
+    lib = _load()
+    dtype = np.dtype(dtype)
+    ct = ctypes.c_double if dtype == np.float64 else ctypes.c_float
+    lam = _prep(cotangent, dtype)
+    ndim = lam.ndim
+    if ndim not in (2, 3):
+        raise ValueError("cotangent must be (ny, nx) or (nz, ny, nx)")
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    per = 4 if ndim == 2 else 6
+    if w.size < 1 + per or (w.size - 1) % per:
+        raise ValueError("weights must have 1 + %dr entries" % per)
+    rad = (w.size - 1) // per
+    nz, ny, nx = (1,) + lam.shape if ndim == 2 else lam.shape
+    gp = np.zeros(lam.shape, dtype) if cp is not None else None
+    fn = lib.oracle_star_adjoint_f64 if dtype == np.float64 else lib.oracle_star_adjoint_f32
+    rc = fn(ndim, rad, nx, ny, nz, _ptr(w, ctypes.c_float), float(cp or 0.0), _ptr(lam, ct), int(T),
+            _ptr(gp, ct) if gp is not None else None)
+    if rc != 0:
+        raise ValueError("oracle_star_adjoint rejected its arguments")
+    return lam, gp
 
 
 def loss(xT, target) -> float:

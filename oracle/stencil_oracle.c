@@ -334,3 +334,53 @@ ORACLE_STAR_DEFINE(float, f32, fmaf)
 
 ORACLE_STAR3_DEFINE(double, f64, fma)
 ORACLE_STAR3_DEFINE(float, f32, fmaf)
+
+/*
+ * Adjoint of T steps of the radius-r star stencil (2D: nz = 1; both forms share it, the source
+ * being independent of the state): lam holds lambda_T = dJ/dx_T on entry and dJ/dx_0 on exit.
+ * Each step scatters every term of the forward update: the cell's own weight cc, and each
+ * directional weight to the neighbour index the forward step read, clamped as in Section 5.1
+ * (so the weights of out-of-grid neighbours land on the boundary cell):
+ *   lambda_{t-1}[clamp(i + offset)] += weight * lambda_t[i]   for every term of cell i.
+ * With grad_p non-NULL (the hotspot form): grad_p = cp * sum_{t=1..T} lambda_t.
+ * Weights in the layout of oracle_star2d (2D) or oracle_star3d (3D).
+ */
+#define ORACLE_STAR_ADJ_DEFINE(REAL, SUF)                                                        \
+  int oracle_star_adjoint_##SUF(int ndim, int rad, int nx, int ny, int nz, const float* wts,     \
+                                float cp, REAL* lam, int T, REAL* grad_p) {                    \
+    if ((ndim != 2 && ndim != 3) || rad < 1 || nx < 1 || ny < 1 || nz < 1 || T < 0) return -1;  \
+    if (ndim == 2) nz = 1;                                                                     \
+    const long n = (long)nx * ny * nz;                                                         \
+    REAL* nxt = (REAL*)malloc(sizeof(REAL) * (size_t)n);                                       \
+    if (!nxt) return -1;                                                                       \
+    if (grad_p)                                                                                \
+      for (long i = 0; i < n; ++i) grad_p[i] = 0;                                              \
+    for (int t = T; t >= 1; --t) {                                                             \
+      if (grad_p)                                                                              \
+        for (long i = 0; i < n; ++i) grad_p[i] = grad_p[i] + (REAL)cp * lam[i];                \
+      for (long i = 0; i < n; ++i) nxt[i] = 0;                                                 \
+      for (long z = 0; z < nz; ++z)                                                            \
+        for (long y = 0; y < ny; ++y)                                                          \
+          for (long x = 0; x < nx; ++x) {                                                      \
+            const long i = (z * ny + y) * nx + x;                                              \
+            const REAL l = lam[i];                                                             \
+            nxt[i] += (REAL)wts[0] * l;                                                        \
+            for (int d = 1; d <= rad; ++d) {                                                   \
+              nxt[(z * ny + y) * nx + clampl(x - d, 0, nx - 1)] += (REAL)wts[2 * d - 1] * l;   \
+              nxt[(z * ny + y) * nx + clampl(x + d, 0, nx - 1)] += (REAL)wts[2 * d] * l;       \
+              nxt[(z * ny + clampl(y + d, 0, ny - 1)) * nx + x] += (REAL)wts[2 * rad + d] * l; \
+              nxt[(z * ny + clampl(y - d, 0, ny - 1)) * nx + x] += (REAL)wts[3 * rad + d] * l; \
+              if (ndim == 3) {                                                                 \
+                nxt[(clampl(z - d, 0, nz - 1) * ny + y) * nx + x] += (REAL)wts[4 * rad + d] * l; \
+                nxt[(clampl(z + d, 0, nz - 1) * ny + y) * nx + x] += (REAL)wts[5 * rad + d] * l; \
+              }                                                                                \
+            }                                                                                  \
+          }                                                                                    \
+      memcpy(lam, nxt, sizeof(REAL) * (size_t)n);                                              \
+    }                                                                                          \
+    free(nxt);                                                                                 \
+    return 0;                                                                                  \
+  }
+
+ORACLE_STAR_ADJ_DEFINE(double, f64)
+ORACLE_STAR_ADJ_DEFINE(float, f32)

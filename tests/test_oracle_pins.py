@@ -824,3 +824,82 @@ def test_star_src_rejects_bad_arguments():
         oracle.star2d(np.zeros((3, 3)), STAR[2], 1, power=np.zeros((3, 4)), src=SRC)
     with pytest.raises(ValueError):
         oracle.star3d(np.zeros((3, 3, 3)), STAR3[2], 1, power=np.zeros((3, 3)), src=SRC)
+
+
+# ---------------------------------------------------------------- radius-r adjoint
+
+def star_weights_2d(r):
+    a2 = SETS["A2"]
+    return np.array([a2[0], a2[1], a2[2], a2[4], a2[3]], np.float32) if r == 1 else STAR[r]
+
+
+@pytest.mark.parametrize("shape", [(6, 5), (1, 7), (5, 1), (2, 3), (1, 1), (4, 9)])
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_star_adjoint_is_the_dense_transpose(shape, r):
+    """grad_x0 = (A^T)^T lambda_T and grad_p = cp * sum_{t=1..T} (A^T)^(T-t) lambda_T, with A the
+    clamped radius-r operator built from its definition."""
+    w = star_weights_2d(r)
+    At = dense_star(shape, w).T
+    lam = uniform(shape, -1.0, 1.0, 201 + r)
+    cp = 0.375
+    for T in (0, 1, 2, 5):
+        g, gp = oracle.star_adjoint(lam, w, T, cp=cp)
+        ref = np.linalg.matrix_power(At, T) @ lam.astype(np.float64).ravel()
+        refp = cp * sum(np.linalg.matrix_power(At, T - t) @ lam.astype(np.float64).ravel() for t in range(1, T + 1)) \
+            if T else np.zeros(lam.size)
+        assert relerr(g, ref.reshape(shape)) < 1e-13, (shape, r, T)
+        assert np.abs(gp.ravel() - refp).max() <= 1e-13 * max(1.0, np.abs(refp).max()), (shape, r, T)
+        g32, _ = oracle.star_adjoint(lam, w, T, dtype=np.float32)
+        assert relerr(g32, ref.reshape(shape)) < 2e-6
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 5), (1, 5, 3), (4, 1, 2), (2, 3, 1)])
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_star3d_adjoint_is_the_dense_transpose(shape, r):
+    w = STAR3[r]
+    At = dense_star3(shape, w).T
+    lam = uniform(shape, -1.0, 1.0, 211 + r)
+    for T in (1, 3):
+        g, gp = oracle.star_adjoint(lam, w, T, cp=0.25)
+        ref = np.linalg.matrix_power(At, T) @ lam.astype(np.float64).ravel()
+        refp = 0.25 * sum(np.linalg.matrix_power(At, T - t) @ lam.astype(np.float64).ravel() for t in range(1, T + 1))
+        assert relerr(g, ref.reshape(shape)) < 1e-13, (shape, r, T)
+        assert np.abs(gp.ravel() - refp).max() <= 1e-13 * max(1.0, np.abs(refp).max())
+
+
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_star_adjoint_dot_product_identity(r):
+    """<F^T(x), y> = <x, adjoint^T(y)> for the linear (diffusion) form, in 2D and 3D."""
+    for shape, w, fwd in (((23, 31), STAR[r], oracle.star2d), ((7, 9, 11), STAR3[r], oracle.star3d)):
+        x = uniform(shape, -1.0, 1.0, 221 + r)
+        y = uniform(shape, -1.0, 1.0, 225 + r)
+        for T in (1, 4, 9):
+            lhs = float(np.dot(fwd(x, w, T).ravel(), y.astype(np.float64).ravel()))
+            g, _ = oracle.star_adjoint(y, w, T)
+            rhs = float(np.dot(x.astype(np.float64).ravel(), g.ravel()))
+            assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs)), (shape, r, T, lhs, rhs)
+
+
+def test_star_adjoint_radius_one_is_the_radius_one_adjoint():
+    """Radius 1 equals the radius-1 oracle adjoint (gradient and grad_p), 2D and 3D."""
+    cf = SETS["AH2"]
+    w = np.array([cf[0], cf[1], cf[2], cf[4], cf[3]], np.float32)
+    lam = uniform((13, 17), -1.0, 1.0, 231)
+    g, gp = oracle.star_adjoint(lam, w, 7, cp=float(cf[7]))
+    g1, gp1 = oracle.adjoint(lam, cf, 7, form=HOTSPOT)
+    assert relerr(g, g1) < 1e-14 and relerr(gp, gp1) < 1e-14
+    cf3 = SETS["A3"]
+    w3 = np.array([cf3[0], cf3[1], cf3[2], cf3[4], cf3[3], cf3[5], cf3[6]], np.float32)
+    lam3 = uniform((5, 6, 7), -1.0, 1.0, 232)
+    g3, _ = oracle.star_adjoint(lam3, w3, 5)
+    g31, _ = oracle.adjoint(lam3, cf3, 5)
+    assert relerr(g3, g31) < 1e-14
+
+
+def test_star_adjoint_rejects_bad_arguments():
+    with pytest.raises(ValueError):
+        oracle.star_adjoint(np.zeros(5), STAR[2], 1)
+    with pytest.raises(ValueError):
+        oracle.star_adjoint(np.zeros((3, 3)), np.zeros(8, np.float32), 1)  # not 1 + 4r weights
+    with pytest.raises(ValueError):
+        oracle.star_adjoint(np.zeros((3, 3)), STAR[2], -1)
