@@ -199,6 +199,7 @@ KERNEL_SOURCES = {
     "tb2d_phys": ["tb2d.hpp", "device_common.hpp", "k_tb2d_phys.hip"],
     "star2d": ["star2d.hpp", "device_common.hpp", "k_star2d.hip", "k_star2d_r12.hip"],
     "star3d": ["star3d.hpp", "star2d.hpp", "device_common.hpp", "k_star3d.hip"],
+    "star_adj": ["star_adjoint.hpp", "star2d.hpp", "device_common.hpp", "k_star_adj.hip"],
     "tb3d_diff": ["tb3d.hpp", "device_common.hpp", "k_tb3d_diff.hip"],
     "tb3d_hot": ["tb3d.hpp", "device_common.hpp", "k_tb3d_hot.hip"],
     "tb3d_adj": ["tb3d.hpp", "device_common.hpp", "k_tb3d_adj.hip"],
@@ -554,12 +555,21 @@ def star3d(S, dev, stream, copy_gbs):
     pp.run(x, wt, 2)
     msp = time_call(lambda: pp.run(x, wt, 20), stream, 1)
     gp = cells * 20 / (msp * 1e-3) / 1e9
+    # the adjoint sweep: one transposed step per launch, reading lambda (neighbours from L1/L2)
+    # and writing it once: 8 B per cell and step; 12R + 1 FLOP per cell (interior cells)
+    gx = torch.empty_like(x)
+    pl.adjoint(x, wt, 2, gx)
+    msa = time_call(lambda: pl.adjoint(x, wt, 20, gx), stream, 2) / 20
+    roof_a = roofline("star_adjoint_kernel<3, %d>" % R, "star_adj", {"rad": R, "shape": list(shape)}, msa, 8.0 * cells,
+                      (12 * R + 1) * float(cells), copy_gbs)
     study = model_row(S, pl, T, ms, 3, 1, (w["nx"], w["ny"], w["nz"]), (64, 64), rad=R)
     pl.close()
     pp.close()
     return {"gcells": round(g, 1), "ms_per_run": round(ms, 2), "k": K, "seg_len": seg,
             "gcells_one_step": round(gp, 1), "speedup_vs_one_step": round(g / gp, 2),
-            "pct_single_pass_roofline": round(100 * g / (HBM_PEAK_GBS / 8), 1), "roofline": roof}, study
+            "gcells_adjoint": round(cells / (msa * 1e-3) / 1e9, 1),
+            "pct_single_pass_roofline": round(100 * g / (HBM_PEAK_GBS / 8), 1), "roofline": roof,
+            "roofline_adjoint": roof_a}, study
 
 
 def diffusion3d(S, dev, stream, copy_gbs):

@@ -273,6 +273,20 @@ stencil_status_t stencil_run_star(stencil_plan_t plan, float* grid, const float*
 stencil_status_t stencil_run_star_hotspot(stencil_plan_t plan, float* grid, const float* power, const float* weights,
                                           const float* src, int T);
 
+/* stencil_adjoint_star: adjoint (vector-Jacobian product) of T steps of a star plan's stencil,
+ * 2D or 3D, either form (the source term does not depend on the state).  cotangent = dJ/dx_T
+ * (device, read only); writes grad_x0 = dJ/dx_0 (device) and, if grad_power is not NULL (the
+ * hotspot form; src = {cp, c_amb, t_amb} is then required), grad_power = dJ/dp =
+ * cp * sum_{t=1..T} lambda_t (device, overwritten).  Each step applies the transposed stencil
+ * lambda_{t-1} = A^T lambda_t, where A is the forward step with the clamp of Section 5.1 at every
+ * distance: cell j gathers the mirrored weights of the cells whose clamped neighbour it is,
+ * zero beyond the grid, and a boundary cell the sum over every cell within the distance whose
+ * neighbour clamps onto it.  One launch per step (not temporal-blocked).  weights as for
+ * stencil_run_star.  Buffers 4-byte aligned; grad_x0 and grad_power must not alias cotangent or
+ * each other.  Asynchronous on the plan's stream; uses the plan's scratch. */
+stencil_status_t stencil_adjoint_star(stencil_plan_t plan, const float* cotangent, const float* weights,
+                                      const float* src, int T, float* grad_x0, float* grad_power);
+
 /* ---------------------------------------------------------------- performance model
  * The paper's external-memory model (Section 4, Eq. 3-9), as used to prune the tuning
  * space (Section 5.3).  Pure host arithmetic; needs no device.  rad = 1 for the evaluated

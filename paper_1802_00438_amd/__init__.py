@@ -29,7 +29,7 @@ EXPORTED = ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoin
             "stencil_batch_destroy", "stencil_get_tuning", "stencil_destroy", "stencil_status_string",
             "stencil_last_error", "stencil_model_estimate", "stencil_plan_model", "stencil_create_star",
             "stencil_run_star", "stencil_batch_sync", "stencil_run_batched_noalloc",
-            "stencil_run_slab", "stencil_get_adjoint_tuning", "stencil_run_star_hotspot")
+            "stencil_run_slab", "stencil_get_adjoint_tuning", "stencil_run_star_hotspot", "stencil_adjoint_star")
 
 
 class StencilError(RuntimeError):
@@ -114,11 +114,13 @@ def lib():
             L.stencil_run_star.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float), i]
             L.stencil_run_star_hotspot.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_float),
                                                    ctypes.POINTER(ctypes.c_float), i]
+            L.stencil_adjoint_star.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                               i, vp, vp]
             for name in ("stencil_create", "stencil_run", "stencil_run_ckpt", "stencil_adjoint",
                          "stencil_run_batched", "stencil_get_tuning", "stencil_model_estimate",
                          "stencil_plan_model", "stencil_create_star", "stencil_run_star", "stencil_batch_sync",
                          "stencil_run_batched_noalloc", "stencil_run_slab", "stencil_get_adjoint_tuning",
-                         "stencil_run_star_hotspot"):
+                         "stencil_run_star_hotspot", "stencil_adjoint_star"):
                 getattr(L, name).restype = i
             _lib = L
     return _lib
@@ -182,6 +184,18 @@ def stencil_run_star(plan, grid, weights, T):
     import numpy as np
     w = np.ascontiguousarray(weights, dtype=np.float32)
     _check(lib().stencil_run_star(plan, _ptr(grid), w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(T)))
+
+
+def stencil_adjoint_star(plan, cotangent, weights, src, T, grad_x0, grad_power):
+    import numpy as np
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    fp = ctypes.POINTER(ctypes.c_float)
+    sv = None if src is None else np.ascontiguousarray(src, dtype=np.float32)
+    if sv is not None and sv.size != 3:
+        raise ValueError("src must be (cp, c_amb, t_amb)")
+    _check(lib().stencil_adjoint_star(plan, _ptr(cotangent), w.ctypes.data_as(fp),
+                                      sv.ctypes.data_as(fp) if sv is not None else None, int(T), _ptr(grad_x0),
+                                      _ptr(grad_power) if grad_power is not None else None))
 
 
 def stencil_run_star_hotspot(plan, grid, power, weights, src, T):
@@ -409,6 +423,20 @@ class StarPlan:
     @property
     def n_weights(self):
         return 1 + (6 if self.ndim == 3 else 4) * self.rad
+
+    def adjoint(self, cotangent, weights, T, grad_x0, grad_power=None, src=None):
+        """dJ/dx_0 of T steps into grad_x0 from cotangent = dJ/dx_T; with grad_power and src =
+        (cp, c_amb, t_amb) (the hotspot form) also dJ/dp = cp * sum_t lambda_t into grad_power."""
+        _check_tensor(cotangent, "cotangent", self.shape, self.device)
+        _check_tensor(grad_x0, "grad_x0", self.shape, self.device)
+        if grad_power is not None:
+            _check_tensor(grad_power, "grad_power", self.shape, self.device)
+            if src is None or len(src) != 3:
+                raise ValueError("grad_power needs src = (cp, c_amb, t_amb)")
+        if len(weights) != self.n_weights:
+            raise ValueError("weights must have 1 + %d*rad entries" % (6 if self.ndim == 3 else 4))
+        stencil_adjoint_star(self.handle, cotangent, weights, src, T, grad_x0, grad_power)
+        return grad_x0, grad_power
 
     def run(self, grid, weights, T, power=None, src=None):
         """weights: cc; w_d, e_d (d = 1..rad); s_1..s_rad; n_1..n_rad; in 3D then b_1..b_rad

@@ -6,6 +6,7 @@
 #include "plain.hpp"
 #include "star2d.hpp"
 #include "star3d.hpp"
+#include "star_adjoint.hpp"
 
 // Kernel mode: forward diffusion, forward hotspot, transposed step (adjoint) without / with
 // grad_p accumulation, or the forward step of Table 2's physical Hotspot 2D formula (2D only).
@@ -41,6 +42,8 @@ hipError_t launch_star2d(int R, int K, const Star2dArgs& a, hipStream_t s);
 // Radius-r 3D star kernels (star3d.hpp): the same for 3D.
 int star3_instantiated(int R, const int** ks);
 hipError_t launch_star3d(int R, int K, const Star3dArgs& a, hipStream_t s);
+// One transposed step of a radius-r star stencil (star_adjoint.hpp).
+hipError_t launch_star_adjoint(const StarAdjArgs& a, hipStream_t s);
 hipError_t launch_fill_int(int* p, size_t n, int v, hipStream_t s);
 
 // Per-mode launchers (one translation unit each).

@@ -1590,4 +1590,61 @@ stencil_status_t stencil_run_star_hotspot(stencil_plan_t p, float* grid, const f
   return run_star(p, grid, power, weights, src, T);
 }
 
+stencil_status_t stencil_adjoint_star(stencil_plan_t p, const float* cotangent, const float* weights,
+                                      const float* src, int T, float* grad_x0, float* grad_power) {
+  stencil_status_t st = check_plan(p);
+  if (st != STENCIL_OK) return st;
+  if (!p->star) return fail(STENCIL_ERR_INVALID_ARG, "not a radius-r star plan (stencil_create_star)");
+  if (!cotangent || !grad_x0 || !weights) return fail(STENCIL_ERR_INVALID_ARG, "cotangent, grad_x0 and weights are required");
+  if (T < 0) return fail(STENCIL_ERR_INVALID_ARG, "T must be >= 0");
+  if ((reinterpret_cast<uintptr_t>(cotangent) | reinterpret_cast<uintptr_t>(grad_x0) |
+       reinterpret_cast<uintptr_t>(grad_power)) & 3)
+    return fail(STENCIL_ERR_INVALID_ARG, "buffers must be 4-byte aligned");
+  if (grad_x0 == cotangent || (grad_power && (grad_power == cotangent || grad_power == grad_x0)))
+    return fail(STENCIL_ERR_INVALID_ARG, "grad_x0 and grad_power must not alias cotangent or each other");
+  if (grad_power && !src) return fail(STENCIL_ERR_INVALID_ARG, "grad_power needs src = {cp, c_amb, t_amb}");
+  const int R = p->rad;
+  const int nw = 1 + (p->ndim == 3 ? 6 : 4) * R;
+  for (int i = 0; i < nw; ++i)
+    if (!std::isfinite(weights[i])) return fail(STENCIL_ERR_INVALID_ARG, "weights must be finite");
+  if (grad_power && !std::isfinite(src[0])) return fail(STENCIL_ERR_INVALID_ARG, "src must be finite");
+  StarAdjArgs a{};
+  a.nx = p->nx; a.ny = p->ny; a.nz = p->ndim == 3 ? p->nz : 1; a.ndim = p->ndim; a.rad = R;
+  a.nbx = (p->nx + 255) / 256;
+  a.c0 = weights[0];
+  a.cp = grad_power ? src[0] : 0.0f;
+  for (int d = 1; d <= R; ++d) {
+    a.wm[0][d - 1] = weights[2 * d - 1];  // x-d: w_d
+    a.wp[0][d - 1] = weights[2 * d];      // x+d: e_d
+    a.wp[1][d - 1] = weights[2 * R + d];  // y+d: s_d
+    a.wm[1][d - 1] = weights[3 * R + d];  // y-d: n_d
+    if (p->ndim == 3) {
+      a.wm[2][d - 1] = weights[4 * R + d];  // z-d: b_d
+      a.wp[2][d - 1] = weights[5 * R + d];  // z+d: a_d
+    }
+  }
+  st = set_device(p);
+  if (st != STENCIL_OK) return st;
+  const size_t bytes = p->cells * sizeof(float);
+  if (grad_power) {
+    if (hipError_t e = launch_fill(grad_power, p->cells, 0.0f, p->stream); e != hipSuccess) return hip_fail(e, "fill");
+  }
+  if (T == 0) {
+    hipError_t e = hipMemcpyAsync(grad_x0, cotangent, bytes, hipMemcpyDeviceToDevice, p->stream);
+    return e == hipSuccess ? STENCIL_OK : hip_fail(e, "hipMemcpyAsync");
+  }
+  // lambda_T -> lambda_0, one launch per step, ping-pong between grad_x0 and plan scratch so
+  // that the last step writes grad_x0
+  const float* in = cotangent;
+  for (int step = 1; step <= T; ++step) {
+    float* out = ((T - step) % 2 == 0) ? grad_x0 : p->scratch;
+    a.lam = in;
+    a.out = out;
+    a.gp = grad_power;
+    if (hipError_t e = launch_star_adjoint(a, p->stream); e != hipSuccess) return hip_fail(e, "kernel launch");
+    in = out;
+  }
+  return STENCIL_OK;
+}
+
 }  // extern "C"

@@ -206,3 +206,9 @@ def test_star_hotspot_rejects_bad_arguments_before_device_work():
     src = (ctypes.c_float * 3)(0.125, 0.25, 64.0)
     assert L.stencil_run_star_hotspot(None, None, None, w, src, 1) == -1  # no plan
     assert L.stencil_run_star_hotspot(None, None, None, None, None, 1) == -1
+
+
+def test_star_adjoint_rejects_bad_arguments_before_device_work():
+    L = S.lib()
+    w = (ctypes.c_float * 9)(*([0.2] * 9))
+    assert L.stencil_adjoint_star(None, None, w, None, 1, None, None) == -1  # no plan
