@@ -127,8 +127,163 @@ __global__ __launch_bounds__(256) void star_adjoint_kernel(StarAdjArgs a) {
   }
 }
 
+// The same step with four consecutive x cells per lane (one 16-byte access per row) and one
+// wave per workgroup, for rows whose length is a multiple of 4 and 16-byte aligned buffers.
+// The x neighbours up to distance 4 are in the lane or its neighbour lanes (DPP); the first
+// and last lane of a wave load theirs.  A neighbour beyond the row is masked to zero, and the
+// boundary sums of the row's first and last cell are sums over those same values.
+template <int NDIM, int R>
+__global__ __launch_bounds__(64) void star_adjoint_v4_kernel(StarAdjArgs a) {
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int chunk = b % a.nbx;
+  const int rest = b / a.nbx;
+  const int lane = threadIdx.x;
+  const int x0 = chunk * 256 + lane * 4;
+  if (x0 >= a.nx) return;
+  const size_t plane = (size_t)a.nx * a.ny;
+  int y = 0, s0, ns;
+  if constexpr (NDIM == 3) {
+    y = rest % a.ny;
+    s0 = (rest / a.ny) * kAdjMS;
+    ns = a.nz;
+  } else {
+    s0 = rest * kAdjMS;
+    ns = a.ny;
+  }
+  const int s1 = min(s0 + kAdjMS, ns);
+  const size_t st = NDIM == 3 ? plane : (size_t)a.nx;
+  const size_t roff = NDIM == 3 ? (size_t)y * a.nx : 0;  // the row's offset within a marched slice
+  const float* base = a.lam + roff + x0;
+  const int ma = NDIM - 1;
+  auto ld4 = [](const float* p, float (&o)[4]) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+  };
+  float win[2 * R + 1][4];
+#pragma unroll
+  for (int k = 0; k < 2 * R + 1; ++k) {
+    const int i = s0 - R + k;
+    if (i >= 0 && i < ns) {
+      ld4(base + (size_t)i * st, win[k]);
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) win[k][v] = 0.0f;
+    }
+  }
+  const bool left = (x0 == 0), right = (x0 + 3 == a.nx - 1);
+  for (int s = s0; s < s1; ++s) {
+    float nxt[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (s + R + 1 < ns) ld4(base + (size_t)(s + R + 1) * st, nxt);  // one ahead
+    const float* rowp = a.lam + (size_t)s * st + roff;               // x = 0 of the cell's row
+    // the cells x0-4 .. x0-1 (lo) and x0+4 .. x0+7 (up): neighbour lanes through DPP, the
+    // wave's end lanes from memory; beyond the row they are masked below
+    float lo[4], up[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      lo[k] = from_lower(win[R][k]);
+      up[k] = from_upper(win[R][k]);
+    }
+    if (lane == 0 && x0 >= 4) ld4(rowp + x0 - 4, lo);
+    if (lane == 63 && x0 + 4 < a.nx) ld4(rowp + x0 + 4, up);
+    // value of the cell at offset o from x0 (o in -4..7), zero beyond the row
+    auto X = [&](int o) -> float {
+      const float v = o < 0 ? lo[(o + 4) & 3] : (o < 4 ? win[R][o & 3] : up[(o - 4) & 3]);
+      return (x0 + o >= 0 && x0 + o <= a.nx - 1) ? v : 0.0f;
+    };
+    float acc[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = a.c0 * win[R][v];
+#pragma unroll
+    for (int d = 1; d <= R; ++d) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float vm = X(v + d), vp = X(v - d);
+        if (v == 0 && left) {  // cells 0..d all clamp their x-d neighbour onto cell 0
+          vm = 0.0f;
+#pragma unroll
+          for (int i = 0; i <= d; ++i) vm += X(i);
+        }
+        if (v == 3 && right) {  // cells nx-1-d..nx-1 all clamp their x+d neighbour onto nx-1
+          vp = 0.0f;
+#pragma unroll
+          for (int i = 3 - d; i <= 3; ++i) vp += X(i);
+        }
+        acc[v] = __builtin_fmaf(a.wm[0][d - 1], vm, acc[v]);
+        acc[v] = __builtin_fmaf(a.wp[0][d - 1], vp, acc[v]);
+      }
+    }
+    if constexpr (NDIM == 3) {
+      // y: the rows y +- d of plane s, zero beyond the grid; the first and last row gather the
+      // clamped terms of every row within the distance
+      const float* pl = a.lam + (size_t)s * plane + x0;
+#pragma unroll
+      for (int d = 1; d <= R; ++d) {
+        float vm[4] = {0.0f, 0.0f, 0.0f, 0.0f}, vp[4] = {0.0f, 0.0f, 0.0f, 0.0f}, t[4];
+        if (y == 0) {
+          for (int i = 0; i <= min(d, a.ny - 1); ++i) {
+            ld4(pl + (size_t)i * a.nx, t);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) vm[v] += t[v];
+          }
+        } else if (y + d <= a.ny - 1) {
+          ld4(pl + (size_t)(y + d) * a.nx, vm);
+        }
+        if (y == a.ny - 1) {
+          for (int i = max(a.ny - 1 - d, 0); i <= a.ny - 1; ++i) {
+            ld4(pl + (size_t)i * a.nx, t);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) vp[v] += t[v];
+          }
+        } else if (y - d >= 0) {
+          ld4(pl + (size_t)(y - d) * a.nx, vp);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          acc[v] = __builtin_fmaf(a.wm[1][d - 1], vm[v], acc[v]);
+          acc[v] = __builtin_fmaf(a.wp[1][d - 1], vp[v], acc[v]);
+        }
+      }
+    }
+    // the marched axis from the window
+#pragma unroll
+    for (int d = 1; d <= R; ++d) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float vm = win[R + d][v], vp = win[R - d][v];
+        if (s == 0) {
+          vm = 0.0f;
+#pragma unroll
+          for (int k = R; k <= R + d; ++k) vm += win[k][v];
+        }
+        if (s == ns - 1) {
+          vp = 0.0f;
+#pragma unroll
+          for (int k = R - d; k <= R; ++k) vp += win[k][v];
+        }
+        acc[v] = __builtin_fmaf(a.wm[ma][d - 1], vm, acc[v]);
+        acc[v] = __builtin_fmaf(a.wp[ma][d - 1], vp, acc[v]);
+      }
+    }
+    const size_t cell = (size_t)s * st + roff + x0;
+    *reinterpret_cast<float4*>(a.out + cell) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    if (a.gp) {
+      float g[4];
+      ld4(a.gp + cell, g);
+      *reinterpret_cast<float4*>(a.gp + cell) =
+          make_float4(__builtin_fmaf(a.cp, win[R][0], g[0]), __builtin_fmaf(a.cp, win[R][1], g[1]),
+                      __builtin_fmaf(a.cp, win[R][2], g[2]), __builtin_fmaf(a.cp, win[R][3], g[3]));
+    }
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) win[k][v] = win[k + 1][v];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) win[2 * R][v] = nxt[v];
+  }
+}
+
 // Workgroups of one step: 256-cell pieces of x, by row (3D) and by kAdjMS-cell strip of the
-// slowest axis.
+// slowest axis (the same count for both kernels: 256 threads of one cell, or 64 of four).
 inline long star_adjoint_blocks(const StarAdjArgs& a) {
   if (a.ndim == 3) return (long)a.nbx * a.ny * ((a.nz + kAdjMS - 1) / kAdjMS);
   return (long)a.nbx * ((a.ny + kAdjMS - 1) / kAdjMS);

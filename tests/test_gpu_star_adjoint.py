@@ -2,8 +2,9 @@
 scatter-form adjoint, in 2D and 3D, for every radius, and the dot-product identity between
 the GPU forward and the GPU adjoint.
 
-The kernel gathers where the oracle scatters, so the sums round in another order: the bar is
-an elementwise relative error of 1e-5 against the FP64 oracle.  The cotangents are positive and
+Both kernels are covered: one cell per thread (rows not a multiple of 4) and four cells per
+lane with DPP neighbours.  The kernels gather where the oracle scatters, so the sums round in
+another order: the bar is an elementwise relative error of 1e-5 against the FP64 oracle.  The cotangents are positive and
 the weights non-negative, so every gradient entry stays away from zero and the elementwise
 bound is meaningful.
 """
@@ -54,8 +55,10 @@ def gpu_adjoint(shape, r, lam, T, hot):
     return gx.cpu().numpy(), None if gp is None else gp.cpu().numpy()
 
 
+# one cell per thread where rows are not whole 16-byte groups; four cells per lane where nx is
+# a multiple of 4 (rows of 4, 8, across a 256-column wave boundary, 3D rows of 4, 256 and 516)
 SHAPES = [(131, 257), (1, 33), (29, 1), (5, 7), (3, 1000), (9, 70, 130), (20, 1, 33), (1, 40, 37), (2, 3, 1),
-          (12, 129, 61)]
+          (12, 129, 61), (64, 4), (7, 8), (3, 260), (5, 33, 516), (2, 1, 4), (17, 9, 256)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
