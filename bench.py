@@ -560,7 +560,7 @@ def star3d(S, dev, stream, copy_gbs):
     gx = torch.empty_like(x)
     pl.adjoint(x, wt, 2, gx)
     msa = time_call(lambda: pl.adjoint(x, wt, 20, gx), stream, 2) / 20
-    roof_a = roofline("star_adjoint_kernel<3, %d>" % R, "star_adj", {"rad": R, "shape": list(shape)}, msa, 8.0 * cells,
+    roof_a = roofline("star_adjoint_v4_kernel<3, %d>" % R, "star_adj", {"rad": R, "shape": list(shape)}, msa, 8.0 * cells,
                       (12 * R + 1) * float(cells), copy_gbs)
     study = model_row(S, pl, T, ms, 3, 1, (w["nx"], w["ny"], w["nz"]), (64, 64), rad=R)
     pl.close()
