@@ -519,7 +519,7 @@ def star2d(S, args, dev, stream, copy_gbs):
     lms = time_call(lambda: pl7.run(x7, wt7, 8 * K), stream, 2) / 8
     # a multiply and 4r FMAs per cell update: 8r + 1 FLOP
     b, f = tb2d_pass(w7["nx"], w7["ny"], K, K, seg, 1, 8 * R + 1, R=R)
-    roof = roofline("star2d_kernel<%d, %d, true>" % (R, K), "star2d", {"k": K, "seg_len": seg, "rad": R}, lms, b, f,
+    roof = roofline("star2d_kernel<%d, %d, true, false>" % (R, K), "star2d", {"k": K, "seg_len": seg, "rad": R}, lms, b, f,
                     copy_gbs)
     pp7 = S.StarPlan(w7["rad"], (w7["ny"], w7["nx"]), {"variant": 1})
     msp7 = time_call(lambda: pp7.run(x7, wt7, 20), stream, 1)
@@ -549,7 +549,7 @@ def star3d(S, dev, stream, copy_gbs):
     K, seg = t["k"], t["seg_len"]
     lms = time_call(lambda: pl.run(x, wt, 8 * K), stream, 2) / 8
     b, f = star3d_pass(w["nx"], w["ny"], w["nz"], R, K, seg)
-    roof = roofline("star3d_kernel<%d, %d>" % (R, K), "star3d", {"k": K, "seg_len": seg, "rad": R}, lms, b, f,
+    roof = roofline("star3d_kernel<%d, %d, false>" % (R, K), "star3d", {"k": K, "seg_len": seg, "rad": R}, lms, b, f,
                     copy_gbs)
     pp = S.StarPlan(R, shape, {"variant": 1})
     pp.run(x, wt, 2)
