@@ -4,7 +4,8 @@ The hand-picked shapes of the other parity tests aim at known corner cases (one 
 of one cell, windows flush with an edge).  Here every case draws its grid size log-uniformly,
 its step count, fused-step count and segment length uniformly, and its form and coefficient
 set from the library's whole surface (2D diffusion, Rodinia hotspot and Table 2's physical
-hotspot; 3D diffusion and hotspot with the tile and the balanced launch; radius-r stars), so
+hotspot; 3D diffusion and hotspot with the tile and the balanced launch; radius-r stars in 2D
+and 3D, in both forms, and their adjoint), so
 that tilings nobody thought of get exercised too.  The bar is the same: bit-identical to the
 FP32 oracle (each kernel keeps the oracle's FMA order), and within max-rel 1e-5 of it.
 """
@@ -15,7 +16,7 @@ import pytest
 
 import oracle
 import paper_1802_00438_amd as S
-from workloads import SETS, STAR_SETS, DIFFUSION, HOTSPOT, HOTSPOT_PHYS, rng, uniform
+from workloads import SETS, STAR_SETS, STAR3_SETS, DIFFUSION, HOTSPOT, HOTSPOT_PHYS, rng, uniform
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -142,6 +143,113 @@ def test_random_star(i):
     assert np.array_equal(got, ref), (r, shape, T, tuning, used, maxrel(got, ref))
 
 
+# ------------------------------------------------------------------ radius-r 3D, hotspot form, adjoint
+
+NSTAR3, NSTARADJ = 40, 32
+KMAX_STAR3 = {1: 3, 2: 2, 3: 2, 4: 1}
+STAR_SRC = (0.125, 2.0 ** -8, 80.0)  # cp, c_amb, t_amb of the hotspot form
+
+
+def star_w(r, ndim, scale=1.0):
+    if ndim == 3:
+        w = STAR3_SETS[r]
+    elif r == 1:
+        cf = SETS["A2"]
+        w = np.array([cf[0], cf[1], cf[2], cf[4], cf[3]], dtype=np.float32)
+    else:
+        w = STAR_SETS[r]
+    return (w.astype(np.float64) * scale).astype(np.float32)
+
+
+def draw_star3(i):
+    g = rng(9350 + i)
+    r = 1 + i % 4
+    lo = 1 if i % 4 == 2 else 20
+    shape = (log_uniform(g, 1, 60), log_uniform(g, lo, 200), log_uniform(g, lo, 300))
+    T = int(g.integers(0, 16))
+    k = int(g.integers(1, KMAX_STAR3[r] + 1))
+    seg = int(g.integers(1, 80))
+    return r, shape, T, {"variant": 2, "k": k, "seg_len": seg}, bool(i % 2)
+
+
+@pytest.mark.parametrize("i", range(NSTAR3))
+def test_random_star3d(i):
+    """3D radius-r stars, half of them in the hotspot form, bit for bit against the oracle."""
+    r, shape, T, tuning, hot = draw_star3(i)
+    print("case star3d", i, r, shape, T, tuning, hot, flush=True)
+    w = star_w(r, 3, 0.875 if hot else 1.0)
+    x0 = uniform(shape, 300.0, 350.0, 9750 + i) if hot else uniform(shape, 0.0, 1.0, 9750 + i)
+    p = uniform(shape, 0.0, 1.0, 9790 + i) if hot else None
+    x = dev(x0)
+    plan = S.StarPlan(r, shape, tuning)
+    try:
+        if hot:
+            plan.run(x, w, T, power=dev(p), src=STAR_SRC)
+        else:
+            plan.run(x, w, T)
+        torch.cuda.synchronize()
+        used = plan.tuning
+    finally:
+        plan.close()
+    got = x.cpu().numpy()
+    ref = oracle.star3d(x0, w, T, dtype=np.float32, power=p, src=STAR_SRC if hot else None)
+    assert np.array_equal(got, ref), (r, shape, T, tuning, hot, used, maxrel(got, ref))
+
+
+@pytest.mark.parametrize("i", range(NSTAR // 2))
+def test_random_star2d_hotspot(i):
+    """The draws of the 2D star sweep in the hotspot form."""
+    r, shape, T, tuning = draw_star(i)
+    print("case star2d hot", i, r, shape, T, tuning, flush=True)
+    w = star_w(r, 2, 0.875)
+    x0 = uniform(shape, 300.0, 350.0, 9800 + i)
+    p = uniform(shape, 0.0, 1.0, 9840 + i)
+    x = dev(x0)
+    plan = S.StarPlan(r, shape, tuning)
+    try:
+        plan.run(x, w, T, power=dev(p), src=STAR_SRC)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    got = x.cpu().numpy()
+    ref = oracle.star2d(x0, w, T, dtype=np.float32, power=p, src=STAR_SRC)
+    assert np.array_equal(got, ref), (r, shape, T, tuning, maxrel(got, ref))
+
+
+def draw_star_adj(i):
+    g = rng(9400 + i)
+    r = 1 + i % 4
+    if i % 2:
+        shape = (log_uniform(g, 1, 40), log_uniform(g, 1, 120), log_uniform(g, 1, 300))
+    else:
+        shape = (log_uniform(g, 1, 600), log_uniform(g, 1, 600))
+    if i % 3 == 0:  # rows of whole 16-byte groups: the four-cells-per-lane kernel
+        shape = shape[:-1] + (4 * max(1, shape[-1] // 4),)
+    T = int(g.integers(0, 13))
+    return r, shape, T, bool(i % 4 >= 2)
+
+
+@pytest.mark.parametrize("i", range(NSTARADJ))
+def test_random_star_adjoint(i):
+    """The radius-r adjoint within 1e-5 elementwise of the FP64 oracle (positive cotangents)."""
+    r, shape, T, hot = draw_star_adj(i)
+    print("case star adjoint", i, r, shape, T, hot, flush=True)
+    w = star_w(r, len(shape))
+    lam = uniform(shape, 0.5, 1.5, 9900 + i)
+    plan = S.StarPlan(r, shape, {"variant": 2, "k": 1})
+    try:
+        gx = torch.empty(shape, device="cuda")
+        gp = torch.empty(shape, device="cuda") if hot else None
+        plan.adjoint(dev(lam), w, T, gx, gp, STAR_SRC if hot else None)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    ref, refp = oracle.star_adjoint(lam, w, T, cp=STAR_SRC[0] if hot else None)
+    assert maxrel(gx.cpu().numpy(), ref) <= TOL, (r, shape, T, hot)
+    if hot and T > 0:
+        assert maxrel(gp.cpu().numpy(), refp) <= TOL, (r, shape, T)
+
+
 def test_draws_cover_the_surface():
     """The sweep reaches every form, both 3D launch shapes, every radius and odd sizes."""
     d2 = [draw_2d(i) for i in range(N2D)]
@@ -151,6 +259,11 @@ def test_draws_cover_the_surface():
     assert {t["seg_len"] == 0 for *_, t in d3} == {True, False}
     assert {r for r, *_ in ds} == {1, 2, 3, 4}
     assert any(s[0] % 2 for _, _, s, _, _ in d2) and any(s[2] % 2 for _, _, s, _, _ in d3)
+    d3s = [draw_star3(i) for i in range(NSTAR3)]
+    assert {r for r, *_ in d3s} == {1, 2, 3, 4} and {h for *_, h in d3s} == {True, False}
+    da = [draw_star_adj(i) for i in range(NSTARADJ)]
+    assert {len(s) for _, s, _, _ in da} == {2, 3} and {h for *_, h in da} == {True, False}
+    assert any(s[-1] % 4 == 0 for _, s, _, _ in da) and any(s[-1] % 4 for _, s, _, _ in da)
 
 
 # ------------------------------------------------------------------ adjoint sweep
