@@ -142,12 +142,20 @@ double model_time_2d(const Geom2D& g, int nx, int ny, long T, bool hot, bool adj
   const double rounds = std::ceil(tiles / slots);
   const double quant = tiles / (rounds * slots);
   // Latency hiding: with fewer tiles than about two per wave slot, each SIMD holds too few
-  // waves for its whole life (measured: 1917 tiles run at ~0.75 of the rate of 6106).
-  const double conc = std::min(1.0, std::sqrt(tiles / (2.0 * slots)));
+  // waves for its whole life (measured: 1917 tiles run at ~0.75 of the rate of 6106); floored
+  // at 0.5, below which the pipeline latency below bounds the pass instead.
+  const double conc = std::max(0.5, std::min(1.0, std::sqrt(tiles / (2.0 * slots))));
   const double tm = bytes / (d.hbm_gbs * 1e9 * d.achievable_frac);
-  const double ta = ops / (d.valu_lane_ops * 0.8) / (quant * conc);
-  if (parts) *parts = ModelParts{passes * tm, passes * ta};
-  return passes * (std::max(tm, ta) + 4e-6);
+  // (wave quantisation applies from the second round on: a single partial round is bounded by
+  // the pipeline latency below, not by the idle slots)
+  const double ta = ops / (d.valu_lane_ops * 0.8) / ((rounds > 1 ? quant : 1.0) * conc);
+  // Pipeline latency: one wave streams its tile's rows in order, each row step a chain of K
+  // dependent level updates, so a pass takes at least rows x (0.06 + 0.095 K) us however few
+  // tiles there are (fitted on a 256^2 grid, where a pass of K = 4 over 16 rows takes 7.8 us,
+  // and of K = 8 over 24 rows 16 us, launch included).
+  const double tl = rows * (0.06e-6 + 0.095e-6 * g.K);
+  if (parts) *parts = ModelParts{passes * tm, passes * std::max(ta, tl)};
+  return passes * (std::max(std::max(tm, ta), tl) + 1e-6);
 }
 
 // Radius-R star passes: the same pricing with a halo of R*K rows and columns per side, and
