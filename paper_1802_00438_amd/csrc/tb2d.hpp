@@ -46,7 +46,8 @@
 
 // Rows of the hotspot source ring: at least K+1.  Rounded up to a power of two (the slot
 // index becomes a mask instead of a compare-and-select per level) when that wastes less than
-// a third of the ring, so the LDS footprint does not cost a wave per SIMD.
+// a third of the ring.  For K = 12 that is 16 rows: 10 workgroups per CU instead of the 12 a
+// 13-row ring admits, yet measured 2% faster than the 13-row ring.
 constexpr int tb2d_ring_rows(int K) {
   int p = 1;
   while (p < K + 1) p *= 2;
@@ -508,7 +509,8 @@ inline int tb2d_part_tiles(const Tb2dArgs& a) {
 constexpr int kTb2dV = 4;
 // Rows in flight per wave: four for diffusion; two where the hotspot source ring or the
 // adjoint's running sums already take the registers, except in the edge-free hotspot kernel
-// for 8 < K <= 12, which has the registers for four at the same two waves per SIMD (+7%).
+// for 8 < K <= 12, which has the registers for four (168 VGPRs) within the occupancy its
+// 16 KiB ring allows (+7%).
 #define TB2D_DEPTH(K, HOT, ADJ, INTERIOR) \
   ((!(HOT) && !(ADJ)) ? 4 : ((HOT) && !(ADJ) && (INTERIOR) && (K) > 8 && (K) <= 12) ? 4 : 2)
 #define TB_LAUNCH2D_F(K, HOT, ADJ, ACC, FULL, PHYS, a, s)                                               \
