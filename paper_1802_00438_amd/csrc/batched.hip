@@ -118,6 +118,7 @@ __global__ __launch_bounds__(64) void batched2d_kernel(BLaunch L) {
     a.nx = g.nx; a.ny = g.ny; a.keff = w.keff;
     a.cs = g.cs; a.kr = g.kr; a.ntx = g.ntx; a.seg = g.seg; a.nseg = g.nseg;
     a.aligned = g.aligned;
+    a.stream = 0;
     a.part = 0; a.ix0 = a.ix1 = a.iy0 = a.iy1 = 0;
     a.ylo = 0; a.yhi = g.ny;
     a.cf = g.cf;

@@ -34,6 +34,31 @@ __device__ __forceinline__ float upd2(float c0, float c, float wxm, float xm, fl
   return acc;
 }
 
+// Vector store of 4 consecutive floats at element x of a row that starts at `row`, a
+// wave-uniform, 16-byte aligned address of a row of n floats (n < 2^29); x is the lane's own.
+// With stream set (a wave-uniform launch argument) the store carries the nontemporal hint, so
+// the written lines are not kept in the caches.  That pays on grids far larger than the chip's
+// 256 MB last-level cache, where an output line is never read back before it would be evicted
+// and keeping it only evicts input rows that neighbouring tiles still read; on grids that fit,
+// the next pass reads its input back from that cache, and the hint costs.  The streaming store
+// is a raw buffer store over the row, whose cache policy is an immediate operand: two pointer
+// stores that differ only in the hint are folded into one by the compiler, which drops the
+// hint.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+constexpr int kRawBufWord3 = 0x00020000;  // descriptor word 3: raw buffer, 32-bit data format
+constexpr int kCachePolicyNT = 2;         // cache-policy immediate of a buffer access: nt
+
+__device__ __forceinline__ void store4(float* row, int x, int n, float a, float b, float c, float d, bool stream) {
+  const f32x4_t v = {a, b, c, d};
+  if (stream) {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(row, 0, n * 4, kRawBufWord3);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, x * 4, 0, kCachePolicyNT);
+  } else {
+    *reinterpret_cast<f32x4_t*>(row + x) = v;
+  }
+}
+
 // Cross-lane moves inside one 64-wide wavefront through DPP (no LDS traffic):
 // from_lower(x) returns lane i-1's x on lane i, from_upper(x) lane i+1's x.  The end lanes
 // receive 0; they only ever hold halo columns whose values are never stored.

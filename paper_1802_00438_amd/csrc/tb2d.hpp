@@ -67,6 +67,7 @@ struct Tb2dArgs {
   int seg;             // output rows per tile
   int nseg;            // tiles along y
   int aligned;         // 1: nx % 4 == 0 and 16-byte aligned buffers (vector access in interior tiles)
+  int stream;          // 1: nontemporal vector stores of the output (grids far larger than the cache)
   // Tiles of this launch: part 0 = every tile; part 1 = the interior rectangle
   // [ix0, ix1) x [iy0, iy1) of tiles that touch no grid edge; part 2 = the frame of all others.
   int part, ix0, ix1, iy0, iy1;
@@ -276,7 +277,7 @@ struct Tb2dTile {
       if (x0 >= ox0 && x0 < ox1) {
 #pragma unroll
         for (int h = 0; h < V; h += 4)
-          *reinterpret_cast<float4*>(rowp + x0 + h) = make_float4(o[h], o[h + 1], o[h + 2], o[h + 3]);
+          store4(rowp, x0 + h, a.nx, o[h], o[h + 1], o[h + 2], o[h + 3], a.stream != 0);
       }
     } else {
 #pragma unroll
