@@ -219,8 +219,13 @@ def counter_records():
         if "<!-- counters-json -->" not in text:
             continue
         blob = text.split("<!-- counters-json -->")[1].split("<!-- /counters-json -->")[0]
+        # the list sits in a fenced block (```json ... ```): parse from its first bracket to its last
+        starts = [i for i in (blob.find("["), blob.find("{")) if i >= 0]
+        end = max(blob.rfind("]"), blob.rfind("}"))
+        if not starts or end < 0:
+            continue
         try:
-            data = json.loads(blob.strip().strip("`").strip())
+            data = json.loads(blob[min(starts):end + 1])
         except ValueError:
             continue
         recs.extend(data if isinstance(data, list) else [data])

@@ -109,3 +109,29 @@ def test_star3d_pass_counts_windows_and_pipeline():
     reads = b / (512 ** 3 * 4) - 1.0
     assert (64 / cs) ** 2 < reads < (64 / cs) ** 2 * (103 + 8) / 103 * 1.01
     assert f == sum(((min(z + 103, 512) - z) + 10 + 2) // 3 * 3 for z in range(0, 512, 103)) * ntx * ntx * 4096 * 2 * 25
+
+
+def test_counter_records_parse_the_committed_summaries():
+    """Every counter summary under profiles/ yields its records (the list sits in a fenced
+    json block), each with the fields measured_traffic needs."""
+    recs = bench.counter_records()
+    assert recs, "no counter records found under profiles/"
+    for r in recs:
+        for key in ("kernel", "family", "config", "source_hash", "fetch_kib_per_dispatch",
+                    "write_kib_per_dispatch", "copy_fetch_factor", "copy_write_factor"):
+            assert key in r, (r.get("kernel"), key)
+        assert r["family"] in bench.KERNEL_SOURCES
+
+
+def test_measured_traffic_needs_current_sources_and_the_same_config(monkeypatch):
+    fam = "plain"
+    rec = {"kernel": "plain_kernel<true, false, false, false>", "family": fam, "config": {"shape": [64, 64]},
+           "source_hash": bench.source_hash(bench.KERNEL_SOURCES[fam]), "fetch_kib_per_dispatch": 2.0,
+           "write_kib_per_dispatch": 3.0, "copy_fetch_factor": 0.5, "copy_write_factor": 1.0}
+    monkeypatch.setattr(bench, "counter_records", lambda: [rec])
+    sym = rec["kernel"]
+    assert bench.measured_traffic(sym, fam, {"shape": [64, 64]}) == 2.0 * 1024 / 0.5 + 3.0 * 1024
+    assert bench.measured_traffic(sym, fam, {"shape": [64, 128]}) is None
+    assert bench.measured_traffic("plain_kernel<false, false, false, false>", fam, {"shape": [64, 64]}) is None
+    monkeypatch.setattr(bench, "counter_records", lambda: [dict(rec, source_hash="0" * 16)])
+    assert bench.measured_traffic(sym, fam, {"shape": [64, 64]}) is None
