@@ -6,7 +6,7 @@
 // 12 B hotspot).
 //
 // One wave per workgroup; lane l owns four consecutive x cells (one 16-byte access) of a
-// 256-column chunk and marches kPlainMR2 rows (2D) or kPlainMR3 planes (3D) along the slowest axis,
+// 256-column chunk and marches kPlainMR2 rows (2D) or a.mr3 planes (3D) along the slowest axis,
 // keeping the previous, current and next row (plane) in registers and loading the one after
 // next an iteration ahead, so every value along the marched axis is fetched once per step (plus
 // two per strip).  The x neighbours beyond a lane's four cells come from the neighbouring lanes
@@ -29,12 +29,13 @@ struct PlainArgs {
   int chunks;          // 256-column chunks per row
   int vec;             // 1: nx % 4 == 0 and 16-byte aligned buffers
   int stream;          // 1: nontemporal stores of the output (grids far larger than the cache)
+  int mr3;             // 3D: planes marched per wave (the strip length along z)
   DevCoef cf;
 };
 
-// Rows (2D) / planes (3D) marched per wave.  32 planes in 3D halve the two extra plane reads
-// per strip against 16 (+1% on 512^3); 32 rows in 2D measured 3% slower than 16.
-constexpr int kPlainMR2 = 16, kPlainMR3 = 32;
+// Rows marched per wave in 2D (32 measured 3% slower).  In 3D the strip length is a launch
+// argument (PlainArgs::mr3) that the host sizes to the grid.
+constexpr int kPlainMR2 = 16;
 
 // four consecutive cells starting at x0 of row r (clamped beyond nx on the scalar path)
 __device__ __forceinline__ void plain_ld4(const float* r, int x0, int nx, bool vec, float (&o)[4]) {
@@ -69,10 +70,10 @@ __global__ __launch_bounds__(64) void plain_kernel(PlainArgs a) {
     ns = a.ny;
   } else {
     y = strip % a.ny;
-    s0 = (strip / a.ny) * kPlainMR3;
+    s0 = (strip / a.ny) * a.mr3;
     ns = a.nz;
   }
-  const int s1 = min(s0 + (a.ndim == 2 ? kPlainMR2 : kPlainMR3), ns);
+  const int s1 = min(s0 + (a.ndim == 2 ? kPlainMR2 : a.mr3), ns);
   const size_t stride = a.ndim == 2 ? (size_t)a.nx : plane;  // distance between marched rows
   const float* sbase = a.src + (a.ndim == 2 ? 0 : (size_t)y * a.nx);
   const int ym = y > 0 ? y - 1 : 0, yp = y < a.ny - 1 ? y + 1 : a.ny - 1;
@@ -176,5 +177,5 @@ __global__ __launch_bounds__(64) void plain_kernel(PlainArgs a) {
 // Workgroups of one plain launch: (256-column chunks) x (strips along the marched axis).
 inline int plain_blocks(const PlainArgs& a) {
   if (a.ndim == 2) return a.chunks * ((a.ny + kPlainMR2 - 1) / kPlainMR2);
-  return a.chunks * a.ny * ((a.nz + kPlainMR3 - 1) / kPlainMR3);
+  return a.chunks * a.ny * ((a.nz + a.mr3 - 1) / a.mr3);
 }

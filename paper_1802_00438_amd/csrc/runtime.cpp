@@ -491,6 +491,22 @@ hipError_t run_pass(const stencil_plan_s* p, KMode m, int K, int keff, const flo
   return launch_tb3d(K, m, full, a, p->stream);
 }
 
+// Planes per strip of the one-step 3D kernel (one one-wave workgroup per 256-column chunk, row
+// and strip): the longest of 16, 32, ..., 256 planes that divides nz evenly and still gives at
+// least 16 workgroups per CU, else 32.  Measured (diffusion, TB/s, at the chosen length against
+// 32 planes): 512^3 4.30 (128) / 4.02, 1024 x 512^2 4.44 (256) / 4.12, 384^3 3.23 (64) / 3.11,
+// 256^3 5.26 (16) / 3.98 (that grid stays in the last-level cache), 256 x 1024^2 4.03 (256) /
+// 4.01; unequal strips cost (160 x 600 x 700: 3.00 at 64 planes, 3.47 at 32), and 640^3 runs at
+// 3.80 (128) against 3.91.
+int plain_strip3d(int chunks, int ny, int nz) {
+  const long cols = (long)chunks * ny;
+  const long want = 16L * device_info().cus;
+  int best = 0;
+  for (int mr = 16; mr <= 256; mr *= 2)
+    if (nz % mr == 0 && cols * (nz / mr) >= want) best = mr;
+  return best ? best : 32;
+}
+
 hipError_t run_plain_step(const stencil_plan_s* p, KMode m, const float* src, float* dst, const float* power,
                           float* gp, const DevCoef& cf) {
   PlainArgs a;
@@ -500,6 +516,7 @@ hipError_t run_plain_step(const stencil_plan_s* p, KMode m, const float* src, fl
   a.vec = ((p->nx & 3) == 0) && aligned16(src) && aligned16(dst) && (!power || aligned16(power)) &&
           (!gp || aligned16(gp)) ? 1 : 0;
   a.stream = stream_stores(p);
+  a.mr3 = p->ndim == 3 ? plain_strip3d(a.chunks, p->ny, p->nz) : 1;
   a.cf = cf;
   return launch_plain(m, a, p->stream);
 }
