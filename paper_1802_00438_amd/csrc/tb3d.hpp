@@ -25,8 +25,10 @@
 //   * Clamp-to-edge is applied per level by using the cell's own value for an out-of-grid
 //     neighbour; tiles that touch no x/y edge run code with no boundary handling, and the z
 //     edges cost only on the few planes that meet them.
-//   * Hotspot: the source q = fma(cp, p, kamb) is re-formed per level from the power plane
-//     (an L2 hit after the first level), keeping registers for the k-level window.
+//   * Hotspot: in a pass of all K steps the source q = fma(cp, p, kamb) of a plane is formed
+//     once, when it becomes the newest output plane (level 1), from a power plane loaded an
+//     iteration ahead; levels 2..K read it back from an LDS ring of K-1 planes that holds each
+//     lane's own cells.  A shorter pass re-forms it per level from the power plane.
 //   * Adjoint: transposed operator (mirrored weights, zero outside the grid, self term with
 //     the weight of the leaving direction); sum_s lambda_s travels with the pipeline and is
 //     added to grad_p once per pass.
@@ -65,6 +67,7 @@ struct Tb3dTile {
   int xw, yw, ox0, ox1, oy0, oy1, z0, z1;
   float S[2][K][R][V];  // per level: centre plane and oldest/partial/newest plane, alternating
   float Lb[PD][R][V];   // next PD input planes (loaded PD iterations ahead)
+  float Qb[R][V];       // hotspot: the power plane of the next iteration's newest output plane
   float Pp[K][R][V];
   float cxm[V], cxp[V];
   bool isL[V], isR[V];
@@ -76,9 +79,21 @@ struct Tb3dTile {
   // exactly the clamp, at no cost per cell.
   int hn_off, hs_off;
   float* hal;                 // LDS: [2][K][NW][2][WX]
+  // Hotspot forward: q = fma(cp, p, kamb) of the K-1 planes before the newest output plane,
+  // one slot per plane (plane j in slot j mod (K-1)), each lane's own cells only:
+  // [K-1][NW][R][64][V].
+  static constexpr bool QONCE = HOT && !ADJ && FULL;  // passes of all K steps
+  static constexpr int QR = (QONCE && K > 1) ? K - 1 : 0;
+  float* qring;
 
-  __device__ __forceinline__ Tb3dTile(const Tb3dArgs& args, int ln, int wv, float* lds)
-      : a(args), lane(ln), wave(wv), hal(lds) {}
+  __device__ __forceinline__ Tb3dTile(const Tb3dArgs& args, int ln, int wv, float* lds, float* qlds = nullptr)
+      : a(args), lane(ln), wave(wv), hal(lds), qring(qlds) {}
+
+  __device__ __forceinline__ float* qslot(int plane, int r) const {
+    int sl = plane % QR;
+    if (sl < 0) sl += QR;
+    return qring + (((sl * NW + wave) * R + r) * 64 + lane) * V;
+  }
 
   __device__ __forceinline__ float* hrow(int buf, int lev, int w, int which) const {
     return hal + ((((buf * K + lev) * NW + w) * 2 + which) * WX);
@@ -123,10 +138,18 @@ struct Tb3dTile {
   // the flush rows swap the weight of the leaving direction.
   template <bool XE, bool YE, bool ZE, bool EA>
   __device__ __forceinline__ void partial(const float (&Pl)[R][V], const float (&Cl)[R][V], float (&o)[R][V],
-                                          int lev_in, int rbuf, int j) const {
+                                          int lev_in, int rbuf, int j, const float (&qin)[R][V]) const {
     float q[R][V];
     (void)q;
-    if constexpr (HOT && !ADJ) {
+    (void)qin;
+    if constexpr (QONCE) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int v = 0; v < V; ++v) q[r][v] = qin[r][v];
+    } else if constexpr (HOT && !ADJ) {
+      // passes of fewer than K steps re-form the source per level (the ring's registers
+      // would spill there)
       const int zc = clampi(j, 0, a.nz - 1);
       const float* pl = a.power + (size_t)zc * a.ny * a.nx;
       const int x0 = xw + lane * V;
@@ -145,7 +168,6 @@ struct Tb3dTile {
         }
       }
     }
-
     float hn[V], hs[V];
     {
       const float* lev = hrow(rbuf, lev_in, 0, 0) + lane * V;
@@ -318,8 +340,35 @@ struct Tb3dTile {
     for (int s = K; s >= 1; --s) {
       const int j = r - s;
       float o[R][V];
+      float q[R][V];
+      (void)q;
+      if constexpr (QONCE) {
+        if (s == 1) {
+          // the newest output plane's source, from the power plane loaded an iteration ahead;
+          // the older planes' sources come from the ring, where this one goes for them
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+            for (int v = 0; v < V; ++v) q[rr][v] = __builtin_fmaf(a.cf.cp, Qb[rr][v], a.cf.kamb);
+          if constexpr (QR > 0) {
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+              float* d = qslot(j, rr);
+#pragma unroll
+              for (int v = 0; v < V; ++v) d[v] = q[rr][v];
+            }
+          }
+        } else {
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr) {
+            const float* d = qslot(j, rr);
+#pragma unroll
+            for (int v = 0; v < V; ++v) q[rr][v] = d[v];
+          }
+        }
+      }
       if (FULL || s <= keff) {
-        partial<XE, YE, ZE, EA>(X[s - 1], C[s - 1], o, s - 1, ROT ^ 1, j);
+        partial<XE, YE, ZE, EA>(X[s - 1], C[s - 1], o, s - 1, ROT ^ 1, j, q);
       } else {
 #pragma unroll
         for (int rr = 0; rr < R; ++rr)
@@ -340,6 +389,7 @@ struct Tb3dTile {
 #pragma unroll
       for (int v = 0; v < V; ++v) X[0][rr][v] = Lb[LB][rr][v];
     load_plane<XE>(r + PD, Lb[LB], a.src);
+    if constexpr (QONCE) load_plane<XE>(r, Qb, a.power);  // for plane r, the next newest
     publish(ROT, 0, X[0]);
     float Pn[K][R][V];
     (void)Pn;
@@ -424,6 +474,7 @@ struct Tb3dTile {
     nit = (nit + 1) & ~1;
 #pragma unroll
     for (int d = 0; d < PD; ++d) load_plane<XE>(r0 + d, Lb[d], a.src);
+    if constexpr (QONCE) load_plane<XE>(r0 - 1, Qb, a.power);
     // Pairs of iterations that compute a plane at a z edge form a prefix (z = 0) and a suffix
     // (z = nz-1) of the loop; they run a body with z-edge handling, the rest a body without
     // it.  Separate loops (rather than a branch inside one loop) keep the register allocation
@@ -535,9 +586,10 @@ struct Tb3dTile {
 // per workgroup instead of once per short tile.
 template <int K, int V, int R, int NW, bool HOT, bool ADJ, bool ACC, bool FULL, int PD>
 __global__ __launch_bounds__(64 * NW) void tb3d_kernel(Tb3dArgs a) {
+  using Tile = Tb3dTile<K, V, R, NW, HOT, ADJ, ACC, FULL, PD>;
   __shared__ __align__(16) float hal[2 * K * NW * 2 * 64 * V];
-  Tb3dTile<K, V, R, NW, HOT, ADJ, ACC, FULL, PD> t(a, threadIdx.x & 63,
-                                                    __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), hal);
+  __shared__ __align__(16) float qring[Tile::QR > 0 ? Tile::QR * NW * R * 64 * V : 1];
+  Tile t(a, threadIdx.x & 63, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), hal, qring);
   if (a.nwork == 0) {
     t.process(xcd_remap(blockIdx.x, a.ntx * a.nty * a.nsegz));
     return;
