@@ -798,6 +798,32 @@ stencil_status_t autotune(stencil_plan_s* p, TuneResult* out) {
           break;
         }
       }
+      // 2D: the candidate segments are 32 rows apart, so the winner's neighbours 16 rows either
+      // side are timed too, and one of them replaces it when it is faster by more than the
+      // trial noise (hotspot 16384^2, k = 12: 176 rows ran 1.4% faster than 192).
+      if (p->ndim == 2) {
+        const Cand win{best.k, best.seg_len, 0.0, 0};
+        std::vector<Cand> nb;
+        for (int d : {-16, 16}) {
+          const int seg = best.seg_len + d;
+          if (seg >= 2 * best.k && seg < p->ny) nb.push_back({best.k, seg, 0.0, 0});
+        }
+        double wr = 0.0;
+        std::vector<double> nr(nb.size(), 0.0);
+        for (int round = 0; round < 3 && !nb.empty(); ++round) {
+          wr = std::max(wr, time_cand(win));
+          for (size_t i = 0; i < nb.size(); ++i) nr[i] = std::max(nr[i], time_cand(nb[i]));
+        }
+        for (size_t i = 0; i < nb.size(); ++i) {
+          if (log_enabled())
+            std::fprintf(stderr, "[stencil] tune K=%d seg=%d (neighbour of %d) measured=%.1f GCell/s against %.1f\n",
+                         nb[i].K, nb[i].seg, win.seg, nr[i] * 1e-9, wr * 1e-9);
+          if (nr[i] > 1.005 * wr) {
+            wr = nr[i];
+            best.seg_len = nb[i].seg;
+          }
+        }
+      }
       // The transposed pass (it also reads and writes grad_p) is timed on candidates of its
       // own: every instantiated K with a few segment lengths and, in 3D, the balanced launch;
       // one round after a warm-up.  (The physical Hotspot 2D form has no transposed pass.)
