@@ -249,10 +249,15 @@ int pick_seg2d(int K, int nx, int ny, int waves_per_cu) {
   const Geom2D g0 = geom2d(K, nx, ny, ny);
   const long slots = (long)d.cus * waves_per_cu;
   // smallest number of y-tiles that fills the device at least once, rounded so the last round
-  // of waves is as full as possible; never segments shorter than 4K rows where avoidable
+  // of waves is as full as possible; never segments shorter than 2K rows, except on grids so
+  // small that even 2-row segments fit one round of waves: those passes are bound by the
+  // pipeline latency of a tile's seg + 2K rows, so shorter segments win there (256^2, k = 4,
+  // 16 steps: 22.3 us at 2-row segments, 23.6 at 4, 30.9 at 8)
+  const bool tiny = (double)g0.ntx * ceil_div(ny, 2) <= (double)slots;
+  const int min_seg = tiny ? 2 : 2 * K;
   int best_seg = ny;
   double best = 1e300;
-  for (int nseg = 1; nseg <= std::max(1, ny / std::max(1, 2 * K)); ++nseg) {
+  for (int nseg = 1; nseg <= std::max(1, ny / std::max(1, min_seg)); ++nseg) {
     const int seg = ceil_div(ny, nseg);
     const int real = ceil_div(ny, seg);
     const double tiles = (double)g0.ntx * real;
