@@ -1681,6 +1681,7 @@ stencil_status_t stencil_adjoint_star(stencil_plan_t p, const float* cotangent, 
   StarAdjArgs a{};
   a.nx = p->nx; a.ny = p->ny; a.nz = p->ndim == 3 ? p->nz : 1; a.ndim = p->ndim; a.rad = R;
   a.nbx = (p->nx + 255) / 256;
+  a.stream = stream_stores(p);
   a.c0 = weights[0];
   a.cp = grad_power ? src[0] : 0.0f;
   for (int d = 1; d <= R; ++d) {

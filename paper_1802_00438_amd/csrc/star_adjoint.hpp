@@ -32,6 +32,7 @@ struct StarAdjArgs {
   float* gp;         // hotspot form: grad_p, accumulated; else null
   int nx, ny, nz, ndim, rad;
   int nbx;           // workgroups per row of x
+  int stream;        // 1: nontemporal stores of lambda_{t-1} (grids far larger than the cache)
   float c0, cp;
   float wm[3][kStarMaxR], wp[3][kStarMaxR];  // per axis (x, y, z): minus and plus weights by distance
 };
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(64) void star_adjoint_v4_kernel(StarAdjArgs a) {
       }
     }
     const size_t cell = (size_t)s * st + roff + x0;
-    *reinterpret_cast<float4*>(a.out + cell) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    store4(a.out + (size_t)s * st + roff, x0, a.nx, acc[0], acc[1], acc[2], acc[3], a.stream != 0);
     if (a.gp) {
       float g[4];
       ld4(a.gp + cell, g);

@@ -9,7 +9,8 @@ sit just above the threshold, small enough for the oracle to compare every cell:
   launches, an unsplit pass, and the one-step kernel, in diffusion and hotspot form;
 * 3D 324 x 320 x 328 (34.0M cells): the one-step kernel, and beside it the temporal-blocked
   tile and balanced launches (plain stores) at the same size, in both forms;
-* the adjoint sweeps (transposed steps) of both, in hotspot form.
+* the adjoint sweeps (transposed steps) of both, in hotspot form, and the radius-2 transposed
+  step (its output stores carry the hint too).
 
 Forward results must equal the FP32 oracle bit for bit (same operations in the same order on
 every cell); adjoint results are compared with the FP64 oracle within 1e-5 elementwise (the
@@ -105,5 +106,25 @@ def test_streaming_adjoint(shape, cset, tuning, T):
     finally:
         plan.close()
     rx, rp = oracle.adjoint(cot, cf, T, form=HOTSPOT)
+    assert maxrel(gx.cpu().numpy(), rx) <= TOL
+    assert maxrel(gp.cpu().numpy(), rp) <= TOL
+
+
+def test_streaming_star_adjoint():
+    """The radius-r transposed step on a 3D grid above the threshold (nontemporal stores of
+    lambda_{t-1}), in the hotspot form, against the FP64 oracle's scatter-form adjoint."""
+    from workloads import STAR3_SETS
+    r, T = 2, 3
+    src = (0.125, 2.0 ** -8, 80.0)
+    lam = uniform(SHAPE3, 0.5, 1.5, 9350)
+    plan = S.StarPlan(r, SHAPE3, {"variant": 2, "k": 1})
+    try:
+        gx = torch.empty(SHAPE3, device="cuda")
+        gp = torch.empty(SHAPE3, device="cuda")
+        plan.adjoint(dev(lam), STAR3_SETS[r], T, gx, gp, src)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    rx, rp = oracle.star_adjoint(lam, STAR3_SETS[r], T, cp=src[0])
     assert maxrel(gx.cpu().numpy(), rx) <= TOL
     assert maxrel(gp.cpu().numpy(), rp) <= TOL
