@@ -97,13 +97,16 @@ def tb2d_pass(nx, ny, K, keff, seg, nread, flops_per, interior_only=False, R=1):
 
 def tb3d_geometry(K, nx, ny, WX=128, WY=48):
     """Tiles along x and y of a 3D pass (edge-flush tiling where the grid is at least one window
-    wide or high, else uniform tiling)."""
+    wide or high; one window flush with x = 0 where an even grid is narrower than a window;
+    else uniform tiling)."""
     krx = (K + 1) // 2 * 2
     csx = (WX - K - krx) // 2 * 2
     csy = WY - 2 * K
     if nx >= WX and nx % 2 == 0:
         fx = (WX - K) // 2 * 2
         ntx = 1 if nx == WX else (2 if nx <= 2 * fx else 2 + math.ceil((nx - 2 * fx) / csx))
+    elif nx % 2 == 0:
+        ntx = 1
     else:
         ntx = math.ceil(nx / csx)
     if ny >= WY:

@@ -364,7 +364,7 @@ bool windows_within_neighbours(int n, int W, int nt, int f, int cs, int kr, bool
 Geom3D batch_geom3d(const BGrid& g, int segz) {
   Geom3D gg = geom3d(kBatchK3, false, g.nx, g.ny, g.nz, segz);
   const int WX = 64 * kTb3dV, WY = kTb3dWY;
-  if (gg.ax && !windows_within_neighbours(g.nx, WX, gg.ntx, gg.fx, gg.csx, gg.krx, true)) {
+  if (gg.ax == 1 && !windows_within_neighbours(g.nx, WX, gg.ntx, gg.fx, gg.csx, gg.krx, true)) {
     gg.ax = 0;
     gg.fx = 0;
     gg.ntx = (g.nx + gg.csx - 1) / gg.csx;

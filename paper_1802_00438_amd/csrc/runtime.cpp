@@ -105,8 +105,13 @@ Geom3D geom3d(int K, bool adj, int nx, int ny, int nz, int segz) {
   // overlapped tiles.  x also needs an even width, so every window starts on an 8-byte
   // boundary.
   g.ax = (nx >= WX && (nx % 2) == 0) ? 1 : 0;
+  // an even grid narrower than a window: one window flush with x = 0 (ax = 2)
+  if (nx < WX && (nx % 2) == 0) g.ax = 2;
   g.ay = (ny >= WY) ? 1 : 0;
-  if (g.ax) {
+  if (g.ax == 2) {
+    g.fx = 0;
+    g.ntx = 1;
+  } else if (g.ax) {
     g.fx = floor_to(WX - K, 2);
     g.ntx = nx == WX ? 1 : (nx <= 2 * g.fx ? 2 : 2 + ceil_div(nx - 2 * g.fx, g.csx));
   } else {

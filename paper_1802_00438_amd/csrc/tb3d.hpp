@@ -50,6 +50,8 @@ struct Tb3dArgs {
   // Edge-flush tiling (forward kernels, grids at least one window wide/high): the first and
   // last tile of an axis place their window flush with the grid edge and output fx (fy)
   // cells from it; the tiles between output csx (csy) cells each.  0: uniform tiling.
+  // ax = 2: a grid narrower than a window with nx even: one window per row of tiles, flush
+  // with x = 0, its lanes past the row idle.
   int ax, ay, fx, fy;
   int aligned;         // 1: nx even and 8-byte aligned buffers (vector access in interior tiles)
   // Output planes [zlo, zhi); tiles (and balanced shares) cover only them.  Every plane
@@ -73,6 +75,7 @@ struct Tb3dTile {
   bool isL[V], isR[V];
   bool rowTop[R], rowBot[R];  // wave-uniform: strip row is grid row 0 / ny-1
   bool topA, botA;            // window flush with grid row 0 / ny-1 (edge-flush tiling)
+  bool pastR;                 // narrow window (a.ax == 2): this lane holds x = nx
   // LDS sources of this wave's halo rows, as offsets within one level's block of hal: the
   // last row of the wave above (y-1) and the first row of the wave below (y+1).  The outermost
   // wave of a window flush with row 0 (ny-1) takes its own first (last) row instead, which is
@@ -99,11 +102,13 @@ struct Tb3dTile {
     return hal + ((((buf * K + lev) * NW + w) * 2 + which) * WX);
   }
 
-  template <bool XE>
+  // EA == 2 (a window wider than the grid): lanes past the row load its last two cells
+  // instead, so every access stays inside the row.
+  template <bool XE, int EA = 0>
   __device__ __forceinline__ void load_plane(int z, float (&d)[R][V], const float* base) const {
     const int zc = clampi(z, 0, a.nz - 1);
     const float* pl = base + (size_t)zc * a.ny * a.nx;
-    const int x0 = xw + lane * V;
+    const int x0 = (EA == 2) ? min(xw + lane * V, a.nx - V) : xw + lane * V;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int y = clampi(yw + wave * R + r, 0, a.ny - 1);
@@ -136,7 +141,7 @@ struct Tb3dTile {
   // with row 0 or ny-1 needs nothing here: its outermost wave reads its own edge row as the
   // halo row (hn_off, hs_off).  The transposed step also takes EA for y-flush windows, where
   // the flush rows swap the weight of the leaving direction.
-  template <bool XE, bool YE, bool ZE, bool EA>
+  template <bool XE, bool YE, bool ZE, int EA>
   __device__ __forceinline__ void partial(const float (&Pl)[R][V], const float (&Cl)[R][V], float (&o)[R][V],
                                           int lev_in, int rbuf, int j, const float (&qin)[R][V]) const {
     float q[R][V];
@@ -152,7 +157,7 @@ struct Tb3dTile {
       // would spill there)
       const int zc = clampi(j, 0, a.nz - 1);
       const float* pl = a.power + (size_t)zc * a.ny * a.nx;
-      const int x0 = xw + lane * V;
+      const int x0 = (EA == 2) ? min(xw + lane * V, a.nx - V) : xw + lane * V;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int y = clampi(yw + wave * R + r, 0, a.ny - 1);
@@ -190,6 +195,12 @@ struct Tb3dTile {
       if constexpr (XE) {
         wl = from_lower(Cl[r][V - 1]);
         eu = from_upper(Cl[r][0]);
+      } else if constexpr (EA == 2) {
+        // window wider than the grid: lane 0 keeps its own value as in a flush window; the
+        // lane that holds x = nx passes on its left neighbour's last cell, so cell nx - 1
+        // reads its own value as its x+1 neighbour, which is the clamp
+        wl = from_lower_or(Cl[r][V - 1], Cl[r][0]);
+        eu = from_upper(pastR ? wl : Cl[r][0]);
       } else if constexpr (EA) {
         wl = from_lower_or(Cl[r][V - 1], Cl[r][0]);
         eu = from_upper_or(Cl[r][0], Cl[r][V - 1]);
@@ -330,7 +341,7 @@ struct Tb3dTile {
   // Iteration with input plane r: level s computes plane r - s.  Planes made in this
   // iteration publish their edge rows in LDS buffer ROT; phase 1 reads the centre planes'
   // edge rows published in the previous iteration (buffer ROT ^ 1).
-  template <int ROT, bool XE, bool YE, bool ZE, bool EA>
+  template <int ROT, bool XE, bool YE, bool ZE, int EA>
   __device__ __forceinline__ void step(int r) {
     float (&X)[K][R][V] = S[ROT];      // oldest planes on entry, partial sums, newest on exit
     float (&C)[K][R][V] = S[ROT ^ 1];  // centre planes
@@ -388,8 +399,8 @@ struct Tb3dTile {
     for (int rr = 0; rr < R; ++rr)
 #pragma unroll
       for (int v = 0; v < V; ++v) X[0][rr][v] = Lb[LB][rr][v];
-    load_plane<XE>(r + PD, Lb[LB], a.src);
-    if constexpr (QONCE) load_plane<XE>(r, Qb, a.power);  // for plane r, the next newest
+    load_plane<XE, EA>(r + PD, Lb[LB], a.src);
+    if constexpr (QONCE) load_plane<XE, EA>(r, Qb, a.power);  // for plane r, the next newest
     publish(ROT, 0, X[0]);
     float Pn[K][R][V];
     (void)Pn;
@@ -450,7 +461,7 @@ struct Tb3dTile {
     __syncthreads();
   }
 
-  template <bool XE, bool YE, bool EA>
+  template <bool XE, bool YE, int EA>
   __device__ __forceinline__ void run() {
 #pragma unroll
     for (int b = 0; b < 2; ++b)
@@ -473,8 +484,8 @@ struct Tb3dTile {
     int nit = (z1 - z0) + keff + K;
     nit = (nit + 1) & ~1;
 #pragma unroll
-    for (int d = 0; d < PD; ++d) load_plane<XE>(r0 + d, Lb[d], a.src);
-    if constexpr (QONCE) load_plane<XE>(r0 - 1, Qb, a.power);
+    for (int d = 0; d < PD; ++d) load_plane<XE, EA>(r0 + d, Lb[d], a.src);
+    if constexpr (QONCE) load_plane<XE, EA>(r0 - 1, Qb, a.power);
     // Pairs of iterations that compute a plane at a z edge form a prefix (z = 0) and a suffix
     // (z = nz-1) of the loop; they run a body with z-edge handling, the rest a body without
     // it.  Separate loops (rather than a branch inside one loop) keep the register allocation
@@ -509,7 +520,9 @@ struct Tb3dTile {
 
   // Output planes [zs, ze) of the x-y column (tx, ty).
   __device__ __forceinline__ void process_column(int tx, int ty, int zs, int ze) {
-    if (a.ax) {
+    if (a.ax == 2) {
+      ox0 = 0; ox1 = a.nx; xw = 0;  // one window, flush with x = 0, wider than the grid
+    } else if (a.ax) {
       if (a.ntx == 1) { ox0 = 0; ox1 = a.nx; xw = 0; }
       else if (tx == 0) { ox0 = 0; ox1 = a.fx; xw = 0; }
       else if (tx == a.ntx - 1) { ox0 = max(a.fx, a.nx - a.fx); ox1 = a.nx; xw = a.nx - WX; }
@@ -540,7 +553,8 @@ struct Tb3dTile {
     }
     z0 = zs;
     z1 = ze;
-    const bool xe = !a.aligned || (xw < 0) || (xw + WX > a.nx);
+    const bool xe = !a.aligned || (xw < 0) || (xw + WX > a.nx && a.ax != 2);
+    pastR = (xw + lane * V == a.nx);
     const bool ye = (yw < 0) || (yw + WY > a.ny);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -568,6 +582,8 @@ struct Tb3dTile {
       if (gy) run<true, true, false>(); else run<true, false, false>();
     } else if (gy) {
       run<false, true, false>();
+    } else if (a.ax == 2) {
+      run<false, false, 2>();
     } else if (xa || (ADJ && (topA || botA))) {
       // x-flush windows take the own-value cross-lane moves; a window flush only in y runs the
       // edge-free body (its halo rows come from the LDS sources above), except in the
